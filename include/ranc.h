@@ -1,0 +1,188 @@
+/*
+ * ranc.h -- C ABI of the MI355X RANC tick engine.
+ *
+ * A RANC network (GPU-RANC Sec. II) is a 2-D mesh of cores. Each core has A
+ * axons, N neurons, a binary crossbar of synaptic connections, an axon type
+ * per axon and a set of G signed weights per neuron (the axon's type selects
+ * the weight), plus per-neuron leak, threshold, reset potential and a
+ * destination for its spikes. Time advances in ticks. One tick (Algorithm 1)
+ * reads each core's scheduled axon spikes for the tick, integrates them
+ * through the crossbar and weights, applies leak, threshold and reset, and
+ * routes every spike to a destination (core, axon) at a future tick through
+ * that core's scheduler (Sec. III-D, III-E) or to the output bus (Sec. IV).
+ *
+ * The library simulates S independent instances ("samples") of one network
+ * side by side on one GPU. All device memory it uses lives in a
+ * caller-provided workspace; the library never allocates device memory.
+ *
+ * Conventions for every call:
+ *   - the return value is a ranc_status; on failure ranc_last_error() gives a
+ *     thread-local message that names the offending field;
+ *   - validation failures change nothing and allocate nothing;
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream);
+ *     calls that launch work return before it finishes; errors raised by the
+ *     device surface as RANC_EDEVICE at the next call that synchronizes.
+ */
+#ifndef RANC_H
+#define RANC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RANC_ABI_VERSION 1u
+
+typedef enum ranc_status {
+    RANC_OK = 0,
+    RANC_EINVAL = -1,       /* malformed argument (null pointer, bad size, bad enum) */
+    RANC_ERANGE = -2,       /* a value outside its allowed range (weight, delay, destination...) */
+    RANC_ENOMEM = -3,       /* workspace too small, or a host allocation failed */
+    RANC_EDEVICE = -4,      /* a HIP call or a kernel failed */
+    RANC_ESTATE = -5,       /* call not valid in the handle's state (e.g. ticks no longer retained) */
+    RANC_ETRUNC = -6,       /* output buffer too small; the required size is reported */
+    RANC_EUNSUPPORTED = -7  /* shape or option this build does not implement */
+} ranc_status;
+
+/* Destination kinds of a neuron's spikes. */
+enum { RANC_DEST_NONE = 0, RANC_DEST_CORE = 1, RANC_DEST_OUT = 2 };
+
+/* Integration paths (fixed at load time; they differ in device data layout). */
+enum {
+    RANC_PATH_AUTO = 0,   /* pick per shape */
+    RANC_PATH_PLAIN = 1,  /* per (core, sample) workgroups, crossbar words and popcounts */
+    RANC_PATH_MFMA = 2    /* per-core workgroups over sample tiles, exact int8 MFMA */
+};
+
+/* Flags of ranc_run_ticks. */
+#define RANC_INPUTS_ON_DEVICE 1u
+
+/*
+ * Network description (host memory; the library copies it during
+ * ranc_load_network, so the caller may free it afterwards).
+ * Core c sits at mesh position (x, y) = (c % grid_w, c / grid_w).
+ * Supported shapes: num_axons, num_neurons in {64, 128, 256, 512};
+ * num_types in {1, 2, 4, 8}; 2 <= weight_bits <= 9; 2 <= potential_bits <= 32;
+ * 1 <= max_delay <= 15; num_cores * num_neurons < 2^27.
+ */
+typedef struct ranc_net_desc {
+    uint32_t abi_version;      /* must be RANC_ABI_VERSION */
+    int32_t num_cores;         /* C = grid_w * grid_h */
+    int32_t num_axons;         /* A */
+    int32_t num_neurons;       /* N */
+    int32_t num_types;         /* G: weights per neuron, one per axon type */
+    int32_t weight_bits;       /* weights lie in [-2^(b-1), 2^(b-1) - 1] */
+    int32_t potential_bits;    /* P: potentials saturate to [-2^(P-1), 2^(P-1) - 1] once per tick */
+    int32_t max_delay;         /* largest tick offset a spike packet may carry */
+    int32_t grid_w, grid_h;    /* mesh size */
+    const uint32_t *crossbar;  /* [C][A][N/32]: bit n%32 of word n/32 set = axon a connects to neuron n */
+    const uint8_t *axon_type;  /* [C][A]: type in [0, G) */
+    const int16_t *weight;     /* [C][N][G] */
+    const int32_t *leak;       /* [C][N]: added every tick */
+    const int32_t *threshold;  /* [C][N]: a neuron fires when its potential reaches it (>=) */
+    const int32_t *reset;      /* [C][N]: potential after a spike; within the P-bit range */
+    const int32_t *v_init;     /* [C][N]: initial potential; within the P-bit range */
+    const uint8_t *dest_kind;  /* [C][N]: RANC_DEST_* */
+    const int16_t *dest_dx;    /* [C][N]: destination core at mesh offset (dx, dy) (CORE only) */
+    const int16_t *dest_dy;
+    const uint16_t *dest_axon; /* [C][N]: destination axon, < A (CORE only) */
+    const uint8_t *dest_delay; /* [C][N]: tick offset in [1, max_delay] (CORE only) */
+    int32_t num_input_cores;   /* C_in >= 0 */
+    const int32_t *input_cores;/* [C_in]: distinct cores that take external input */
+} ranc_net_desc;
+
+/* An output-bus spike. */
+typedef struct ranc_spike {
+    int64_t tick;
+    int32_t core;
+    int32_t neuron;
+} ranc_spike;
+
+/* Per-sample totals since load or the last reset. */
+typedef struct ranc_counters {
+    uint64_t emitted;    /* spikes fired */
+    uint64_t routed;     /* spikes sent to a (core, axon) */
+    uint64_t delivered;  /* scheduler bits set by routed spikes and read at their tick
+                            (several spikes to one (core, axon, tick) count once) */
+    uint64_t out;        /* spikes sent to the output bus */
+    uint64_t events;     /* synaptic events: sum over ticks and cores of
+                            (spiking axon, connected neuron) pairs */
+} ranc_counters;
+
+typedef struct ranc_net ranc_net;  /* opaque handle */
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char *ranc_last_error(void);
+
+/*
+ * Bytes of device workspace ranc_load_network needs for this network,
+ * num_samples instances, at most max_ticks_per_call ticks per
+ * ranc_run_ticks call (the output-spike raster and the input staging area
+ * hold that many ticks) and the given path. Host-only computation; validates
+ * the description like ranc_load_network.
+ */
+ranc_status ranc_workspace_bytes(const ranc_net_desc *desc, int32_t num_samples,
+                                 int32_t max_ticks_per_call, int32_t path, size_t *bytes);
+
+/*
+ * Validate the description, lay it out in the workspace (a device buffer of
+ * at least ranc_workspace_bytes bytes, 256-byte aligned, owned by the caller
+ * and kept alive until ranc_free), upload it on `stream`, and set every
+ * instance to its initial state: potentials = v_init, empty schedulers,
+ * tick 0. Synchronizes `stream` before returning. *out receives a handle
+ * owned by the library until ranc_free.
+ */
+ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples,
+                              int32_t max_ticks_per_call, int32_t path, void *workspace,
+                              size_t workspace_bytes, void *stream, ranc_net **out);
+
+/*
+ * Advance every instance of each of the num_nets networks by num_ticks
+ * ticks (1 <= num_ticks <= max_ticks_per_call). inputs[i] (may be NULL for
+ * no external input) holds network i's external spikes as
+ * [S][num_ticks][C_in][A/32] uint32 bitmaps (bit a%32 of word a/32 = axon a
+ * of input core k spikes at that tick), in device memory when flags has
+ * RANC_INPUTS_ON_DEVICE, else in host memory (copied to the workspace's
+ * staging area first). Consecutive calls continue the same simulation:
+ * spikes whose delivery tick lies beyond the call stay scheduled.
+ * Returns after queueing the work on `stream`.
+ */
+ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets,
+                           const uint32_t *const *inputs, uint32_t flags, int32_t num_ticks,
+                           void *stream);
+
+/*
+ * Output-bus spikes of one sample with tick_begin <= tick < tick_end, sorted
+ * by (tick, core, neuron). Ticks must lie in the retained window: the last
+ * max_ticks_per_call ticks run (else RANC_ESTATE). If capacity is too small,
+ * *count receives the required number and RANC_ETRUNC is returned.
+ * Synchronizes the stream of the last run.
+ */
+ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, int64_t tick_end,
+                             ranc_spike *out, int64_t capacity, int64_t *count);
+
+/* Current potentials of one sample into out[C][N] (host). Synchronizes. */
+ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out);
+
+/* Counters of one sample. Synchronizes. */
+ranc_status ranc_read_counters(ranc_net *net, int32_t sample, ranc_counters *out);
+
+/* Next tick to be simulated (ticks run since load or reset). */
+ranc_status ranc_current_tick(const ranc_net *net, int64_t *tick);
+
+/* Integration path chosen at load (RANC_PATH_PLAIN or RANC_PATH_MFMA). */
+ranc_status ranc_get_path(const ranc_net *net, int32_t *path);
+
+/* Return every instance to its initial state (queued on `stream`). */
+ranc_status ranc_reset_state(ranc_net *net, void *stream);
+
+/* Release the handle (the workspace stays the caller's). NULL is a no-op. */
+void ranc_free(ranc_net *net);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RANC_H */

@@ -1,0 +1,611 @@
+// runtime.cpp -- host side of the C ABI declared in include/ranc.h.
+//
+// Validation of the network description, the workspace layout, host-side
+// packing of the description into the device layouts of ranc_internal.h
+// (crossbar columns, per-type masks, MFMA weight planes, the inverted routing
+// table), the tick loop that queues the per-tick kernels, and readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ranc.h"
+#include "ranc_internal.h"
+
+using namespace ranc;
+
+namespace {
+
+thread_local std::string g_err;
+
+ranc_status fail(ranc_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+ranc_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(RANC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+enum Region {
+    R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
+    R_ININDEX, R_RTPTR, R_RTSRC, R_DEG, R_PLANES,
+    R_PARAMS_END,  // everything before this is uploaded once at load
+    R_V = R_PARAMS_END, R_RING, R_SPK, R_RASTER, R_CNT, R_EXT, R_NREG
+};
+
+struct Plan {
+    int C, A, N, G, W, NW, D, Q, S, RT, Wout, Cin, path, two, spw;
+    long long E;  // routed (CORE) neurons
+    size_t off[R_NREG], size[R_NREG], params_bytes, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+ranc_status validate(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t path)
+{
+    if (!d)
+        return fail(RANC_EINVAL, "desc is NULL");
+    if (d->abi_version != RANC_ABI_VERSION)
+        return fail(RANC_EINVAL, "abi_version %u != %u", d->abi_version, RANC_ABI_VERSION);
+    if (S < 1)
+        return fail(RANC_EINVAL, "num_samples must be >= 1 (got %d)", S);
+    if (S > 65535)
+        return fail(RANC_EUNSUPPORTED, "num_samples must be <= 65535 (got %d)", S);
+    if (RT < 1)
+        return fail(RANC_EINVAL, "max_ticks_per_call must be >= 1 (got %d)", RT);
+    if (path < RANC_PATH_AUTO || path > RANC_PATH_MFMA)
+        return fail(RANC_EINVAL, "unknown path %d", path);
+    if (d->num_cores < 1)
+        return fail(RANC_EINVAL, "num_cores must be >= 1");
+    if (d->grid_w < 1 || d->grid_h < 1 || (long long)d->grid_w * d->grid_h != d->num_cores)
+        return fail(RANC_EINVAL, "grid %dx%d does not hold %d cores", d->grid_w, d->grid_h, d->num_cores);
+    if (!pow2_in(d->num_axons, 64, 512))
+        return fail(RANC_EUNSUPPORTED, "num_axons must be 64, 128, 256 or 512 (got %d)", d->num_axons);
+    if (!pow2_in(d->num_neurons, 64, 512))
+        return fail(RANC_EUNSUPPORTED, "num_neurons must be 64, 128, 256 or 512 (got %d)", d->num_neurons);
+    if (!pow2_in(d->num_types, 1, 8))
+        return fail(RANC_EUNSUPPORTED, "num_types must be 1, 2, 4 or 8 (got %d)", d->num_types);
+    if (d->weight_bits < 2 || d->weight_bits > 9)
+        return fail(RANC_ERANGE, "weight_bits must be in [2, 9] (got %d)", d->weight_bits);
+    if (d->potential_bits < 2 || d->potential_bits > 32)
+        return fail(RANC_ERANGE, "potential_bits must be in [2, 32] (got %d)", d->potential_bits);
+    if (d->max_delay < 1 || d->max_delay > 15)
+        return fail(RANC_ERANGE, "max_delay must be in [1, 15] (got %d)", d->max_delay);
+    if ((long long)d->num_cores * d->num_neurons >= (1LL << 27))
+        return fail(RANC_EUNSUPPORTED, "num_cores * num_neurons must be < 2^27");
+    if (!d->crossbar || !d->axon_type || !d->weight || !d->leak || !d->threshold || !d->reset ||
+        !d->v_init || !d->dest_kind || !d->dest_dx || !d->dest_dy || !d->dest_axon || !d->dest_delay)
+        return fail(RANC_EINVAL, "a parameter array pointer is NULL");
+    if (d->num_input_cores < 0 || d->num_input_cores > d->num_cores)
+        return fail(RANC_EINVAL, "num_input_cores out of range (%d)", d->num_input_cores);
+    if (d->num_input_cores > 0 && !d->input_cores)
+        return fail(RANC_EINVAL, "input_cores is NULL");
+    const int C = d->num_cores, A = d->num_axons, N = d->num_neurons, G = d->num_types;
+    for (size_t i = 0; i < (size_t)C * A; ++i)
+        if (d->axon_type[i] >= G)
+            return fail(RANC_ERANGE, "axon_type[%zu] = %u is not < num_types", i, d->axon_type[i]);
+    const int wlo = -(1 << (d->weight_bits - 1)), whi = (1 << (d->weight_bits - 1)) - 1;
+    for (size_t i = 0; i < (size_t)C * N * G; ++i)
+        if (d->weight[i] < wlo || d->weight[i] > whi)
+            return fail(RANC_ERANGE, "weight[%zu] = %d outside %d-bit range", i, d->weight[i], d->weight_bits);
+    const long long vlo = -(1LL << (d->potential_bits - 1)), vhi = (1LL << (d->potential_bits - 1)) - 1;
+    for (size_t i = 0; i < (size_t)C * N; ++i) {
+        if (d->reset[i] < vlo || d->reset[i] > vhi)
+            return fail(RANC_ERANGE, "reset[%zu] = %d outside the potential range", i, d->reset[i]);
+        if (d->v_init[i] < vlo || d->v_init[i] > vhi)
+            return fail(RANC_ERANGE, "v_init[%zu] = %d outside the potential range", i, d->v_init[i]);
+        const uint8_t k = d->dest_kind[i];
+        if (k > RANC_DEST_OUT)
+            return fail(RANC_EINVAL, "dest_kind[%zu] = %u unknown", i, k);
+        if (k == RANC_DEST_CORE) {
+            const int c = (int)(i / N);
+            const long long x = c % d->grid_w + (long long)d->dest_dx[i];
+            const long long y = c / d->grid_w + (long long)d->dest_dy[i];
+            if (x < 0 || x >= d->grid_w || y < 0 || y >= d->grid_h)
+                return fail(RANC_ERANGE, "neuron %zu: destination (%+d, %+d) leaves the %dx%d mesh", i,
+                            d->dest_dx[i], d->dest_dy[i], d->grid_w, d->grid_h);
+            if (d->dest_axon[i] >= A)
+                return fail(RANC_ERANGE, "neuron %zu: dest_axon %u >= num_axons", i, d->dest_axon[i]);
+            if (d->dest_delay[i] < 1 || d->dest_delay[i] > d->max_delay)
+                return fail(RANC_ERANGE, "neuron %zu: dest_delay %u outside [1, %d]", i, d->dest_delay[i],
+                            d->max_delay);
+        }
+    }
+    std::vector<char> seen(C, 0);
+    for (int i = 0; i < d->num_input_cores; ++i) {
+        const int c = d->input_cores[i];
+        if (c < 0 || c >= C)
+            return fail(RANC_ERANGE, "input_cores[%d] = %d out of range", i, c);
+        if (seen[c])
+            return fail(RANC_EINVAL, "input core %d listed twice", c);
+        seen[c] = 1;
+    }
+    return RANC_OK;
+}
+
+ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t path, Plan &p)
+{
+    ranc_status st = validate(d, S, RT, path);
+    if (st != RANC_OK)
+        return st;
+    p.C = d->num_cores;
+    p.A = d->num_axons;
+    p.N = d->num_neurons;
+    p.G = d->num_types;
+    p.W = p.A / 32;
+    p.NW = p.N / 32;
+    p.D = d->max_delay;
+    p.Q = p.D + 1;
+    p.S = S;
+    p.RT = RT;
+    p.Cin = d->num_input_cores;
+    p.two = d->weight_bits > 8;
+    if (path == RANC_PATH_AUTO)
+        path = (S >= 64 && mfma_shape_supported(p.A, p.N, p.two)) ? RANC_PATH_MFMA : RANC_PATH_PLAIN;
+    if (path == RANC_PATH_MFMA && !mfma_shape_supported(p.A, p.N, p.two))
+        return fail(RANC_EUNSUPPORTED, "MFMA path does not support A=%d N=%d with %d-bit weights", p.A, p.N,
+                    d->weight_bits);
+    p.path = path;
+    // Samples per MFMA workgroup: aim for >= 1024 workgroups, in 64-sample tiles.
+    {
+        const int tiles = (S + 63) / 64;
+        int chunks = (1024 + p.C - 1) / p.C;
+        chunks = std::max(1, std::min(chunks, tiles));
+        const int tiles_per = (tiles + chunks - 1) / chunks;
+        p.spw = 64 * tiles_per;
+        if (const char *e = getenv("RANC_MFMA_SPW")) {
+            const int v = atoi(e);
+            if (v > 0 && v % 64 == 0)
+                p.spw = v;
+        }
+    }
+    long long E = 0, wout = 0;
+    for (size_t i = 0; i < (size_t)p.C * p.N; ++i)
+        E += d->dest_kind[i] == RANC_DEST_CORE;
+    for (int c = 0; c < p.C; ++c)
+        for (int w = 0; w < p.NW; ++w) {
+            bool any = false;
+            for (int b = 0; b < 32; ++b)
+                any |= d->dest_kind[(size_t)c * p.N + 32 * w + b] == RANC_DEST_OUT;
+            wout += any;
+        }
+    p.E = E;
+    p.Wout = (int)wout;
+    const size_t C = p.C, A = p.A, N = p.N, G = p.G, W = p.W, NW = p.NW;
+    const bool mf = p.path == RANC_PATH_MFMA;
+    p.size[R_COLBITS] = mf ? 0 : C * W * N * 4;
+    p.size[R_TYPEMASK] = C * G * W * 4;
+    p.size[R_WTS] = C * G * N * 4;
+    p.size[R_LEAK] = p.size[R_THR] = p.size[R_RST] = p.size[R_VINIT] = C * N * 4;
+    p.size[R_COREMASK] = p.size[R_OUTMASK] = p.size[R_OUTWORD] = C * NW * 4;
+    p.size[R_ININDEX] = C * 4;
+    p.size[R_RTPTR] = (C * W * p.D + 1) * 4;
+    p.size[R_RTSRC] = std::max<size_t>((size_t)E, 1) * 4;
+    p.size[R_DEG] = C * A * 4;
+    p.size[R_PLANES] = mf ? C * A * N * (p.two ? 2 : 1) : 0;
+    p.size[R_V] = C * S * N * 4;
+    p.size[R_RING] = (size_t)p.Q * S * C * W * 4;
+    p.size[R_SPK] = (size_t)S * C * NW * 4;
+    p.size[R_RASTER] = (size_t)RT * S * p.Wout * 4;
+    p.size[R_CNT] = C * S * CNT_N * 8;
+    p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
+    size_t off = 0;
+    for (int r = 0; r < R_NREG; ++r) {
+        if (r == R_PARAMS_END)
+            p.params_bytes = off;
+        p.off[r] = off;
+        off += align256(p.size[r]);
+    }
+    p.total = off;
+    return RANC_OK;
+}
+
+// Host-side packing of the parameter region (bytes [0, params_bytes)).
+void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &buf, std::vector<int> &out_words)
+{
+    buf.assign(p.params_bytes, 0);
+    auto at = [&](Region r) { return buf.data() + p.off[r]; };
+    const int C = p.C, A = p.A, N = p.N, G = p.G, W = p.W, NW = p.NW;
+    auto conn = [&](int c, int a, int j) -> int {
+        return (d->crossbar[((size_t)c * A + a) * NW + j / 32] >> (j % 32)) & 1u;
+    };
+    if (p.size[R_COLBITS]) {
+        uint32_t *col = (uint32_t *)at(R_COLBITS);
+        for (int c = 0; c < C; ++c)
+            for (int a = 0; a < A; ++a)
+                for (int j = 0; j < N; ++j)
+                    if (conn(c, a, j))
+                        col[((size_t)c * W + a / 32) * N + j] |= 1u << (a % 32);
+    }
+    uint32_t *tm = (uint32_t *)at(R_TYPEMASK);
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < A; ++a)
+            tm[((size_t)c * G + d->axon_type[(size_t)c * A + a]) * W + a / 32] |= 1u << (a % 32);
+    int32_t *wts = (int32_t *)at(R_WTS);
+    for (int c = 0; c < C; ++c)
+        for (int g = 0; g < G; ++g)
+            for (int j = 0; j < N; ++j)
+                wts[((size_t)c * G + g) * N + j] = d->weight[((size_t)c * N + j) * G + g];
+    memcpy(at(R_LEAK), d->leak, (size_t)C * N * 4);
+    memcpy(at(R_THR), d->threshold, (size_t)C * N * 4);
+    memcpy(at(R_RST), d->reset, (size_t)C * N * 4);
+    memcpy(at(R_VINIT), d->v_init, (size_t)C * N * 4);
+    uint32_t *cmask = (uint32_t *)at(R_COREMASK), *omask = (uint32_t *)at(R_OUTMASK);
+    int32_t *oword = (int32_t *)at(R_OUTWORD);
+    out_words.clear();
+    for (int c = 0; c < C; ++c)
+        for (int w = 0; w < NW; ++w) {
+            uint32_t cm = 0, om = 0;
+            for (int b = 0; b < 32; ++b) {
+                const uint8_t k = d->dest_kind[(size_t)c * N + 32 * w + b];
+                cm |= (uint32_t)(k == RANC_DEST_CORE) << b;
+                om |= (uint32_t)(k == RANC_DEST_OUT) << b;
+            }
+            cmask[(size_t)c * NW + w] = cm;
+            omask[(size_t)c * NW + w] = om;
+            oword[(size_t)c * NW + w] = om ? (int32_t)(out_words.size() / 2) : -1;
+            if (om) {
+                out_words.push_back(c);
+                out_words.push_back(w);
+            }
+        }
+    int32_t *inidx = (int32_t *)at(R_ININDEX);
+    for (int c = 0; c < C; ++c)
+        inidx[c] = -1;
+    for (int i = 0; i < p.Cin; ++i)
+        inidx[d->input_cores[i]] = i;
+    // Inverted routing table: bucket key = (dest core * W + dest word) * D + delay - 1.
+    uint32_t *ptr = (uint32_t *)at(R_RTPTR), *src = (uint32_t *)at(R_RTSRC);
+    const size_t keys = (size_t)C * W * p.D;
+    std::vector<uint32_t> fill(keys + 1, 0);
+    auto key_of = [&](size_t i, int c) -> size_t {
+        const int dc = (c % d->grid_w + d->dest_dx[i]) + (c / d->grid_w + d->dest_dy[i]) * d->grid_w;
+        return ((size_t)dc * W + d->dest_axon[i] / 32) * p.D + (d->dest_delay[i] - 1);
+    };
+    for (size_t i = 0; i < (size_t)C * N; ++i)
+        if (d->dest_kind[i] == RANC_DEST_CORE)
+            ++fill[key_of(i, (int)(i / N)) + 1];
+    for (size_t k = 0; k < keys; ++k)
+        fill[k + 1] += fill[k];
+    memcpy(ptr, fill.data(), (keys + 1) * 4);
+    for (size_t i = 0; i < (size_t)C * N; ++i)
+        if (d->dest_kind[i] == RANC_DEST_CORE) {
+            const size_t k = key_of(i, (int)(i / N));
+            src[fill[k]++] = ((uint32_t)i << 5) | (d->dest_axon[i] % 32u);
+        }
+    int32_t *deg = (int32_t *)at(R_DEG);
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < A; ++a) {
+            int k = 0;
+            for (int w = 0; w < NW; ++w)
+                k += __builtin_popcount(d->crossbar[((size_t)c * A + a) * NW + w]);
+            deg[(size_t)c * A + a] = k;
+        }
+    if (p.size[R_PLANES]) {
+        // B tiles: [C][N/16][A/64][planes][64 lanes][16 bytes]; lane l, byte b of
+        // k-step k covers axon 64k + 16(l/16) + b and neuron 16nb + l%16.
+        int8_t *pl = (int8_t *)at(R_PLANES);
+        const int NB = N / 16, KS = A / 64, PL = p.two ? 2 : 1;
+        for (int c = 0; c < C; ++c)
+            for (int nb = 0; nb < NB; ++nb)
+                for (int k = 0; k < KS; ++k)
+                    for (int l = 0; l < 64; ++l)
+                        for (int b = 0; b < 16; ++b) {
+                            const int a = 64 * k + 16 * (l / 16) + b, j = 16 * nb + l % 16;
+                            const int w = conn(c, a, j) ? d->weight[((size_t)c * N + j) * G +
+                                                                    d->axon_type[(size_t)c * A + a]]
+                                                        : 0;
+                            const size_t base = ((((size_t)c * NB + nb) * KS + k) * PL) * 1024 + (size_t)l * 16 + b;
+                            if (PL == 2) {
+                                const int hi = w >> 7;      // arithmetic shift: floor(w / 128)
+                                const int lo = w & 127;
+                                pl[base] = (int8_t)(-hi);
+                                pl[base + 1024] = (int8_t)lo;
+                            } else {
+                                pl[base] = (int8_t)w;
+                            }
+                        }
+    }
+}
+
+}  // namespace
+
+struct ranc_net {
+    Plan p;
+    DevNet dn;
+    uint8_t *ws;
+    hipStream_t last_stream;
+    int64_t tick;
+    uint64_t version, raster_version;
+    std::vector<int> out_words;        // (core, word) pairs of raster columns
+    std::vector<uint32_t> raster_host; // mirror of the raster
+};
+
+extern "C" {
+
+const char *ranc_last_error(void) { return g_err.c_str(); }
+
+ranc_status ranc_workspace_bytes(const ranc_net_desc *desc, int32_t num_samples, int32_t max_ticks_per_call,
+                                 int32_t path, size_t *bytes)
+{
+    if (!bytes)
+        return fail(RANC_EINVAL, "bytes is NULL");
+    Plan p;
+    ranc_status st = make_plan(desc, num_samples, max_ticks_per_call, path, p);
+    if (st != RANC_OK)
+        return st;
+    *bytes = p.total;
+    return RANC_OK;
+}
+
+ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, int32_t max_ticks_per_call,
+                              int32_t path, void *workspace, size_t workspace_bytes, void *stream, ranc_net **out)
+{
+    if (!out)
+        return fail(RANC_EINVAL, "out is NULL");
+    *out = nullptr;
+    Plan p;
+    ranc_status st = make_plan(desc, num_samples, max_ticks_per_call, path, p);
+    if (st != RANC_OK)
+        return st;
+    if (!workspace)
+        return fail(RANC_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256)
+        return fail(RANC_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < p.total)
+        return fail(RANC_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, p.total);
+    ranc_net *net = new (std::nothrow) ranc_net();
+    if (!net)
+        return fail(RANC_ENOMEM, "host allocation failed");
+    net->p = p;
+    net->ws = (uint8_t *)workspace;
+    auto reg = [&](Region r) -> uint8_t * { return net->ws + p.off[r]; };
+    DevNet &n = net->dn;
+    n.C = p.C; n.A = p.A; n.N = p.N; n.G = p.G; n.W = p.W; n.NW = p.NW; n.D = p.D; n.Q = p.Q;
+    n.S = p.S; n.RT = p.RT; n.Wout = p.Wout; n.Cin = p.Cin;
+    n.vmin = (int32_t)(-(1LL << (desc->potential_bits - 1)));
+    n.vmax = (int32_t)((1LL << (desc->potential_bits - 1)) - 1);
+    n.colbits = (const uint32_t *)reg(R_COLBITS);
+    n.typemask = (const uint32_t *)reg(R_TYPEMASK);
+    n.wts = (const int32_t *)reg(R_WTS);
+    n.leak = (const int32_t *)reg(R_LEAK);
+    n.thr = (const int32_t *)reg(R_THR);
+    n.rst = (const int32_t *)reg(R_RST);
+    n.vinit = (const int32_t *)reg(R_VINIT);
+    n.coremask = (const uint32_t *)reg(R_COREMASK);
+    n.outmask = (const uint32_t *)reg(R_OUTMASK);
+    n.outword = (const int32_t *)reg(R_OUTWORD);
+    n.in_index = (const int32_t *)reg(R_ININDEX);
+    n.rt_ptr = (const uint32_t *)reg(R_RTPTR);
+    n.rt_src = (const uint32_t *)reg(R_RTSRC);
+    n.deg = (const int32_t *)reg(R_DEG);
+    n.planes = (const uint4 *)reg(R_PLANES);
+    n.V = (int32_t *)reg(R_V);
+    n.ring = (uint32_t *)reg(R_RING);
+    n.spk = (uint32_t *)reg(R_SPK);
+    n.raster = (uint32_t *)reg(R_RASTER);
+    n.cnt = (unsigned long long *)reg(R_CNT);
+    std::vector<uint8_t> host;
+    pack_params(desc, p, host, net->out_words);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(net->ws, host.data(), p.params_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_reset_state(n, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete net;
+        return hip_fail(e, "uploading the network");
+    }
+    net->last_stream = s;
+    net->tick = 0;
+    net->version = 1;
+    net->raster_version = 0;
+    *out = net;
+    return RANC_OK;
+}
+
+ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32_t *const *inputs, uint32_t flags,
+                           int32_t num_ticks, void *stream)
+{
+    if (!nets || num_nets < 1)
+        return fail(RANC_EINVAL, "nets is NULL or num_nets < 1");
+    for (int i = 0; i < num_nets; ++i) {
+        if (!nets[i])
+            return fail(RANC_EINVAL, "nets[%d] is NULL", i);
+        if (num_ticks < 1 || num_ticks > nets[i]->p.RT)
+            return fail(RANC_EINVAL, "num_ticks %d outside [1, max_ticks_per_call=%d]", num_ticks, nets[i]->p.RT);
+    }
+    if (flags & ~RANC_INPUTS_ON_DEVICE)
+        return fail(RANC_EINVAL, "unknown flags 0x%x", flags);
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < num_nets; ++i) {
+        ranc_net *net = nets[i];
+        const Plan &p = net->p;
+        const uint32_t *base = inputs ? inputs[i] : nullptr;
+        const size_t tick_words = (size_t)p.Cin * p.W;
+        if (base && p.Cin > 0 && !(flags & RANC_INPUTS_ON_DEVICE)) {
+            uint32_t *stage = (uint32_t *)(net->ws + p.off[R_EXT]);
+            hipError_t e = hipMemcpyAsync(stage, base, (size_t)p.S * num_ticks * tick_words * 4,
+                                          hipMemcpyHostToDevice, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "staging inputs");
+            base = stage;
+        }
+        if (p.Cin == 0)
+            base = nullptr;
+        for (int k = 0; k < num_ticks; ++k) {
+            TickArgs ta;
+            ta.q_now = (int)(net->tick % p.Q);
+            ta.r_row = (int)(net->tick % p.RT);
+            ta.ext_t = base ? base + (size_t)k * tick_words : nullptr;
+            ta.ext_sstride = (long long)num_ticks * tick_words;
+            hipError_t e = p.path == RANC_PATH_MFMA ? launch_integrate_mfma(net->dn, ta, p.two, p.spw, s)
+                                                     : launch_integrate_plain(net->dn, ta, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "launching integration");
+            e = launch_route(net->dn, ta.q_now, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "launching routing");
+            ++net->tick;
+        }
+        net->last_stream = s;
+        ++net->version;
+    }
+    return RANC_OK;
+}
+
+static ranc_status sync_net(ranc_net *net)
+{
+    hipError_t e = hipStreamSynchronize(net->last_stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "synchronizing");
+    return RANC_OK;
+}
+
+ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, int64_t tick_end, ranc_spike *out,
+                             int64_t capacity, int64_t *count)
+{
+    if (!net || !count)
+        return fail(RANC_EINVAL, "net or count is NULL");
+    const Plan &p = net->p;
+    if (sample < 0 || sample >= p.S)
+        return fail(RANC_EINVAL, "sample %d out of range", sample);
+    const int64_t lo = std::max<int64_t>(0, net->tick - p.RT);
+    if (tick_begin < lo || tick_end > net->tick || tick_begin > tick_end)
+        return fail(RANC_ESTATE, "ticks [%lld, %lld) outside the retained window [%lld, %lld)",
+                    (long long)tick_begin, (long long)tick_end, (long long)lo, (long long)net->tick);
+    ranc_status st = sync_net(net);
+    if (st != RANC_OK)
+        return st;
+    if (net->raster_version != net->version) {
+        net->raster_host.resize((size_t)p.RT * p.S * p.Wout);
+        if (!net->raster_host.empty()) {
+            hipError_t e = hipMemcpy(net->raster_host.data(), net->dn.raster, net->raster_host.size() * 4,
+                                     hipMemcpyDeviceToHost);
+            if (e != hipSuccess)
+                return hip_fail(e, "reading the raster");
+        }
+        net->raster_version = net->version;
+    }
+    int64_t k = 0;
+    for (int64_t t = tick_begin; t < tick_end; ++t) {
+        const uint32_t *row = net->raster_host.data() + ((size_t)(t % p.RT) * p.S + sample) * p.Wout;
+        for (int ow = 0; ow < p.Wout; ++ow) {
+            uint32_t w = row[ow];
+            while (w) {
+                const int b = __builtin_ctz(w);
+                w &= w - 1;
+                if (out && k < capacity) {
+                    out[k].tick = t;
+                    out[k].core = net->out_words[2 * ow];
+                    out[k].neuron = net->out_words[2 * ow + 1] * 32 + b;
+                }
+                ++k;
+            }
+        }
+    }
+    *count = k;
+    if (k > capacity)
+        return fail(RANC_ETRUNC, "%lld spikes do not fit capacity %lld", (long long)k, (long long)capacity);
+    return RANC_OK;
+}
+
+ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out)
+{
+    if (!net || !out)
+        return fail(RANC_EINVAL, "net or out is NULL");
+    const Plan &p = net->p;
+    if (sample < 0 || sample >= p.S)
+        return fail(RANC_EINVAL, "sample %d out of range", sample);
+    ranc_status st = sync_net(net);
+    if (st != RANC_OK)
+        return st;
+    hipError_t e = hipMemcpy2D(out, (size_t)p.N * 4, net->dn.V + (size_t)sample * p.N, (size_t)p.S * p.N * 4,
+                               (size_t)p.N * 4, p.C, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_fail(e, "reading potentials");
+    return RANC_OK;
+}
+
+ranc_status ranc_read_counters(ranc_net *net, int32_t sample, ranc_counters *out)
+{
+    if (!net || !out)
+        return fail(RANC_EINVAL, "net or out is NULL");
+    const Plan &p = net->p;
+    if (sample < 0 || sample >= p.S)
+        return fail(RANC_EINVAL, "sample %d out of range", sample);
+    ranc_status st = sync_net(net);
+    if (st != RANC_OK)
+        return st;
+    std::vector<unsigned long long> buf((size_t)p.C * CNT_N);
+    hipError_t e = hipMemcpy2D(buf.data(), CNT_N * 8, net->dn.cnt + (size_t)sample * CNT_N, (size_t)p.S * CNT_N * 8,
+                               CNT_N * 8, p.C, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_fail(e, "reading counters");
+    unsigned long long sum[CNT_N] = {0, 0, 0, 0, 0};
+    for (int c = 0; c < p.C; ++c)
+        for (int k = 0; k < CNT_N; ++k)
+            sum[k] += buf[(size_t)c * CNT_N + k];
+    out->emitted = sum[CNT_EMITTED];
+    out->routed = sum[CNT_ROUTED];
+    out->delivered = sum[CNT_DELIVERED];
+    out->out = sum[CNT_OUT];
+    out->events = sum[CNT_EVENTS];
+    return RANC_OK;
+}
+
+ranc_status ranc_current_tick(const ranc_net *net, int64_t *tick)
+{
+    if (!net || !tick)
+        return fail(RANC_EINVAL, "net or tick is NULL");
+    *tick = net->tick;
+    return RANC_OK;
+}
+
+ranc_status ranc_get_path(const ranc_net *net, int32_t *path)
+{
+    if (!net || !path)
+        return fail(RANC_EINVAL, "net or path is NULL");
+    *path = net->p.path;
+    return RANC_OK;
+}
+
+ranc_status ranc_reset_state(ranc_net *net, void *stream)
+{
+    if (!net)
+        return fail(RANC_EINVAL, "net is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_reset_state(net->dn, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "resetting state");
+    net->tick = 0;
+    net->last_stream = s;
+    ++net->version;
+    return RANC_OK;
+}
+
+void ranc_free(ranc_net *net)
+{
+    if (!net)
+        return;
+    hipStreamSynchronize(net->last_stream);
+    delete net;
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+"""Thin ctypes binding of the C ABI in ``include/ranc.h``.
+
+The functions below carry the C names and only marshal arguments; every step
+of the simulation runs in the HIP library ``libranc.so``. PyTorch supplies the
+device memory (the workspace is a ``torch.uint8`` CUDA tensor owned by the
+caller) and the stream (``torch.cuda.current_stream()``). If the library is
+not built, importing the binding raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libranc.so")
+
+RANC_ABI_VERSION = 1
+RANC_OK, RANC_EINVAL, RANC_ERANGE, RANC_ENOMEM, RANC_EDEVICE, RANC_ESTATE, RANC_ETRUNC, RANC_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "RANC_OK", -1: "RANC_EINVAL", -2: "RANC_ERANGE", -3: "RANC_ENOMEM", -4: "RANC_EDEVICE",
+                -5: "RANC_ESTATE", -6: "RANC_ETRUNC", -7: "RANC_EUNSUPPORTED"}
+RANC_PATH_AUTO, RANC_PATH_PLAIN, RANC_PATH_MFMA = 0, 1, 2
+PATHS = {"auto": RANC_PATH_AUTO, "plain": RANC_PATH_PLAIN, "mfma": RANC_PATH_MFMA}
+RANC_INPUTS_ON_DEVICE = 1
+
+EXPORTED = ("ranc_last_error", "ranc_workspace_bytes", "ranc_load_network", "ranc_run_ticks",
+            "ranc_read_spikes", "ranc_read_potentials", "ranc_read_counters", "ranc_current_tick",
+            "ranc_get_path", "ranc_reset_state", "ranc_free")
+
+
+class RancError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class ranc_net_desc(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32)] + [
+        (n, C.c_int32) for n in ("num_cores", "num_axons", "num_neurons", "num_types", "weight_bits",
+                                 "potential_bits", "max_delay", "grid_w", "grid_h")] + [
+        ("crossbar", C.c_void_p), ("axon_type", C.c_void_p), ("weight", C.c_void_p), ("leak", C.c_void_p),
+        ("threshold", C.c_void_p), ("reset", C.c_void_p), ("v_init", C.c_void_p), ("dest_kind", C.c_void_p),
+        ("dest_dx", C.c_void_p), ("dest_dy", C.c_void_p), ("dest_axon", C.c_void_p), ("dest_delay", C.c_void_p),
+        ("num_input_cores", C.c_int32), ("input_cores", C.c_void_p)]
+
+
+class ranc_spike(C.Structure):
+    _fields_ = [("tick", C.c_int64), ("core", C.c_int32), ("neuron", C.c_int32)]
+
+
+class ranc_counters(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("emitted", "routed", "delivered", "out", "events")]
+
+
+SPIKE_DTYPE = np.dtype([("tick", "<i8"), ("core", "<i4"), ("neuron", "<i4")])
+
+
+def _load_lib():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python paper_2404_16208_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_size_t
+    sig = {
+        "ranc_last_error": (C.c_char_p, []),
+        "ranc_workspace_bytes": (C.c_int, [C.POINTER(ranc_net_desc), i32, i32, i32, C.POINTER(sz)]),
+        "ranc_load_network": (C.c_int, [C.POINTER(ranc_net_desc), i32, i32, i32, vp, sz, vp, C.POINTER(vp)]),
+        "ranc_run_ticks": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp), u32, i32, vp]),
+        "ranc_read_spikes": (C.c_int, [vp, i32, i64, i64, vp, i64, C.POINTER(i64)]),
+        "ranc_read_potentials": (C.c_int, [vp, i32, vp]),
+        "ranc_read_counters": (C.c_int, [vp, i32, C.POINTER(ranc_counters)]),
+        "ranc_current_tick": (C.c_int, [vp, C.POINTER(i64)]),
+        "ranc_get_path": (C.c_int, [vp, C.POINTER(i32)]),
+        "ranc_reset_state": (C.c_int, [vp, vp]),
+        "ranc_free": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load_lib()
+
+
+def _check(status):
+    if status != RANC_OK:
+        raise RancError(status, ranc_last_error())
+    return status
+
+
+# ------------------------------------------------------------- C names
+
+def ranc_last_error() -> str:
+    return _lib.ranc_last_error().decode()
+
+
+class Desc:
+    """A ranc_net_desc plus the contiguous numpy arrays it points to."""
+
+    def __init__(self, net):
+        a = lambda x, dt: np.ascontiguousarray(x, dtype=dt)
+        self.arrays = dict(crossbar=a(net.crossbar, np.uint32), axon_type=a(net.axon_type, np.uint8),
+                           weight=a(net.weight, np.int16), leak=a(net.leak, np.int32),
+                           threshold=a(net.threshold, np.int32), reset=a(net.reset, np.int32),
+                           v_init=a(net.v_init, np.int32), dest_kind=a(net.dest_kind, np.uint8),
+                           dest_dx=a(net.dest_dx, np.int16), dest_dy=a(net.dest_dy, np.int16),
+                           dest_axon=a(net.dest_axon, np.uint16), dest_delay=a(net.dest_delay, np.uint8),
+                           input_cores=a(net.input_cores, np.int32))
+        p = {k: v.ctypes.data for k, v in self.arrays.items()}
+        self.c = ranc_net_desc(RANC_ABI_VERSION, net.num_cores, net.num_axons, net.num_neurons, net.num_types,
+                               net.weight_bits, net.potential_bits, net.max_delay, net.grid_w, net.grid_h,
+                               p["crossbar"], p["axon_type"], p["weight"], p["leak"], p["threshold"], p["reset"],
+                               p["v_init"], p["dest_kind"], p["dest_dx"], p["dest_dy"], p["dest_axon"],
+                               p["dest_delay"], len(self.arrays["input_cores"]), p["input_cores"])
+
+
+def ranc_workspace_bytes(desc: Desc, num_samples: int, max_ticks_per_call: int, path: int = RANC_PATH_AUTO) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.ranc_workspace_bytes(C.byref(desc.c), num_samples, max_ticks_per_call, path, C.byref(out)))
+    return int(out.value)
+
+
+def ranc_load_network(desc: Desc, num_samples: int, max_ticks_per_call: int, path: int, workspace_ptr: int,
+                      workspace_bytes: int, stream: int) -> int:
+    h = C.c_void_p(0)
+    _check(_lib.ranc_load_network(C.byref(desc.c), num_samples, max_ticks_per_call, path, workspace_ptr,
+                                  workspace_bytes, stream, C.byref(h)))
+    return int(h.value)
+
+
+def ranc_run_ticks(handles, inputs_ptrs, flags: int, num_ticks: int, stream: int) -> None:
+    n = len(handles)
+    harr = (C.c_void_p * n)(*handles)
+    iarr = (C.c_void_p * n)(*[p or None for p in inputs_ptrs]) if inputs_ptrs is not None else None
+    _check(_lib.ranc_run_ticks(harr, n, iarr, flags, num_ticks, stream))
+
+
+def ranc_read_spikes(handle: int, sample: int, tick_begin: int, tick_end: int) -> np.ndarray:
+    count = C.c_int64(0)
+    st = _lib.ranc_read_spikes(handle, sample, tick_begin, tick_end, None, 0, C.byref(count))
+    if st not in (RANC_OK, RANC_ETRUNC):
+        _check(st)
+    out = np.zeros(int(count.value), dtype=SPIKE_DTYPE)
+    if count.value:
+        _check(_lib.ranc_read_spikes(handle, sample, tick_begin, tick_end, out.ctypes.data, len(out),
+                                     C.byref(count)))
+    return out
+
+
+def ranc_read_potentials(handle: int, sample: int, C_: int, N: int) -> np.ndarray:
+    out = np.empty((C_, N), dtype=np.int32)
+    _check(_lib.ranc_read_potentials(handle, sample, out.ctypes.data))
+    return out
+
+
+def ranc_read_counters(handle: int, sample: int) -> dict:
+    c = ranc_counters()
+    _check(_lib.ranc_read_counters(handle, sample, C.byref(c)))
+    return {k: int(getattr(c, k)) for k, _ in ranc_counters._fields_}
+
+
+def ranc_current_tick(handle: int) -> int:
+    t = C.c_int64(0)
+    _check(_lib.ranc_current_tick(handle, C.byref(t)))
+    return int(t.value)
+
+
+def ranc_get_path(handle: int) -> int:
+    p = C.c_int32(0)
+    _check(_lib.ranc_get_path(handle, C.byref(p)))
+    return int(p.value)
+
+
+def ranc_reset_state(handle: int, stream: int) -> None:
+    _check(_lib.ranc_reset_state(handle, stream))
+
+
+def ranc_free(handle: int) -> None:
+    _lib.ranc_free(handle)
+
+
+# ------------------------------------------------------------- convenience
+
+class RancNet:
+    """A loaded network with its torch-owned workspace on the current CUDA device."""
+
+    def __init__(self, net, num_samples: int, max_ticks_per_call: int, path="auto", device="cuda"):
+        import torch
+
+        self.net = net
+        self.S = num_samples
+        self.RT = max_ticks_per_call
+        self.desc = Desc(net)
+        p = PATHS[path] if isinstance(path, str) else int(path)
+        nbytes = ranc_workspace_bytes(self.desc, num_samples, max_ticks_per_call, p)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(self.workspace.device)
+        self.handle = ranc_load_network(self.desc, num_samples, max_ticks_per_call, p,
+                                        self.workspace.data_ptr(), self.workspace.numel(),
+                                        self.stream.cuda_stream)
+        self.path = {RANC_PATH_PLAIN: "plain", RANC_PATH_MFMA: "mfma"}[ranc_get_path(self.handle)]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ranc_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def tick(self) -> int:
+        return ranc_current_tick(self.handle)
+
+    def run(self, inputs, num_ticks: int):
+        """Advance by num_ticks. ``inputs``: None, a numpy uint32 array or a CUDA tensor
+        (int32/uint32 bits) of shape [S, num_ticks, C_in, A/32]."""
+        flags, ptr, keep = 0, None, None
+        if inputs is not None:
+            if isinstance(inputs, np.ndarray):
+                keep = np.ascontiguousarray(inputs, dtype=np.uint32)
+                assert keep.shape[:2] == (self.S, num_ticks), keep.shape
+                ptr = keep.ctypes.data
+            else:
+                assert inputs.is_cuda and inputs.is_contiguous() and inputs.element_size() == 4
+                assert tuple(inputs.shape[:2]) == (self.S, num_ticks), tuple(inputs.shape)
+                flags, ptr, keep = RANC_INPUTS_ON_DEVICE, inputs.data_ptr(), inputs
+        ranc_run_ticks([self.handle], [ptr] if ptr else None, flags, num_ticks, self.stream.cuda_stream)
+        if isinstance(keep, np.ndarray):
+            self.stream.synchronize()   # host buffer must outlive the staging copy
+        return self
+
+    def spikes(self, sample: int, tick_begin: int | None = None, tick_end: int | None = None) -> np.ndarray:
+        t = self.tick
+        if tick_end is None:
+            tick_end = t
+        if tick_begin is None:
+            tick_begin = max(0, t - self.RT)
+        sp = ranc_read_spikes(self.handle, sample, tick_begin, tick_end)
+        return np.stack([sp["tick"], sp["core"].astype(np.int64), sp["neuron"].astype(np.int64)], axis=1) \
+            if len(sp) else np.zeros((0, 3), np.int64)
+
+    def potentials(self, sample: int) -> np.ndarray:
+        return ranc_read_potentials(self.handle, sample, self.net.num_cores, self.net.num_neurons)
+
+    def counters(self, sample: int) -> dict:
+        return ranc_read_counters(self.handle, sample)
+
+    def reset(self):
+        ranc_reset_state(self.handle, self.stream.cuda_stream)
+        return self

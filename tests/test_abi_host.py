@@ -1,0 +1,195 @@
+"""Host-side tests of the C ABI: exported symbols and description validation.
+
+These need no GPU: ranc_workspace_bytes validates the description and sizes
+the workspace on the host. Every rejection must name the offending field.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_16208_amd import workloads as W
+from tests.oracle_pins import make_net
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2404_16208_amd import ranc
+    return ranc
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ranc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ranc_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function(R):
+    names = header_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(R.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/ranc.h but not exported"
+    assert sorted(R.EXPORTED) == names
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "ranc_copy", os.path.join(ROOT, "paper_2404_16208_amd", "ranc.py"))
+    mod = importlib.util.module_from_spec(spec)
+    src = open(spec.origin).read().replace('LIB_PATH = os.path.join(_HERE, "libranc.so")',
+                                           f'LIB_PATH = {str(tmp_path / "missing.so")!r}')
+    with pytest.raises(ImportError):
+        exec(compile(src, spec.origin, "exec"), mod.__dict__)
+
+
+def base_net():
+    return W.random_net(7, 4, 64, 64, 4, grid_w=2, max_delay=3, p_core=0.6, p_out=0.3,
+                        input_cores=[0, 3], config_id=600)
+
+
+def ws_status(R, net, S=4, T=8, path=0):
+    d = R.Desc(net)
+    out = ctypes.c_size_t(0)
+    st = R._lib.ranc_workspace_bytes(ctypes.byref(d.c), S, T, path, ctypes.byref(out))
+    return st, R.ranc_last_error(), int(out.value)
+
+
+def test_valid_net_sizes(R):
+    net = base_net()
+    st, msg, b = ws_status(R, net)
+    assert st == R.RANC_OK, msg
+    # at least potentials + scheduler + spikes
+    C, A, N, S = 4, 64, 64, 4
+    assert b >= C * S * N * 4 + 4 * S * C * (A // 32) * 4
+    st2, _, b2 = ws_status(R, net, S=8)
+    assert st2 == 0 and b2 > b
+
+
+@pytest.mark.parametrize("mutate,status,needle", [
+    (lambda n: setattr(n, "num_axons", 96), "RANC_EUNSUPPORTED", "num_axons"),
+    (lambda n: setattr(n, "num_neurons", 32), "RANC_EUNSUPPORTED", "num_neurons"),
+    (lambda n: setattr(n, "num_types", 3), "RANC_EUNSUPPORTED", "num_types"),
+    (lambda n: setattr(n, "weight_bits", 10), "RANC_ERANGE", "weight_bits"),
+    (lambda n: setattr(n, "potential_bits", 33), "RANC_ERANGE", "potential_bits"),
+    (lambda n: setattr(n, "max_delay", 0), "RANC_ERANGE", "max_delay"),
+    (lambda n: setattr(n, "max_delay", 16), "RANC_ERANGE", "max_delay"),
+    (lambda n: setattr(n, "grid_w", 3), "RANC_EINVAL", "grid"),
+])
+def test_shape_rejections(R, mutate, status, needle):
+    net = base_net()
+    mutate(net)
+    st, msg, _ = ws_status(R, net)
+    assert R.STATUS_NAMES[st] == status and needle in msg, (st, msg)
+
+
+def _first_core_neuron(net):
+    idx = np.argwhere(net.dest_kind == W.DEST_CORE)
+    return tuple(idx[0])
+
+
+@pytest.mark.parametrize("case,status,needle", [
+    ("weight_high", "RANC_ERANGE", "weight"),
+    ("weight_low", "RANC_ERANGE", "weight"),
+    ("axon_type", "RANC_ERANGE", "axon_type"),
+    ("delay_zero", "RANC_ERANGE", "dest_delay"),
+    ("delay_big", "RANC_ERANGE", "dest_delay"),
+    ("dest_axon", "RANC_ERANGE", "dest_axon"),
+    ("off_grid_x", "RANC_ERANGE", "leaves"),
+    ("off_grid_y", "RANC_ERANGE", "leaves"),
+    ("reset_range", "RANC_ERANGE", "reset"),
+    ("vinit_range", "RANC_ERANGE", "v_init"),
+    ("dest_kind", "RANC_EINVAL", "dest_kind"),
+    ("input_dup", "RANC_EINVAL", "twice"),
+    ("input_range", "RANC_ERANGE", "input_cores"),
+])
+def test_value_rejections(R, case, status, needle):
+    net = base_net()
+    c, n = _first_core_neuron(net)
+    if case == "weight_high":
+        net.weight[1, 2, 3] = 256
+    elif case == "weight_low":
+        net.weight[1, 2, 3] = -257
+    elif case == "axon_type":
+        net.axon_type[2, 5] = 4
+    elif case == "delay_zero":
+        net.dest_delay[c, n] = 0
+    elif case == "delay_big":
+        net.dest_delay[c, n] = 4
+    elif case == "dest_axon":
+        net.dest_axon[c, n] = 64
+    elif case == "off_grid_x":
+        net.dest_dx[c, n] = 2
+    elif case == "off_grid_y":
+        net.dest_dy[c, n] = -3
+    elif case == "reset_range":
+        net.potential_bits = 8
+        net.reset[0, 0] = 128
+    elif case == "vinit_range":
+        net.potential_bits = 8
+        net.v_init[0, 0] = -129
+    elif case == "dest_kind":
+        net.dest_kind[0, 0] = 3
+    elif case == "input_dup":
+        net.input_cores = np.array([1, 1], np.int32)
+    elif case == "input_range":
+        net.input_cores = np.array([4], np.int32)
+    st, msg, _ = ws_status(R, net)
+    assert R.STATUS_NAMES[st] == status and needle in msg, (st, msg)
+
+
+def test_boundary_values_accepted(R):
+    net = base_net()
+    net.weight[0, 0, 0] = -256          # [-2^(b-1), 2^(b-1)-1] at b = 9
+    net.weight[0, 0, 1] = 255
+    c, n = _first_core_neuron(net)
+    net.dest_delay[c, n] = 3            # = max_delay
+    st, msg, _ = ws_status(R, net)
+    assert st == R.RANC_OK, msg
+
+
+def test_argument_rejections(R):
+    net = base_net()
+    d = R.Desc(net)
+    out = ctypes.c_size_t(0)
+    assert R._lib.ranc_workspace_bytes(None, 4, 8, 0, ctypes.byref(out)) == R.RANC_EINVAL
+    assert R._lib.ranc_workspace_bytes(ctypes.byref(d.c), 0, 8, 0, ctypes.byref(out)) == R.RANC_EINVAL
+    assert R._lib.ranc_workspace_bytes(ctypes.byref(d.c), 4, 0, 0, ctypes.byref(out)) == R.RANC_EINVAL
+    assert R._lib.ranc_workspace_bytes(ctypes.byref(d.c), 4, 8, 9, ctypes.byref(out)) == R.RANC_EINVAL
+    d.c.abi_version = 99
+    assert R._lib.ranc_workspace_bytes(ctypes.byref(d.c), 4, 8, 0, ctypes.byref(out)) == R.RANC_EINVAL
+    assert "abi_version" in R.ranc_last_error()
+    d = R.Desc(net)
+    d.c.crossbar = None
+    assert R._lib.ranc_workspace_bytes(ctypes.byref(d.c), 4, 8, 0, ctypes.byref(out)) == R.RANC_EINVAL
+    # load with a null / undersized / misaligned workspace fails before touching the device
+    d = R.Desc(net)
+    h = ctypes.c_void_p(0)
+    assert R._lib.ranc_load_network(ctypes.byref(d.c), 4, 8, 0, None, 0, None, ctypes.byref(h)) == R.RANC_EINVAL
+    assert R._lib.ranc_load_network(ctypes.byref(d.c), 4, 8, 0, 256, 16, None, ctypes.byref(h)) == R.RANC_ENOMEM
+    assert R._lib.ranc_load_network(ctypes.byref(d.c), 4, 8, 0, 257, 1 << 30, None, ctypes.byref(h)) == R.RANC_EINVAL
+    assert not h.value
+    # run / read with null handles
+    assert R._lib.ranc_run_ticks(None, 1, None, 0, 1, None) == R.RANC_EINVAL
+    assert R._lib.ranc_read_potentials(None, 0, None) == R.RANC_EINVAL
+    R._lib.ranc_free(None)
+
+
+def test_mfma_path_unsupported_shape_reported(R):
+    net = W.random_net(8, 4, 512, 512, 2, grid_w=2, config_id=601)
+    st, msg, _ = ws_status(R, net, path=R.RANC_PATH_MFMA)
+    assert R.STATUS_NAMES[st] == "RANC_EUNSUPPORTED" and "MFMA" in msg
+    st, msg, _ = ws_status(R, net, path=R.RANC_PATH_AUTO)
+    assert st == R.RANC_OK, msg
+
+
+def test_tiny_validation_net_from_pins_rejected_shape(R):
+    # the oracle's pin nets use 1-axon cores: the library refuses them explicitly
+    net = make_net(1, 1, 1, dest_kind=W.DEST_OUT)
+    st, msg, _ = ws_status(R, net)
+    assert R.STATUS_NAMES[st] == "RANC_EUNSUPPORTED"

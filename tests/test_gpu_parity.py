@@ -1,0 +1,167 @@
+"""GPU parity: the HIP library against the serial oracle, bit for bit.
+
+Every test compares output-bus spikes (tick, core, neuron), final potentials
+and the five counters per sample. Sizes are chosen so the oracle finishes in
+seconds while the GPU launch still spans several tiles and a ragged tail
+(e.g. 70 or 100 samples = one full 64-sample MFMA tile plus a partial one).
+"""
+import numpy as np
+import pytest
+
+from paper_2404_16208_amd import workloads as W
+from tests.parity_utils import assert_parity, gpu_run, log, oracle_results, assert_sample_equal
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_16208_amd import ranc  # noqa: F401  (fails loudly if the library is missing)
+
+
+# ----------------------------------------------------------- tiny 5-core net
+
+@pytest.mark.parametrize("path", ["plain", "mfma"])
+def test_tiny_net_all_samples(path):
+    net = W.tiny_net(0)
+    x = W.tiny_inputs(0, S=10, T=16)
+    assert_parity(net, x, 16, path, what="tiny5")
+
+
+# ----------------------------------------------------------- random shapes
+
+SHAPES = [
+    # C, A, N, G, weight_bits, potential_bits, max_delay, grid_w, S, T
+    (6, 256, 256, 4, 9, 32, 4, 3, 70, 12),
+    (4, 64, 64, 2, 4, 8, 2, 2, 70, 10),
+    (8, 128, 64, 8, 8, 16, 7, 4, 100, 9),
+    (4, 64, 128, 1, 9, 12, 15, 2, 65, 20),
+    (4, 128, 256, 4, 6, 32, 3, 4, 64, 8),
+    (3, 512, 128, 4, 8, 32, 5, 3, 66, 6),
+    (2, 512, 512, 2, 9, 32, 3, 2, 5, 6),
+    (4, 256, 64, 4, 9, 10, 1, 2, 129, 7),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "C{}A{}N{}G{}b{}P{}D{}".format(*s[:7]))
+@pytest.mark.parametrize("path", ["plain", "auto"])
+def test_random_shapes(shape, path):
+    C, A, N, G, b, P, D, gw, S, T = shape
+    wmax = (1 << (b - 1)) - 1
+    lim = (1 << (P - 1)) - 1
+    net = W.random_net(1000 + C * A + N + G + b + P + D, C, A, N, G, weight_bits=b, potential_bits=P,
+                       max_delay=D, grid_w=gw, density=0.25, p_core=0.7, p_out=0.25,
+                       leak_range=(-4, 4), thr_range=(max(1, wmax // 2), min(lim, 4 * wmax)),
+                       reset_range=(-3, 2), vinit_range=(-5, 5),
+                       input_cores=list(range(0, C, 2)), config_id=700,
+                       weight_range=(-wmax - 1, wmax))
+    x = W.bernoulli_inputs(11, net, S, T, 0.3, config_id=700)
+    assert_parity(net, x, T, path, what=f"rand{shape[:7]}")
+
+
+def test_large_core_count_unstaged_route():
+    # 1280 cores x 512 neurons: the per-sample spike bitmap (80 KiB) exceeds the
+    # LDS staging size, so the router reads spikes from global memory.
+    net = W.random_net(77, 1280, 64, 512, 2, weight_bits=9, max_delay=6, grid_w=40, density=0.3,
+                       p_core=0.8, p_out=0.1, input_cores=list(range(0, 1280, 3)), config_id=701)
+    x = W.bernoulli_inputs(12, net, 3, 5, 0.3, config_id=701)
+    assert_parity(net, x, 5, "plain", what="C1280N512")
+
+
+def test_no_input_no_output_cores():
+    net = W.random_net(78, 4, 64, 64, 2, max_delay=2, grid_w=2, p_core=1.0, p_out=0.0,
+                       leak_range=(5, 20), thr_range=(10, 40), input_cores=[], config_id=702)
+    assert len(net.input_cores) == 0 and not (net.dest_kind == W.DEST_OUT).any()
+    for path in ("plain", "mfma"):
+        g = gpu_run(net, None, 9, path, S=64)
+        ref = oracle_results(net, None, 9, [0])[0]
+        for s in (0, 31, 63):
+            assert_sample_equal(g, ref, s, 9, what=f"noio/{path}")
+
+
+# ----------------------------------------------------------- resume / state
+
+@pytest.mark.parametrize("path", ["plain", "mfma"])
+def test_chunked_run_equals_single_run(path):
+    net = W.random_net(79, 6, 128, 128, 4, max_delay=5, grid_w=3, density=0.3, p_core=0.7, p_out=0.3,
+                       input_cores=[0, 1, 2], config_id=703)
+    x = W.bernoulli_inputs(13, net, 70, 17, 0.35, config_id=703)
+    # chunks of 5 + 5 + 7 ticks: deliveries scheduled past a chunk end must survive
+    assert_parity(net, x, 17, path, chunks=[5, 5, 7], what="chunked")
+
+
+@pytest.mark.parametrize("path", ["plain", "mfma"])
+def test_device_inputs_and_reset(path):
+    net = W.tiny_net(0)
+    x = W.tiny_inputs(0, S=64, T=16)
+    g = assert_parity(net, x, 16, path, samples=[0, 7, 63], device_inputs=True, what="devinputs")
+    v_before = [g.potentials(s) for s in (0, 63)]
+    e_before = [g.spikes(s) for s in (0, 63)]
+    g.reset()
+    assert g.tick == 0
+    g.run(np.ascontiguousarray(x), 16)
+    for i, s in enumerate((0, 63)):
+        assert np.array_equal(g.potentials(s), v_before[i])
+        assert np.array_equal(g.spikes(s), e_before[i])
+
+
+def test_read_window_errors():
+    from paper_2404_16208_amd import ranc as R
+    net = W.tiny_net(0)
+    x = W.tiny_inputs(0, S=2, T=16)
+    g = gpu_run(net, x, 16, "plain", chunks=[8, 8])
+    with pytest.raises(R.RancError) as ei:
+        R.ranc_read_spikes(g.handle, 0, 0, 16)       # ticks 0..7 were overwritten
+    assert ei.value.status == R.RANC_ESTATE
+    with pytest.raises(R.RancError) as ei:
+        R.ranc_read_spikes(g.handle, 2, 8, 16)       # sample out of range
+    assert ei.value.status == R.RANC_EINVAL
+
+
+# ----------------------------------------------------------- 512-core MNIST-shaped net
+
+@pytest.fixture(scope="module")
+def mnist():
+    log("[gen] mnist net + 100x32 inputs")
+    return W.mnist_net(0), W.mnist_inputs(0, 100, 32)
+
+
+@pytest.mark.parametrize("path", ["plain", "mfma"])
+def test_mnist512_100x32(mnist, path):
+    net, x = mnist
+    samples = [0, 1, 2, 3, 13, 37, 63, 64, 65, 77, 98, 99]
+    assert_parity(net, x, 32, path, samples=samples, what="mnist512")
+
+
+def test_mnist512_paths_agree_all_samples(mnist):
+    net, x = mnist
+    gp = gpu_run(net, x, 32, "plain")
+    gm = gpu_run(net, x, 32, "mfma")
+    for s in range(100):
+        assert np.array_equal(gp.potentials(s), gm.potentials(s)), s
+        assert np.array_equal(gp.spikes(s), gm.spikes(s)), s
+        assert gp.counters(s) == gm.counters(s), s
+
+
+def test_mnist512_batched_1024_samples():
+    """The 1024-sample batch on the MFMA path: sampled samples against the
+    oracle, every sample against the plain GPU path, and the first 100 samples
+    equal to the 100-sample batch (samples are independent instances)."""
+    import torch
+    net = W.mnist_net(0)
+    log("[gen] mnist 1024x32 inputs")
+    x = W.mnist_inputs(0, 1024, 32)
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    from paper_2404_16208_amd.ranc import RancNet
+    gm = RancNet(net, 1024, 32, path="mfma").run(xd, 32)
+    ref = oracle_results(net, x, 32, [0, 511, 640, 1000, 1023])
+    for s, r in ref.items():
+        assert_sample_equal(gm, r, s, 32, what="mnist1024/mfma")
+    gp = RancNet(net, 1024, 32, path="plain").run(xd, 32)
+    torch.cuda.synchronize()
+    for s in range(0, 1024, 7):
+        assert np.array_equal(gp.potentials(s), gm.potentials(s)), s
+        assert np.array_equal(gp.spikes(s), gm.spikes(s)), s
+        assert gp.counters(s) == gm.counters(s), s
