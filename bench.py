@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Throughput of the RANC tick engine on one MI355X.
+
+Workload: the 512-core layered feed-forward net shaped like the paper's
+MNIST-512c application (4 layers x 128 cores of 256 axons x 256 neurons,
+crossbar density 0.2, 4 axon types, signed 9-bit weights, delays 1-4,
+rate-coded 784-pixel input), 1024 independent samples. One step advances all
+1024 samples by 32 ticks (every tick: scheduler slot + input, integration,
+leak/threshold/reset, routing into the delayed-delivery scheduler), on the
+batched int8-MFMA path. Inputs are synthetic and resident in HBM before
+timing starts. The same steps are also timed on the plain path.
+
+Output: one JSON line. ``value`` is synaptic events per second (events =
+(spiking axon, connected neuron) pairs, counted by the GPU itself over the
+timed steps); core-ticks per second is reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "synaptic events/sec & core-ticks/sec at 512 cores; batched-MFMA vs plain, bit-exact"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_integrate_mfma_mnist512_s1024.txt")
+KERNEL_SOURCES = ["paper_2404_16208_amd/csrc/kern_mfma.hip", "paper_2404_16208_amd/csrc/kern_common.h",
+                  "paper_2404_16208_amd/csrc/ranc_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def integrate_algorithmic_bytes(net, S: int, path: str) -> dict:
+    """Bytes one integration launch must move at minimum (one tick, all samples).
+
+    Per (sample, core): potentials read + written (8 N), the tick's axon spike
+    bits read (A/8) and the spike bits written (N/8). Per (sample, input core):
+    external input bits (A/8). Per (sample, output word): 4 bytes of raster.
+    Per core, once per launch: the weights in the path's form (MFMA: A*N bytes
+    per int8 plane; plain: crossbar columns A*N/8 + per-type weights 4GN +
+    type masks GA/8) and the neuron parameters (leak, threshold, reset: 12 N).
+    """
+    C, A, N, G = net.num_cores, net.num_axons, net.num_neurons, net.num_types
+    Cin = len(net.input_cores)
+    out_words = int(((net.dest_kind == 2).reshape(C, N // 32, 32).any(axis=2)).sum())
+    per_unit = 8 * N + A // 8 + N // 8
+    state = S * C * per_unit + S * Cin * (A // 8) + S * out_words * 4
+    if path == "mfma":
+        planes = 2 if net.weight_bits > 8 else 1
+        params = C * (A * N * planes + 12 * N + 4 * A)
+    else:
+        params = C * (A * N // 8 + 4 * G * N + G * A // 8 + 12 * N)
+    return dict(per_unit=per_unit, units=S * C, total=state + params, state=state, params=params)
+
+
+def read_traffic(src_hash: str):
+    """HBM traffic per integration launch from the committed rocprofv3 PMC
+    summary, or None if it is absent or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(g, xd, T, warmup, steps, torch):
+    for _ in range(warmup):
+        g.run(xd, T)
+    torch.cuda.synchronize()
+    before = g.total_counters()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(steps):
+        g.run(xd, T)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    after = g.total_counters()
+    delta = {k: after[k] - before[k] for k in after}
+    return ms, delta
+
+
+def kernel_profile(g, xd, T, steps, torch):
+    g.profile(True)
+    for _ in range(steps):
+        g.run(xd, T)
+    torch.cuda.synchronize()
+    p = g.profile_read()
+    g.profile(False)
+    return p
+
+
+def cpu_baseline(net, x, T, n_samples, gpu_net, torch):
+    """The serial oracle on a bounded sample (test-infrastructure code), timed
+    on the host; the same samples are compared bit for bit with a fresh GPU run."""
+    from oracle import ranc_oracle as O
+
+    threads = max(1, min(16, os.cpu_count() or 1, n_samples))
+    O.build(force=False)
+    t0 = time.perf_counter()
+    res = O.simulate(net, x, T, samples=range(n_samples), threads=threads)
+    dt = time.perf_counter() - t0
+    events = sum(r["counters"]["events"] for r in res)
+    gpu_net.reset()
+    gpu_net.run(torch.from_numpy(x.view("int32")).cuda(), T)
+    torch.cuda.synchronize()
+    import numpy as np
+    exact = True
+    for r in res:
+        s = r["sample"]
+        exact &= bool(np.array_equal(gpu_net.spikes(s), r["events"]))
+        exact &= bool(np.array_equal(gpu_net.potentials(s), r["v"]))
+        c = gpu_net.counters(s)
+        exact &= all(c[k] == r["counters"][k] for k in c)
+    return {"value": events / dt, "unit": "synaptic events/s", "cores": threads, "kind": "oracle",
+            "sample": f"samples 0..{n_samples - 1} of the 1024-sample batch x {T} ticks "
+                      f"(serial C oracle, one sample per thread), {dt:.2f} s wall",
+            "core_ticks_per_s": n_samples * net.num_cores * T / dt,
+            "gpu_bit_exact_on_sample": exact}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--samples", type=int, default=1024)
+    ap.add_argument("--ticks", type=int, default=32)
+    ap.add_argument("--cpu-samples", type=int, default=16)
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; multi-GPU runs are not part of this build "
+                                   "(samples shard across GPUs without communication, see DESIGN.md)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2404_16208_amd import workloads as W
+    from paper_2404_16208_amd.ranc import RancNet
+
+    torch.cuda.set_device(0)
+    S, T = args.samples, args.ticks
+    print(f"[bench] generating 512-core net and {S}x{T} inputs", file=sys.stderr, flush=True)
+    net = W.mnist_net(0)
+    x = W.mnist_inputs(0, S, T)
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    C = net.num_cores
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20)
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {n} bytes done", file=sys.stderr, flush=True)
+        del a, b
+
+    print("[bench] mfma path: load + warmup + timed steps", file=sys.stderr, flush=True)
+    g = RancNet(net, S, T, path="mfma")
+    ms, delta = time_steps(g, xd, T, args.warmup, args.steps, torch)
+    prof = kernel_profile(g, xd, T, max(2, min(args.steps, 10)), torch)
+    secs = ms / 1e3
+    events_per_s = delta["events"] / secs
+    core_ticks = S * C * T * args.steps
+    ib = integrate_algorithmic_bytes(net, S, "mfma")
+    avg_int_ms = prof["integrate_ms"] / max(1, prof["integrate_launches"])
+    avg_route_ms = prof["route_ms"] / max(1, prof["route_launches"])
+    achieved = ib["total"] / (avg_int_ms / 1e3) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = read_traffic(src_hash)
+    out = {
+        "metric": METRIC,
+        "value": events_per_s,
+        "unit": "synaptic events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": f"512-core layered feed-forward net (4 layers x 128 cores of 256 axons x 256 "
+                               f"neurons, MNIST-shaped), {S} samples x {T} ticks per step, batched int8-MFMA",
+                   "cores": C, "axons": 256, "neurons": 256, "samples": S, "ticks_per_step": T, "path": "mfma",
+                   "parallelism": "single GPU"},
+        "core_ticks_per_s": core_ticks / secs,
+        "synaptic_events_per_step": delta["events"] / args.steps,
+        "spikes_emitted_per_step": delta["emitted"] / args.steps,
+        "kernels": {"integrate_mfma_avg_ms": avg_int_ms, "route_avg_ms": avg_route_ms,
+                    "launches_profiled": prof["integrate_launches"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (traffic / (avg_int_ms / 1e3) / 1e9) if traffic else None,
+                     "kernel": "k_integrate_mfma<256,256,two planes>",
+                     "algorithmic_bytes_per_launch": ib["total"],
+                     "bytes_per_unit": ib["per_unit"], "units_per_launch": ib["units"],
+                     "kernel_source_sha256_16": src_hash},
+    }
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+
+    if not args.skip_plain:
+        print("[bench] plain path", file=sys.stderr, flush=True)
+        gp = RancNet(net, S, T, path="plain")
+        psteps = max(2, args.steps // 4)
+        pms, pdelta = time_steps(gp, xd, T, 1, psteps, torch)
+        pprof = kernel_profile(gp, xd, T, 2, torch)
+        pint = pprof["integrate_ms"] / max(1, pprof["integrate_launches"])
+        pib = integrate_algorithmic_bytes(net, S, "plain")
+        out["plain"] = {"value": pdelta["events"] / (pms / 1e3), "unit": "synaptic events/s",
+                        "core_ticks_per_s": S * C * T * psteps / (pms / 1e3), "ms_per_step": pms / psteps,
+                        "steps": psteps, "integrate_plain_avg_ms": pint,
+                        "route_avg_ms": pprof["route_ms"] / max(1, pprof["route_launches"]),
+                        "integrate_hbm_frac": pib["total"] / (pint / 1e3) / 1e9 / HBM_PEAK_GBS}
+        out["mfma_speedup_vs_plain"] = out["plain"]["ms_per_step"] and (out["plain"]["ms_per_step"] / out["ms_per_step"])
+        gp.close()
+        del gp
+        torch.cuda.empty_cache()
+
+    if not args.skip_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        gc = RancNet(net, S, T, path="mfma")
+        out["cpu_baseline"] = cpu_baseline(net, x, T, min(args.cpu_samples, S), gc, torch)
+        gc.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -175,6 +175,21 @@ ranc_status ranc_current_tick(const ranc_net *net, int64_t *tick);
 /* Integration path chosen at load (RANC_PATH_PLAIN or RANC_PATH_MFMA). */
 ranc_status ranc_get_path(const ranc_net *net, int32_t *path);
 
+/* Kernel timing, recorded with HIP events on the launch stream around every
+ * integration and routing launch while enabled. */
+typedef struct ranc_profile {
+    double integrate_ms;         /* summed duration of integration launches */
+    double route_ms;             /* summed duration of routing launches */
+    int64_t integrate_launches;
+    int64_t route_launches;
+} ranc_profile;
+
+/* Enable (1) or disable (0) timing; enabling clears the totals. Host-side only. */
+ranc_status ranc_profile_enable(ranc_net *net, int32_t enable);
+
+/* Totals since timing was enabled. Synchronizes the stream of the last run. */
+ranc_status ranc_profile_read(ranc_net *net, ranc_profile *out);
+
 /* Return every instance to its initial state (queued on `stream`). */
 ranc_status ranc_reset_state(ranc_net *net, void *stream);
 

@@ -325,8 +325,21 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
 
 }  // namespace
 
+struct EventPair {
+    hipEvent_t a, b;
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<EventPair> pool;          // created on demand, reused
+    std::vector<std::pair<int, int>> used; // (pool index, kind 0=integrate 1=route)
+    double ms[2] = {0, 0};
+    int64_t launches[2] = {0, 0};
+};
+
 struct ranc_net {
     Plan p;
+    Profiler prof;
     DevNet dn;
     uint8_t *ws;
     hipStream_t last_stream;
@@ -335,6 +348,50 @@ struct ranc_net {
     std::vector<int> out_words;        // (core, word) pairs of raster columns
     std::vector<uint32_t> raster_host; // mirror of the raster
 };
+
+static hipError_t prof_begin(ranc_net *net, int kind, hipStream_t s, int *slot)
+{
+    *slot = -1;
+    if (!net->prof.on)
+        return hipSuccess;
+    Profiler &pr = net->prof;
+    const size_t idx = pr.used.size();
+    if (idx == pr.pool.size()) {
+        EventPair e;
+        hipError_t r = hipEventCreate(&e.a);
+        if (r == hipSuccess)
+            r = hipEventCreate(&e.b);
+        if (r != hipSuccess)
+            return r;
+        pr.pool.push_back(e);
+    }
+    pr.used.push_back({(int)idx, kind});
+    *slot = (int)idx;
+    return hipEventRecord(pr.pool[idx].a, s);
+}
+
+static hipError_t prof_end(ranc_net *net, int slot, hipStream_t s)
+{
+    if (slot < 0)
+        return hipSuccess;
+    return hipEventRecord(net->prof.pool[slot].b, s);
+}
+
+// Fold recorded event pairs into the totals (the stream must be synchronized).
+static hipError_t prof_collect(ranc_net *net)
+{
+    Profiler &pr = net->prof;
+    for (auto &u : pr.used) {
+        float ms = 0.f;
+        hipError_t r = hipEventElapsedTime(&ms, pr.pool[u.first].a, pr.pool[u.first].b);
+        if (r != hipSuccess)
+            return r;
+        pr.ms[u.second] += ms;
+        pr.launches[u.second] += 1;
+    }
+    pr.used.clear();
+    return hipSuccess;
+}
 
 extern "C" {
 
@@ -455,11 +512,28 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
             ta.r_row = (int)(net->tick % p.RT);
             ta.ext_t = base ? base + (size_t)k * tick_words : nullptr;
             ta.ext_sstride = (long long)num_ticks * tick_words;
-            hipError_t e = p.path == RANC_PATH_MFMA ? launch_integrate_mfma(net->dn, ta, p.two, p.spw, s)
-                                                     : launch_integrate_plain(net->dn, ta, s);
+            // A long timed run folds finished event pairs in batches.
+            if (net->prof.used.size() >= 4096) {
+                hipError_t e = hipStreamSynchronize(s);
+                if (e == hipSuccess)
+                    e = prof_collect(net);
+                if (e != hipSuccess)
+                    return hip_fail(e, "collecting kernel timings");
+            }
+            int slot;
+            hipError_t e = prof_begin(net, 0, s, &slot);
+            if (e == hipSuccess)
+                e = p.path == RANC_PATH_MFMA ? launch_integrate_mfma(net->dn, ta, p.two, p.spw, s)
+                                             : launch_integrate_plain(net->dn, ta, s);
+            if (e == hipSuccess)
+                e = prof_end(net, slot, s);
             if (e != hipSuccess)
                 return hip_fail(e, "launching integration");
-            e = launch_route(net->dn, ta.q_now, s);
+            e = prof_begin(net, 1, s, &slot);
+            if (e == hipSuccess)
+                e = launch_route(net->dn, ta.q_now, s);
+            if (e == hipSuccess)
+                e = prof_end(net, slot, s);
             if (e != hipSuccess)
                 return hip_fail(e, "launching routing");
             ++net->tick;
@@ -586,6 +660,39 @@ ranc_status ranc_get_path(const ranc_net *net, int32_t *path)
     return RANC_OK;
 }
 
+ranc_status ranc_profile_enable(ranc_net *net, int32_t enable)
+{
+    if (!net)
+        return fail(RANC_EINVAL, "net is NULL");
+    if (enable) {
+        ranc_status st = sync_net(net);
+        if (st != RANC_OK)
+            return st;
+        net->prof.used.clear();
+        net->prof.ms[0] = net->prof.ms[1] = 0;
+        net->prof.launches[0] = net->prof.launches[1] = 0;
+    }
+    net->prof.on = enable != 0;
+    return RANC_OK;
+}
+
+ranc_status ranc_profile_read(ranc_net *net, ranc_profile *out)
+{
+    if (!net || !out)
+        return fail(RANC_EINVAL, "net or out is NULL");
+    ranc_status st = sync_net(net);
+    if (st != RANC_OK)
+        return st;
+    hipError_t e = prof_collect(net);
+    if (e != hipSuccess)
+        return hip_fail(e, "reading kernel timings");
+    out->integrate_ms = net->prof.ms[0];
+    out->route_ms = net->prof.ms[1];
+    out->integrate_launches = net->prof.launches[0];
+    out->route_launches = net->prof.launches[1];
+    return RANC_OK;
+}
+
 ranc_status ranc_reset_state(ranc_net *net, void *stream)
 {
     if (!net)
@@ -605,6 +712,10 @@ void ranc_free(ranc_net *net)
     if (!net)
         return;
     hipStreamSynchronize(net->last_stream);
+    for (auto &e : net->prof.pool) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
     delete net;
 }
 

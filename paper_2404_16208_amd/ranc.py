@@ -27,7 +27,7 @@ RANC_INPUTS_ON_DEVICE = 1
 
 EXPORTED = ("ranc_last_error", "ranc_workspace_bytes", "ranc_load_network", "ranc_run_ticks",
             "ranc_read_spikes", "ranc_read_potentials", "ranc_read_counters", "ranc_current_tick",
-            "ranc_get_path", "ranc_reset_state", "ranc_free")
+            "ranc_get_path", "ranc_profile_enable", "ranc_profile_read", "ranc_reset_state", "ranc_free")
 
 
 class RancError(RuntimeError):
@@ -48,6 +48,11 @@ class ranc_net_desc(C.Structure):
 
 class ranc_spike(C.Structure):
     _fields_ = [("tick", C.c_int64), ("core", C.c_int32), ("neuron", C.c_int32)]
+
+
+class ranc_profile(C.Structure):
+    _fields_ = [("integrate_ms", C.c_double), ("route_ms", C.c_double),
+                ("integrate_launches", C.c_int64), ("route_launches", C.c_int64)]
 
 
 class ranc_counters(C.Structure):
@@ -73,6 +78,8 @@ def _load_lib():
         "ranc_read_counters": (C.c_int, [vp, i32, C.POINTER(ranc_counters)]),
         "ranc_current_tick": (C.c_int, [vp, C.POINTER(i64)]),
         "ranc_get_path": (C.c_int, [vp, C.POINTER(i32)]),
+        "ranc_profile_enable": (C.c_int, [vp, i32]),
+        "ranc_profile_read": (C.c_int, [vp, C.POINTER(ranc_profile)]),
         "ranc_reset_state": (C.c_int, [vp, vp]),
         "ranc_free": (None, [vp]),
     }
@@ -175,6 +182,16 @@ def ranc_get_path(handle: int) -> int:
     return int(p.value)
 
 
+def ranc_profile_enable(handle: int, enable: bool) -> None:
+    _check(_lib.ranc_profile_enable(handle, 1 if enable else 0))
+
+
+def ranc_profile_read(handle: int) -> dict:
+    p = ranc_profile()
+    _check(_lib.ranc_profile_read(handle, C.byref(p)))
+    return {k: (float(getattr(p, k)) if k.endswith("_ms") else int(getattr(p, k))) for k, _ in ranc_profile._fields_}
+
+
 def ranc_reset_state(handle: int, stream: int) -> None:
     _check(_lib.ranc_reset_state(handle, stream))
 
@@ -256,3 +273,17 @@ class RancNet:
     def reset(self):
         ranc_reset_state(self.handle, self.stream.cuda_stream)
         return self
+
+    def profile(self, enable: bool = True):
+        ranc_profile_enable(self.handle, enable)
+        return self
+
+    def profile_read(self) -> dict:
+        return ranc_profile_read(self.handle)
+
+    def total_counters(self) -> dict:
+        tot = dict(emitted=0, routed=0, delivered=0, out=0, events=0)
+        for s in range(self.S):
+            for k, v in self.counters(s).items():
+                tot[k] += v
+        return tot
