@@ -65,7 +65,7 @@ enum {
  * Core c sits at mesh position (x, y) = (c % grid_w, c / grid_w).
  * Supported shapes: num_axons, num_neurons in {64, 128, 256, 512};
  * num_types in {1, 2, 4, 8}; 2 <= weight_bits <= 9; 2 <= potential_bits <= 32;
- * 1 <= max_delay <= 15; num_cores * num_neurons < 2^27.
+ * 1 <= max_delay <= 15; num_cores * num_neurons <= 2^23.
  */
 typedef struct ranc_net_desc {
     uint32_t abi_version;      /* must be RANC_ABI_VERSION */
@@ -80,7 +80,7 @@ typedef struct ranc_net_desc {
     const uint32_t *crossbar;  /* [C][A][N/32]: bit n%32 of word n/32 set = axon a connects to neuron n */
     const uint8_t *axon_type;  /* [C][A]: type in [0, G) */
     const int16_t *weight;     /* [C][N][G] */
-    const int32_t *leak;       /* [C][N]: added every tick */
+    const int32_t *leak;       /* [C][N]: added every tick; within [-2^30, 2^30] */
     const int32_t *threshold;  /* [C][N]: a neuron fires when its potential reaches it (>=) */
     const int32_t *reset;      /* [C][N]: potential after a spike; within the P-bit range */
     const int32_t *v_init;     /* [C][N]: initial potential; within the P-bit range */

@@ -15,17 +15,20 @@ __device__ inline unsigned wave_sum(unsigned v)
     return v;
 }
 
-// Potential update shared by every path (GPU-RANC Sec. II, LIF): the exact
-// sum V + I + leak (64-bit) saturates to the potential range once per tick,
-// the neuron fires when the result reaches its threshold and then takes its
-// reset value.
+// Potential update shared by every path (GPU-RANC Sec. II, LIF): the sum
+// V + I + leak saturates to the potential range once per tick, the neuron
+// fires when the result reaches its threshold and then takes its reset value.
+// |I| <= 512 * 256 and |leak| <= 2^30 (checked at load), so I + leak is exact
+// in int32 and one saturating 32-bit add gives clamp(V + I + leak) to the
+// int32 range exactly; clamping that to [vmin, vmax] equals clamping the
+// exact sum to the P-bit range.
 __device__ inline bool lif_update(int32_t v, int32_t in, int32_t leak, int32_t thr, int32_t rst,
                                   int32_t vmin, int32_t vmax, int32_t &v_out)
 {
-    long long u = (long long)v + (long long)in + (long long)leak;
-    u = u < vmin ? (long long)vmin : (u > vmax ? (long long)vmax : u);
-    const bool fire = u >= (long long)thr;
-    v_out = fire ? rst : (int32_t)u;
+    int32_t u = __builtin_elementwise_add_sat(v, in + leak);
+    u = min(max(u, vmin), vmax);
+    const bool fire = u >= thr;
+    v_out = fire ? rst : u;
     return fire;
 }
 

@@ -4,94 +4,199 @@
 // core's scheduler SRAM at the packet's tick offset. Here that write is done
 // from the destination side instead, so that no two lanes ever write the same
 // word and no atomics are needed: the routing table is inverted at load time
-// into, for every (destination core, axon word, delay), the list of source
-// neurons that send there (rt_ptr / rt_src). The lane that owns destination
-// word (core, w) of one sample gathers the spike bits of those sources, ORs
-// them into a 32-bit word per delay d, and ORs each non-zero word into
-// scheduler slot (t + d) % Q, which only it writes. Arrivals at the same
-// (core, axon, tick) therefore merge into one bit (the scheduler SRAM holds
-// booleans, Sec. III-E). The same lane clears slot t % Q, which this tick's
-// integration has already read (the clear of the obsolete row that Sec.
-// III-E does at the start of the next tick).
+// into one list per destination axon word (core, w) of the source neurons that
+// send there, with their delays. The lane that owns (core, w) for a sample
+// gathers the spike bits of those sources into a 32-bit word per delay d and
+// ORs each non-zero word into scheduler slot (t + d) % Q, which only it
+// writes. Arrivals at the same (core, axon, tick) therefore merge into one bit
+// (the scheduler SRAM holds booleans, Sec. III-E). The same lane clears slot
+// t % Q, which this tick's integration has already read (the clear of the
+// obsolete row that Sec. III-E does at the start of the next tick).
 //
-// The sample's current spike bitmap (C*N/32 words) is staged in LDS when it
-// fits, so the gather reads LDS; otherwise it is read from global memory.
+// Layout for the MI355X: the lists are stored wave-interleaved (entry k of the
+// 64 words of a wavefront are 64 consecutive u32), so each table load is one
+// coalesced 256-byte access, and each list is sorted by delay with a count per
+// delay, so a lane gathers every delay's word into its own register. A block
+// serves SB samples at a time with their spike bitmaps staged in LDS, so every
+// table entry fetched from L2 is used SB times. When the bitmaps do not fit in
+// LDS the gather reads them from memory.
 #include "kern_common.h"
 #include "ranc_internal.h"
 
 namespace ranc {
 
-static constexpr int ROUTE_THREADS = 1024;
-static constexpr int ROUTE_LDS_WORDS = 16384;  // 64 KiB
+static constexpr int ROUTE_THREADS = 256;
+static constexpr size_t ROUTE_LDS_BYTES = 128 * 1024;
 
-template <bool STAGE>
+// One destination word (core, w) for SB samples: gather every delay's word in
+// registers (the per-delay loop is unrolled, so accumulators are indexed
+// statically), then OR all non-zero words into their scheduler slots together
+// so their read-modify-writes overlap.
+template <int SB, int DMAX, bool STAGE>
 __global__ __launch_bounds__(ROUTE_THREADS) void k_route(DevNet n, int q_now)
 {
     extern __shared__ uint32_t sp[];
-    const int s = blockIdx.y;
+    const int s_base = blockIdx.y * SB;
+    const int nsb = min(SB, n.S - s_base);
     const size_t words = (size_t)n.C * n.NW;
-    const uint32_t *src = n.spk + (size_t)s * words;
+    const uint32_t *spk = n.spk + (size_t)s_base * words;
     if (STAGE) {
-        for (size_t i = threadIdx.x; i < words; i += blockDim.x)
-            sp[i] = src[i];
+        for (size_t i = threadIdx.x; i < (size_t)nsb * words; i += blockDim.x)
+            sp[i] = spk[i];
         __syncthreads();
     }
+    const uint32_t *bits = STAGE ? sp : spk;
     const int CW = n.C * n.W;
     const size_t slot_stride = (size_t)n.S * CW;
-    uint32_t *ring_s = n.ring + (size_t)s * CW;
+    uint32_t *ring_b = n.ring + (size_t)s_base * CW;
     for (int dw = blockIdx.x * blockDim.x + threadIdx.x; dw < CW; dw += gridDim.x * blockDim.x) {
-        ring_s[(size_t)q_now * slot_stride + dw] = 0u;
-        const uint32_t *p = n.rt_ptr + (size_t)dw * n.D;
-        uint32_t beg = p[0];
-        for (int d = 1; d <= n.D; ++d) {
-            const uint32_t end = p[d];
-            uint32_t acc = 0;
-            for (uint32_t e = beg; e < end; ++e) {
-                const uint32_t ent = n.rt_src[e];
-                const uint32_t g = ent >> 5;
-                const uint32_t wd = STAGE ? sp[g >> 5] : src[g >> 5];
-                acc |= ((wd >> (g & 31u)) & 1u) << (ent & 31u);
+#pragma unroll
+        for (int b = 0; b < SB; ++b)
+            if (b < nsb)
+                ring_b[(size_t)q_now * slot_stride + (size_t)b * CW + dw] = 0u;
+        const uint16_t *dcnt = n.rt_dcnt + (size_t)dw * DMAX;
+        uint32_t cnt[DMAX];
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
+            cnt[d] = dcnt[d];
+        const uint32_t *e = n.rt_ent + n.rt_goff[dw >> 6] + (dw & 63);
+        uint32_t acc[DMAX][SB];
+        uint32_t k0 = 0;
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) {
+#pragma unroll
+            for (int b = 0; b < SB; ++b)
+                acc[d][b] = 0u;
+            const uint32_t kn = k0 + cnt[d];
+#pragma unroll 4
+            for (uint32_t k = k0; k < kn; ++k) {
+                const uint32_t ent = e[(size_t)k * 64];
+                const uint32_t g = ent >> RT_SRC_SHIFT;
+                const uint32_t pos = ent & 31u;
+                const uint32_t wi = g >> 5, bi = g & 31u;
+#pragma unroll
+                for (int b = 0; b < SB; ++b)
+                    if (b < nsb)
+                        acc[d][b] |= ((bits[(size_t)b * words + wi] >> bi) & 1u) << pos;
             }
-            beg = end;
-            if (acc) {
-                int q = q_now + d;
-                if (q >= n.Q)
-                    q -= n.Q;
-                ring_s[(size_t)q * slot_stride + dw] |= acc;
-            }
+            k0 = kn;
+        }
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) {
+            if (d >= n.D)
+                break;
+            int q = q_now + d + 1;
+            if (q >= n.Q)
+                q -= n.Q;
+            uint32_t *dst = ring_b + (size_t)q * slot_stride + dw;
+#pragma unroll
+            for (int b = 0; b < SB; ++b)
+                if (b < nsb && acc[d][b])
+                    dst[(size_t)b * CW] |= acc[d][b];
         }
     }
 }
 
-hipError_t launch_route(const DevNet &n, int q_now, hipStream_t st)
+int route_dmax(int D) { return D <= 4 ? 4 : D <= 8 ? 8 : 16; }
+
+RouteCfg route_default_cfg(const DevNet &n)
 {
+    RouteCfg c;
+    const size_t bitmap = (size_t)n.C * n.NW * 4;
+    const int dmax = route_dmax(n.D);
+    int sb = 1;
+    // two samples per block measured fastest on the 512-core net (1024 samples)
+    while (sb < 8 && bitmap * (size_t)(sb * 2) <= 64 * 1024 && sb * 2 <= n.S && dmax * sb * 2 <= 16)
+        sb *= 2;
+    c.samples_per_block = sb;
+    c.stage = bitmap * (size_t)sb <= 64 * 1024;
+    const int groups = (n.S + sb - 1) / sb;
     const int CW = n.C * n.W;
-    const size_t words = (size_t)n.C * n.NW;
-    if (n.S > 65535)
-        return hipErrorInvalidValue;
-    int per_sample = (CW + ROUTE_THREADS - 1) / ROUTE_THREADS;
-    if (words <= (size_t)ROUTE_LDS_WORDS) {
-        // Every block of a sample stages that sample's bitmap; use several
-        // blocks per sample only while the grid is small.
-        int want = (512 + n.S - 1) / n.S;
-        int bx = want < per_sample ? want : per_sample;
-        if (bx < 1)
-            bx = 1;
-        hipLaunchKernelGGL(k_route<true>, dim3(bx, n.S), dim3(ROUTE_THREADS), words * sizeof(uint32_t),
-                           st, n, q_now);
-    } else {
-        hipLaunchKernelGGL(k_route<false>, dim3(per_sample, n.S), dim3(ROUTE_THREADS), 0, st, n, q_now);
+    const int max_split = (CW + ROUTE_THREADS - 1) / ROUTE_THREADS;
+    int split = (2048 + groups - 1) / groups;
+    if (split > max_split)
+        split = max_split;
+    if (split < 1)
+        split = 1;
+    c.blocks_per_group = split;
+    return c;
+}
+
+template <int SB, int DMAX, bool STAGE>
+static hipError_t launch_route_v(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st)
+{
+    const dim3 grid(cfg.blocks_per_group, (n.S + SB - 1) / SB);
+    const size_t lds = STAGE ? (size_t)n.C * n.NW * 4 * SB : 0;
+    if (lds > 64 * 1024) {
+        static bool raised = false;
+        if (!raised) {
+            hipError_t e = hipFuncSetAttribute((const void *)k_route<SB, DMAX, STAGE>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)ROUTE_LDS_BYTES);
+            if (e != hipSuccess)
+                return e;
+            raised = true;
+        }
     }
+    hipLaunchKernelGGL((k_route<SB, DMAX, STAGE>), grid, dim3(ROUTE_THREADS), lds, st, n, q_now);
     return hipGetLastError();
+}
+
+template <int SB, int DMAX>
+static hipError_t launch_route_sd(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st)
+{
+    // more than 32 accumulators per lane would spill
+    if constexpr (SB * DMAX <= 32)
+        return cfg.stage ? launch_route_v<SB, DMAX, true>(n, q_now, cfg, st)
+                         : launch_route_v<SB, DMAX, false>(n, q_now, cfg, st);
+    else
+        return hipErrorInvalidValue;
+}
+
+template <int SB>
+static hipError_t launch_route_s(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st)
+{
+    switch (route_dmax(n.D)) {
+    case 4: return launch_route_sd<SB, 4>(n, q_now, cfg, st);
+    case 8: return launch_route_sd<SB, 8>(n, q_now, cfg, st);
+    default: return launch_route_sd<SB, 16>(n, q_now, cfg, st);
+    }
+}
+
+hipError_t launch_route(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st)
+{
+    if (cfg.blocks_per_group < 1)
+        return hipErrorInvalidValue;
+    if (cfg.stage && (size_t)n.C * n.NW * 4 * cfg.samples_per_block > ROUTE_LDS_BYTES)
+        return hipErrorInvalidValue;
+    if ((n.S + cfg.samples_per_block - 1) / cfg.samples_per_block > 65535)
+        return hipErrorInvalidValue;
+    switch (cfg.samples_per_block) {
+    case 1: return launch_route_s<1>(n, q_now, cfg, st);
+    case 2: return launch_route_s<2>(n, q_now, cfg, st);
+    case 4: return launch_route_s<4>(n, q_now, cfg, st);
+    case 8: return launch_route_s<8>(n, q_now, cfg, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 __global__ void k_reset_potentials(DevNet n)
 {
-    const size_t total = (size_t)n.C * n.S * n.N;
+    const size_t total = n.vlayout == VLAYOUT_BRICK ? (size_t)n.C * n.S16 * n.N : (size_t)n.C * n.S * n.N;
+    const int NB = n.N / 16;
+    const size_t groups = (size_t)n.S16 / 16;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (size_t)gridDim.x * blockDim.x) {
-        const size_t c = i / ((size_t)n.S * n.N);
-        const size_t j = i % n.N;
+        size_t c, j;
+        if (n.vlayout == VLAYOUT_BRICK) {
+            const size_t lane = (i >> 2) & 63;
+            const size_t brick = i >> 8;              // (c * NB + nb) * groups + g
+            const size_t cnb = brick / groups;
+            c = cnb / NB;
+            j = (cnb % NB) * 16 + (lane & 15);
+        } else {
+            c = i / ((size_t)n.S * n.N);
+            j = i % n.N;
+        }
         n.V[i] = n.vinit[c * n.N + j];
     }
 }
@@ -106,12 +211,18 @@ __global__ void k_fill_u32(uint32_t *p, size_t count)
 hipError_t launch_reset_state(const DevNet &n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reset_potentials, dim3(2048), dim3(256), 0, st, n);
-    const size_t ring_words = (size_t)n.Q * n.S * n.C * n.W;
-    const size_t spk_words = (size_t)n.S * n.C * n.NW;
+    const bool hist = n.vlayout == VLAYOUT_BRICK;
+    const size_t ring_words = hist ? 0 : (size_t)n.Q * n.S * n.C * n.W;
+    const size_t spk_words = hist ? 0 : (size_t)n.S * n.C * n.NW;
+    const size_t hist_words = hist ? (size_t)n.Q * n.C * n.N * (n.S16 / 16) / 2 : 0;
     const size_t raster_words = (size_t)n.RT * n.S * n.Wout;
     const size_t cnt_words = (size_t)n.C * n.S * CNT_N * 2;
-    hipLaunchKernelGGL(k_fill_u32, dim3(2048), dim3(256), 0, st, n.ring, ring_words);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, n.spk, spk_words);
+    if (ring_words)
+        hipLaunchKernelGGL(k_fill_u32, dim3(2048), dim3(256), 0, st, n.ring, ring_words);
+    if (spk_words)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, n.spk, spk_words);
+    if (hist_words)
+        hipLaunchKernelGGL(k_fill_u32, dim3(2048), dim3(256), 0, st, (uint32_t *)n.hist, hist_words);
     if (raster_words)
         hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, n.raster, raster_words);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, (uint32_t *)n.cnt, cnt_words);

@@ -1,25 +1,39 @@
 // ranc_internal.h -- device data layout shared by the host runtime and the kernels.
 //
 // Notation: C cores, A axons and N neurons per core, G axon types,
-// W = A/32 axon words, NW = N/32 neuron words, D = max delay, Q = D + 1
-// scheduler slots, S samples, RT retained raster ticks, Wout output words.
+// W = A/32 axon words, NW = N/32 neuron words, NB = N/16 neuron blocks,
+// D = max delay, Q = D + 1 scheduler slots, S samples (S16: S rounded up to
+// 16), RT retained raster ticks, Wout output words.
 //
 // Parameters (written once at load):
-//   colbits  u32 [C][W][N]     bit b of colbits[c][w][n] = crossbar(c, 32w+b, n)
+//   colbits  u32 [C][W][N]     bit b of colbits[c][w][n] = crossbar(c, 32w+b, n)   (plain path)
 //   typemask u32 [C][G][W]     bit b of typemask[c][g][w] = (type(c, 32w+b) == g)
 //   wts      i32 [C][G][N]     weight of neuron n for axon type g
 //   leak, thr, rst, vinit i32 [C][N]
 //   coremask, outmask u32 [C][NW]  neurons whose destination is a core / the output bus
 //   outword  i32 [C][NW]       raster column of that neuron word, -1 if it has no output neuron
 //   in_index i32 [C]           input slot of the core, -1 if it takes no external input
-//   rt_ptr   u32 [C*W*D + 1]   CSR over (destination core, axon word, delay-1):
-//   rt_src   u32 [E]           (source neuron g = c*N + n) << 5 | (destination axon % 32)
+//   routing table (destination-owned, one list per destination axon word dw = c*W + w),
+//   stored wave-interleaved: words are grouped by 64; group g holds its
+//   words' lists as rt_ent[rt_goff[g] + k*64 + (dw % 64)], each list sorted by
+//   delay; rt_dcnt u16 [C*W][DMAX] counts the entries of each delay
+//   (DMAX = max delay rounded up to 4, 8 or 16). Entry bits: [0,5)
+//   destination axon % 32, [5,9) delay - 1, [9,32) source neuron c*N + n.
 //   deg      i32 [C][A]        connected neurons per axon (synaptic-event counter, MFMA path)
 //   planes   int8 MFMA B operand tiles (MFMA path), see kern_mfma.hip
+//   rtx_ptr  u32 [C*A + 1], rtx_ent u32 [E]  (MFMA path) the same routing table keyed by
+//                              destination axon: entries (source neuron c*N + n) << 4 | (delay - 1)
 // State:
-//   V        i32 [C][S][N]
+//   V        i32, layout by path:
+//              plain: [C][S][N]
+//              MFMA:  [C][NB][S16/16][64][4], element (lane l, r) of brick
+//                     (c, nb, g) = sample 16g + 4(l/16) + r, neuron 16nb + l%16
+//   plain path:
 //   ring     u32 [Q][S][C][W]  scheduler: slot t%Q holds the axon spikes of tick t
 //   spk      u32 [S][C][NW]    spikes of the current tick
+//   MFMA path:
+//   hist     u16 [Q][C*N][S16/16]  spikes of tick t in slot t%Q, bit i of element
+//                              (slot, neuron, g) = sample 16g + i
 //   raster   u32 [RT][S][Wout] output-bus spikes of tick t in row t%RT
 //   cnt      u64 [C][S][5]     emitted, routed, delivered, out, events
 #pragma once
@@ -30,21 +44,29 @@
 namespace ranc {
 
 enum { CNT_EMITTED = 0, CNT_ROUTED, CNT_DELIVERED, CNT_OUT, CNT_EVENTS, CNT_N };
+enum { VLAYOUT_CSN = 0, VLAYOUT_BRICK = 1 };
+
+// Routing entry fields.
+static constexpr int RT_POS_BITS = 5, RT_DELAY_SHIFT = 5, RT_SRC_SHIFT = 9;
+static constexpr long long RT_MAX_NEURONS = 1LL << 23;
 
 struct DevNet {
-    int C, A, N, G, W, NW, D, Q, S, RT, Wout, Cin;
+    int C, A, N, G, W, NW, D, Q, S, S16, RT, Wout, Cin, vlayout;
     int32_t vmin, vmax;
     // parameters
     const uint32_t *colbits, *typemask;
     const int32_t *wts, *leak, *thr, *rst, *vinit;
     const uint32_t *coremask, *outmask;
     const int32_t *outword, *in_index;
-    const uint32_t *rt_ptr, *rt_src;
+    const uint16_t *rt_dcnt;
+    const uint32_t *rt_goff, *rt_ent;
     const int32_t *deg;
     const uint4 *planes;
+    const uint32_t *rtx_ptr, *rtx_ent;
     // state
     int32_t *V;
     uint32_t *ring, *spk, *raster;
+    uint16_t *hist;
     unsigned long long *cnt;
 };
 
@@ -56,12 +78,22 @@ struct TickArgs {
     long long ext_sstride;  // words between consecutive samples of the input block
 };
 
+// Route launch shape (chosen per network by the runtime).
+struct RouteCfg {
+    int samples_per_block;  // 1, 2, 4 or 8 spike bitmaps per block
+    int blocks_per_group;   // blocks sharing one group of samples (split of the destination words)
+    int stage;              // stage the bitmaps in LDS
+};
+
 // Launchers (return the first HIP error, hipSuccess otherwise).
 hipError_t launch_integrate_plain(const DevNet &n, const TickArgs &a, hipStream_t st);
 hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes,
                                  int samples_per_wg, hipStream_t st);
-hipError_t launch_route(const DevNet &n, int q_now, hipStream_t st);
+hipError_t launch_route(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st);
 hipError_t launch_reset_state(const DevNet &n, hipStream_t st);
 bool mfma_shape_supported(int A, int N, int two_planes);
+RouteCfg route_default_cfg(const DevNet &n);
+int route_dmax(int max_delay);
+int mfma_max_samples_per_wg();
 
 }  // namespace ranc

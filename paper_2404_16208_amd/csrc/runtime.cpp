@@ -41,14 +41,15 @@ ranc_status hip_fail(hipError_t e, const char *what)
 
 enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
-    R_ININDEX, R_RTPTR, R_RTSRC, R_DEG, R_PLANES,
+    R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEG, R_PLANES, R_RTXPTR, R_RTXENT,
     R_PARAMS_END,  // everything before this is uploaded once at load
-    R_V = R_PARAMS_END, R_RING, R_SPK, R_RASTER, R_CNT, R_EXT, R_NREG
+    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_EXT, R_NREG
 };
 
 struct Plan {
-    int C, A, N, G, W, NW, D, Q, S, RT, Wout, Cin, path, two, spw;
-    long long E;  // routed (CORE) neurons
+    int C, A, N, G, W, NW, D, Q, S, S16, RT, Wout, Cin, path, two, spw;
+    long long E;         // routed (CORE) neurons
+    long long ell_words; // u32 words of the wave-interleaved routing table
     size_t off[R_NREG], size[R_NREG], params_bytes, total;
 };
 
@@ -86,8 +87,8 @@ ranc_status validate(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t path
         return fail(RANC_ERANGE, "potential_bits must be in [2, 32] (got %d)", d->potential_bits);
     if (d->max_delay < 1 || d->max_delay > 15)
         return fail(RANC_ERANGE, "max_delay must be in [1, 15] (got %d)", d->max_delay);
-    if ((long long)d->num_cores * d->num_neurons >= (1LL << 27))
-        return fail(RANC_EUNSUPPORTED, "num_cores * num_neurons must be < 2^27");
+    if ((long long)d->num_cores * d->num_neurons > RT_MAX_NEURONS)
+        return fail(RANC_EUNSUPPORTED, "num_cores * num_neurons must be <= 2^23");
     if (!d->crossbar || !d->axon_type || !d->weight || !d->leak || !d->threshold || !d->reset ||
         !d->v_init || !d->dest_kind || !d->dest_dx || !d->dest_dy || !d->dest_axon || !d->dest_delay)
         return fail(RANC_EINVAL, "a parameter array pointer is NULL");
@@ -109,6 +110,8 @@ ranc_status validate(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t path
             return fail(RANC_ERANGE, "reset[%zu] = %d outside the potential range", i, d->reset[i]);
         if (d->v_init[i] < vlo || d->v_init[i] > vhi)
             return fail(RANC_ERANGE, "v_init[%zu] = %d outside the potential range", i, d->v_init[i]);
+        if (d->leak[i] < -(1 << 30) || d->leak[i] > (1 << 30))
+            return fail(RANC_ERANGE, "leak[%zu] = %d outside [-2^30, 2^30]", i, d->leak[i]);
         const uint8_t k = d->dest_kind[i];
         if (k > RANC_DEST_OUT)
             return fail(RANC_EINVAL, "dest_kind[%zu] = %u unknown", i, k);
@@ -152,6 +155,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.D = d->max_delay;
     p.Q = p.D + 1;
     p.S = S;
+    p.S16 = (S + 15) / 16 * 16;
     p.RT = RT;
     p.Cin = d->num_input_cores;
     p.two = d->weight_bits > 8;
@@ -167,16 +171,36 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
         int chunks = (1024 + p.C - 1) / p.C;
         chunks = std::max(1, std::min(chunks, tiles));
         const int tiles_per = (tiles + chunks - 1) / chunks;
-        p.spw = 64 * tiles_per;
+        p.spw = std::min(64 * tiles_per, mfma_max_samples_per_wg());
         if (const char *e = getenv("RANC_MFMA_SPW")) {
             const int v = atoi(e);
-            if (v > 0 && v % 64 == 0)
+            if (v > 0 && v % 64 == 0 && v <= mfma_max_samples_per_wg())
                 p.spw = v;
         }
     }
     long long E = 0, wout = 0;
     for (size_t i = 0; i < (size_t)p.C * p.N; ++i)
         E += d->dest_kind[i] == RANC_DEST_CORE;
+    {
+        // wave-interleaved table: every group of 64 destination words is padded
+        // to its longest list
+        const size_t CW = (size_t)p.C * p.W;
+        std::vector<uint32_t> cnt(CW, 0);
+        for (size_t i = 0; i < (size_t)p.C * p.N; ++i)
+            if (d->dest_kind[i] == RANC_DEST_CORE) {
+                const int c = (int)(i / p.N);
+                const int dc = (c % d->grid_w + d->dest_dx[i]) + (c / d->grid_w + d->dest_dy[i]) * d->grid_w;
+                ++cnt[(size_t)dc * p.W + d->dest_axon[i] / 32];
+            }
+        long long words = 0;
+        for (size_t g = 0; g < (CW + 63) / 64; ++g) {
+            uint32_t mx = 0;
+            for (size_t k = g * 64; k < std::min(CW, g * 64 + 64); ++k)
+                mx = std::max(mx, cnt[k]);
+            words += 64LL * mx;
+        }
+        p.ell_words = words;
+    }
     for (int c = 0; c < p.C; ++c)
         for (int w = 0; w < p.NW; ++w) {
             bool any = false;
@@ -194,13 +218,17 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_LEAK] = p.size[R_THR] = p.size[R_RST] = p.size[R_VINIT] = C * N * 4;
     p.size[R_COREMASK] = p.size[R_OUTMASK] = p.size[R_OUTWORD] = C * NW * 4;
     p.size[R_ININDEX] = C * 4;
-    p.size[R_RTPTR] = (C * W * p.D + 1) * 4;
-    p.size[R_RTSRC] = std::max<size_t>((size_t)E, 1) * 4;
+    p.size[R_RTDCNT] = mf ? 0 : (C * W + 63) / 64 * 64 * route_dmax(p.D) * 2;
+    p.size[R_RTGOFF] = mf ? 0 : (C * W + 63) / 64 * 4;
+    p.size[R_RTENT] = mf ? 0 : std::max<size_t>((size_t)p.ell_words, 1) * 4;
+    p.size[R_RTXPTR] = mf ? (C * A + 1) * 4 : 0;
+    p.size[R_RTXENT] = mf ? std::max<size_t>((size_t)E, 1) * 4 : 0;
     p.size[R_DEG] = C * A * 4;
     p.size[R_PLANES] = mf ? C * A * N * (p.two ? 2 : 1) : 0;
-    p.size[R_V] = C * S * N * 4;
-    p.size[R_RING] = (size_t)p.Q * S * C * W * 4;
-    p.size[R_SPK] = (size_t)S * C * NW * 4;
+    p.size[R_V] = C * (mf ? (size_t)p.S16 : (size_t)S) * N * 4;
+    p.size[R_RING] = mf ? 0 : (size_t)p.Q * S * C * W * 4;
+    p.size[R_SPK] = mf ? 0 : (size_t)S * C * NW * 4;
+    p.size[R_HIST] = mf ? (size_t)p.Q * C * N * (p.S16 / 16) * 2 : 0;
     p.size[R_RASTER] = (size_t)RT * S * p.Wout * 4;
     p.size[R_CNT] = C * S * CNT_N * 8;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
@@ -269,25 +297,60 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
         inidx[c] = -1;
     for (int i = 0; i < p.Cin; ++i)
         inidx[d->input_cores[i]] = i;
-    // Inverted routing table: bucket key = (dest core * W + dest word) * D + delay - 1.
-    uint32_t *ptr = (uint32_t *)at(R_RTPTR), *src = (uint32_t *)at(R_RTSRC);
-    const size_t keys = (size_t)C * W * p.D;
-    std::vector<uint32_t> fill(keys + 1, 0);
-    auto key_of = [&](size_t i, int c) -> size_t {
-        const int dc = (c % d->grid_w + d->dest_dx[i]) + (c / d->grid_w + d->dest_dy[i]) * d->grid_w;
-        return ((size_t)dc * W + d->dest_axon[i] / 32) * p.D + (d->dest_delay[i] - 1);
-    };
-    for (size_t i = 0; i < (size_t)C * N; ++i)
-        if (d->dest_kind[i] == RANC_DEST_CORE)
-            ++fill[key_of(i, (int)(i / N)) + 1];
-    for (size_t k = 0; k < keys; ++k)
-        fill[k + 1] += fill[k];
-    memcpy(ptr, fill.data(), (keys + 1) * 4);
-    for (size_t i = 0; i < (size_t)C * N; ++i)
-        if (d->dest_kind[i] == RANC_DEST_CORE) {
-            const size_t k = key_of(i, (int)(i / N));
-            src[fill[k]++] = ((uint32_t)i << 5) | (d->dest_axon[i] % 32u);
+    // Inverted routing table, one list per destination axon word, sorted by
+    // delay, stored wave-interleaved (see ranc_internal.h).
+    if (p.size[R_RTENT]) {
+        const size_t CW = (size_t)C * W;
+        std::vector<std::vector<uint32_t>> lists(CW);
+        for (size_t i = 0; i < (size_t)C * N; ++i)
+            if (d->dest_kind[i] == RANC_DEST_CORE) {
+                const int c = (int)(i / N);
+                const int dc = (c % d->grid_w + d->dest_dx[i]) + (c / d->grid_w + d->dest_dy[i]) * d->grid_w;
+                const uint32_t ent = ((uint32_t)i << RT_SRC_SHIFT) |
+                                     ((uint32_t)(d->dest_delay[i] - 1) << RT_DELAY_SHIFT) | (d->dest_axon[i] % 32u);
+                lists[(size_t)dc * W + d->dest_axon[i] / 32].push_back(ent);
+            }
+        const int dmax = route_dmax(p.D);
+        uint16_t *dcnt = (uint16_t *)at(R_RTDCNT);
+        uint32_t *goff = (uint32_t *)at(R_RTGOFF), *ent = (uint32_t *)at(R_RTENT);
+        size_t off = 0;
+        for (size_t g = 0; g < (CW + 63) / 64; ++g) {
+            size_t mx = 0;
+            for (size_t k = g * 64; k < std::min(CW, g * 64 + 64); ++k) {
+                auto &L = lists[k];
+                std::stable_sort(L.begin(), L.end(), [](uint32_t a, uint32_t b) {
+                    return ((a >> RT_DELAY_SHIFT) & 15u) < ((b >> RT_DELAY_SHIFT) & 15u);
+                });
+                for (uint32_t x : L)
+                    ++dcnt[k * dmax + ((x >> RT_DELAY_SHIFT) & 15u)];
+                mx = std::max(mx, L.size());
+                for (size_t e = 0; e < L.size(); ++e)
+                    ent[off + e * 64 + (k - g * 64)] = L[e];
+            }
+            goff[g] = (uint32_t)off;
+            off += 64 * mx;
         }
+    }
+    // MFMA path: the inverted table keyed by destination axon (CSR).
+    if (p.size[R_RTXPTR]) {
+        uint32_t *ptr = (uint32_t *)at(R_RTXPTR), *ent = (uint32_t *)at(R_RTXENT);
+        const size_t CA = (size_t)C * A;
+        std::vector<uint32_t> fill(CA + 1, 0);
+        auto dest_of = [&](size_t i) -> size_t {
+            const int c = (int)(i / N);
+            const int dc = (c % d->grid_w + d->dest_dx[i]) + (c / d->grid_w + d->dest_dy[i]) * d->grid_w;
+            return (size_t)dc * A + d->dest_axon[i];
+        };
+        for (size_t i = 0; i < (size_t)C * N; ++i)
+            if (d->dest_kind[i] == RANC_DEST_CORE)
+                ++fill[dest_of(i) + 1];
+        for (size_t k = 0; k < CA; ++k)
+            fill[k + 1] += fill[k];
+        memcpy(ptr, fill.data(), (CA + 1) * 4);
+        for (size_t i = 0; i < (size_t)C * N; ++i)
+            if (d->dest_kind[i] == RANC_DEST_CORE)
+                ent[fill[dest_of(i)]++] = ((uint32_t)i << 4) | (uint32_t)(d->dest_delay[i] - 1);
+    }
     int32_t *deg = (int32_t *)at(R_DEG);
     for (int c = 0; c < C; ++c)
         for (int a = 0; a < A; ++a) {
@@ -339,6 +402,7 @@ struct Profiler {
 
 struct ranc_net {
     Plan p;
+    RouteCfg rcfg;
     Profiler prof;
     DevNet dn;
     uint8_t *ws;
@@ -347,6 +411,8 @@ struct ranc_net {
     uint64_t version, raster_version;
     std::vector<int> out_words;        // (core, word) pairs of raster columns
     std::vector<uint32_t> raster_host; // mirror of the raster
+    uint64_t v_version = 0;
+    std::vector<int32_t> v_host;       // mirror of the potentials (brick layout only)
 };
 
 static hipError_t prof_begin(ranc_net *net, int kind, hipStream_t s, int *slot)
@@ -434,7 +500,8 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     auto reg = [&](Region r) -> uint8_t * { return net->ws + p.off[r]; };
     DevNet &n = net->dn;
     n.C = p.C; n.A = p.A; n.N = p.N; n.G = p.G; n.W = p.W; n.NW = p.NW; n.D = p.D; n.Q = p.Q;
-    n.S = p.S; n.RT = p.RT; n.Wout = p.Wout; n.Cin = p.Cin;
+    n.S = p.S; n.S16 = p.S16; n.RT = p.RT; n.Wout = p.Wout; n.Cin = p.Cin;
+    n.vlayout = p.path == RANC_PATH_MFMA ? VLAYOUT_BRICK : VLAYOUT_CSN;
     n.vmin = (int32_t)(-(1LL << (desc->potential_bits - 1)));
     n.vmax = (int32_t)((1LL << (desc->potential_bits - 1)) - 1);
     n.colbits = (const uint32_t *)reg(R_COLBITS);
@@ -448,13 +515,17 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.outmask = (const uint32_t *)reg(R_OUTMASK);
     n.outword = (const int32_t *)reg(R_OUTWORD);
     n.in_index = (const int32_t *)reg(R_ININDEX);
-    n.rt_ptr = (const uint32_t *)reg(R_RTPTR);
-    n.rt_src = (const uint32_t *)reg(R_RTSRC);
+    n.rt_dcnt = (const uint16_t *)reg(R_RTDCNT);
+    n.rt_goff = (const uint32_t *)reg(R_RTGOFF);
+    n.rt_ent = (const uint32_t *)reg(R_RTENT);
     n.deg = (const int32_t *)reg(R_DEG);
     n.planes = (const uint4 *)reg(R_PLANES);
     n.V = (int32_t *)reg(R_V);
     n.ring = (uint32_t *)reg(R_RING);
     n.spk = (uint32_t *)reg(R_SPK);
+    n.hist = (uint16_t *)reg(R_HIST);
+    n.rtx_ptr = (const uint32_t *)reg(R_RTXPTR);
+    n.rtx_ent = (const uint32_t *)reg(R_RTXENT);
     n.raster = (uint32_t *)reg(R_RASTER);
     n.cnt = (unsigned long long *)reg(R_CNT);
     std::vector<uint8_t> host;
@@ -469,6 +540,21 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
         delete net;
         return hip_fail(e, "uploading the network");
     }
+    net->rcfg = route_default_cfg(n);
+    if (const char *e = getenv("RANC_ROUTE_SB")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8)
+            net->rcfg.samples_per_block = v;
+    }
+    if (const char *e = getenv("RANC_ROUTE_SPLIT")) {
+        const int v = atoi(e);
+        if (v >= 1)
+            net->rcfg.blocks_per_group = v;
+    }
+    if (const char *e = getenv("RANC_ROUTE_STAGE"))
+        net->rcfg.stage = atoi(e) != 0;
+    if ((size_t)n.C * n.NW * 4 * net->rcfg.samples_per_block > 128 * 1024)
+        net->rcfg.stage = 0;
     net->last_stream = s;
     net->tick = 0;
     net->version = 1;
@@ -529,13 +615,18 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
                 e = prof_end(net, slot, s);
             if (e != hipSuccess)
                 return hip_fail(e, "launching integration");
-            e = prof_begin(net, 1, s, &slot);
-            if (e == hipSuccess)
-                e = launch_route(net->dn, ta.q_now, s);
-            if (e == hipSuccess)
-                e = prof_end(net, slot, s);
-            if (e != hipSuccess)
-                return hip_fail(e, "launching routing");
+            // The MFMA path delivers spikes inside the next tick's integration
+            // (spike history gathered by destination); the plain path routes
+            // into the scheduler ring here.
+            if (p.path != RANC_PATH_MFMA) {
+                e = prof_begin(net, 1, s, &slot);
+                if (e == hipSuccess)
+                    e = launch_route(net->dn, ta.q_now, net->rcfg, s);
+                if (e == hipSuccess)
+                    e = prof_end(net, slot, s);
+                if (e != hipSuccess)
+                    return hip_fail(e, "launching routing");
+            }
             ++net->tick;
         }
         net->last_stream = s;
@@ -610,10 +701,29 @@ ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out)
     ranc_status st = sync_net(net);
     if (st != RANC_OK)
         return st;
-    hipError_t e = hipMemcpy2D(out, (size_t)p.N * 4, net->dn.V + (size_t)sample * p.N, (size_t)p.S * p.N * 4,
-                               (size_t)p.N * 4, p.C, hipMemcpyDeviceToHost);
-    if (e != hipSuccess)
-        return hip_fail(e, "reading potentials");
+    if (net->dn.vlayout == VLAYOUT_CSN) {
+        hipError_t e = hipMemcpy2D(out, (size_t)p.N * 4, net->dn.V + (size_t)sample * p.N, (size_t)p.S * p.N * 4,
+                                   (size_t)p.N * 4, p.C, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return hip_fail(e, "reading potentials");
+        return RANC_OK;
+    }
+    // brick layout: mirror once per state version, then gather on the host
+    if (net->v_version != net->version) {
+        net->v_host.resize((size_t)p.C * p.S16 * p.N);
+        hipError_t e = hipMemcpy(net->v_host.data(), net->dn.V, net->v_host.size() * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return hip_fail(e, "reading potentials");
+        net->v_version = net->version;
+    }
+    const int NB = p.N / 16;
+    const size_t groups = (size_t)p.S16 / 16;
+    const int g = sample / 16, i = sample % 16, g4 = i / 4, r = i % 4;
+    for (int c = 0; c < p.C; ++c)
+        for (int nb = 0; nb < NB; ++nb)
+            for (int jj = 0; jj < 16; ++jj)
+                out[(size_t)c * p.N + nb * 16 + jj] =
+                    net->v_host[((((size_t)c * NB + nb) * groups + g) * 64 + g4 * 16 + jj) * 4 + r];
     return RANC_OK;
 }
 

@@ -107,6 +107,8 @@ def _first_core_neuron(net):
     ("dest_kind", "RANC_EINVAL", "dest_kind"),
     ("input_dup", "RANC_EINVAL", "twice"),
     ("input_range", "RANC_ERANGE", "input_cores"),
+    ("leak_high", "RANC_ERANGE", "leak"),
+    ("leak_low", "RANC_ERANGE", "leak"),
 ])
 def test_value_rejections(R, case, status, needle):
     net = base_net()
@@ -139,6 +141,10 @@ def test_value_rejections(R, case, status, needle):
         net.input_cores = np.array([1, 1], np.int32)
     elif case == "input_range":
         net.input_cores = np.array([4], np.int32)
+    elif case == "leak_high":
+        net.leak[3, 3] = (1 << 30) + 1
+    elif case == "leak_low":
+        net.leak[3, 3] = -(1 << 30) - 1
     st, msg, _ = ws_status(R, net)
     assert R.STATUS_NAMES[st] == status and needle in msg, (st, msg)
 
@@ -149,6 +155,8 @@ def test_boundary_values_accepted(R):
     net.weight[0, 0, 1] = 255
     c, n = _first_core_neuron(net)
     net.dest_delay[c, n] = 3            # = max_delay
+    net.leak[0, 0] = 1 << 30
+    net.leak[0, 1] = -(1 << 30)
     st, msg, _ = ws_status(R, net)
     assert st == R.RANC_OK, msg
 

@@ -165,3 +165,25 @@ def test_mnist512_batched_1024_samples():
         assert np.array_equal(gp.potentials(s), gm.potentials(s)), s
         assert np.array_equal(gp.spikes(s), gm.spikes(s)), s
         assert gp.counters(s) == gm.counters(s), s
+
+
+# ----------------------------------------------------------- saturation edges
+
+@pytest.mark.parametrize("path", ["plain", "mfma"])
+@pytest.mark.parametrize("pbits", [32, 2, 7])
+def test_saturation_extremes(path, pbits):
+    """Potentials at the ends of the P-bit range, leaks at +-2^30, thresholds
+    at the int32 limits: the exact int64 oracle against the saturating 32-bit
+    update of the kernels."""
+    net = W.random_net(80 + pbits, 4, 64, 64, 2, weight_bits=9, potential_bits=pbits, max_delay=2, grid_w=2,
+                       density=0.5, p_core=0.5, p_out=0.5, input_cores=[0, 1, 2, 3], config_id=704)
+    r = np.random.default_rng(pbits)
+    lo, hi = -(1 << (pbits - 1)), (1 << (pbits - 1)) - 1
+    shape = net.v_init.shape
+    net.v_init[:] = r.choice(np.array([lo, hi, lo + 1, hi - 1, 0], np.int64), size=shape)
+    net.reset[:] = r.choice(np.array([lo, hi, 0], np.int64), size=shape)
+    net.leak[:] = r.choice(np.array([-(1 << 30), 1 << 30, -1, 1, 0, hi, lo], np.int64)
+                           .clip(-(1 << 30), 1 << 30), size=shape)
+    net.threshold[:] = r.choice(np.array([2**31 - 1, -2**31, hi, lo, 0, 100], np.int64), size=shape)
+    x = W.bernoulli_inputs(14, net, 70, 12, 0.4, config_id=704)
+    assert_parity(net, x, 12, path, what=f"saturation_P{pbits}")
