@@ -412,7 +412,9 @@ struct ranc_net {
     std::vector<int> out_words;        // (core, word) pairs of raster columns
     std::vector<uint32_t> raster_host; // mirror of the raster
     uint64_t v_version = 0;
-    std::vector<int32_t> v_host;       // mirror of the potentials (brick layout only)
+    std::vector<int32_t> v_host;       // mirror of the potentials
+    uint64_t cnt_version = 0;
+    std::vector<unsigned long long> cnt_host; // mirror of the counters
 };
 
 static hipError_t prof_begin(ranc_net *net, int kind, hipStream_t s, int *slot)
@@ -643,6 +645,23 @@ static ranc_status sync_net(ranc_net *net)
     return RANC_OK;
 }
 
+// Whole-buffer host mirrors, refreshed once per state version: reading many
+// samples costs one device-to-host copy.
+static ranc_status refresh_mirror(ranc_net *net, const void *src, size_t bytes, void *dst, uint64_t &version,
+                                  const char *what)
+{
+    if (version == net->version)
+        return RANC_OK;
+    ranc_status st = sync_net(net);
+    if (st != RANC_OK)
+        return st;
+    hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_fail(e, what);
+    version = net->version;
+    return RANC_OK;
+}
+
 ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, int64_t tick_end, ranc_spike *out,
                              int64_t capacity, int64_t *count)
 {
@@ -655,19 +674,11 @@ ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, 
     if (tick_begin < lo || tick_end > net->tick || tick_begin > tick_end)
         return fail(RANC_ESTATE, "ticks [%lld, %lld) outside the retained window [%lld, %lld)",
                     (long long)tick_begin, (long long)tick_end, (long long)lo, (long long)net->tick);
-    ranc_status st = sync_net(net);
+    net->raster_host.resize((size_t)p.RT * p.S * p.Wout);
+    ranc_status st = refresh_mirror(net, net->dn.raster, net->raster_host.size() * 4, net->raster_host.data(),
+                                    net->raster_version, "reading the raster");
     if (st != RANC_OK)
         return st;
-    if (net->raster_version != net->version) {
-        net->raster_host.resize((size_t)p.RT * p.S * p.Wout);
-        if (!net->raster_host.empty()) {
-            hipError_t e = hipMemcpy(net->raster_host.data(), net->dn.raster, net->raster_host.size() * 4,
-                                     hipMemcpyDeviceToHost);
-            if (e != hipSuccess)
-                return hip_fail(e, "reading the raster");
-        }
-        net->raster_version = net->version;
-    }
     int64_t k = 0;
     for (int64_t t = tick_begin; t < tick_end; ++t) {
         const uint32_t *row = net->raster_host.data() + ((size_t)(t % p.RT) * p.S + sample) * p.Wout;
@@ -698,23 +709,16 @@ ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out)
     const Plan &p = net->p;
     if (sample < 0 || sample >= p.S)
         return fail(RANC_EINVAL, "sample %d out of range", sample);
-    ranc_status st = sync_net(net);
+    const bool brick = net->dn.vlayout == VLAYOUT_BRICK;
+    net->v_host.resize((size_t)p.C * (brick ? p.S16 : p.S) * p.N);
+    ranc_status st = refresh_mirror(net, net->dn.V, net->v_host.size() * 4, net->v_host.data(), net->v_version,
+                                    "reading potentials");
     if (st != RANC_OK)
         return st;
-    if (net->dn.vlayout == VLAYOUT_CSN) {
-        hipError_t e = hipMemcpy2D(out, (size_t)p.N * 4, net->dn.V + (size_t)sample * p.N, (size_t)p.S * p.N * 4,
-                                   (size_t)p.N * 4, p.C, hipMemcpyDeviceToHost);
-        if (e != hipSuccess)
-            return hip_fail(e, "reading potentials");
+    if (!brick) {
+        for (int c = 0; c < p.C; ++c)
+            memcpy(out + (size_t)c * p.N, net->v_host.data() + ((size_t)c * p.S + sample) * p.N, (size_t)p.N * 4);
         return RANC_OK;
-    }
-    // brick layout: mirror once per state version, then gather on the host
-    if (net->v_version != net->version) {
-        net->v_host.resize((size_t)p.C * p.S16 * p.N);
-        hipError_t e = hipMemcpy(net->v_host.data(), net->dn.V, net->v_host.size() * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess)
-            return hip_fail(e, "reading potentials");
-        net->v_version = net->version;
     }
     const int NB = p.N / 16;
     const size_t groups = (size_t)p.S16 / 16;
@@ -734,18 +738,15 @@ ranc_status ranc_read_counters(ranc_net *net, int32_t sample, ranc_counters *out
     const Plan &p = net->p;
     if (sample < 0 || sample >= p.S)
         return fail(RANC_EINVAL, "sample %d out of range", sample);
-    ranc_status st = sync_net(net);
+    net->cnt_host.resize((size_t)p.C * p.S * CNT_N);
+    ranc_status st = refresh_mirror(net, net->dn.cnt, net->cnt_host.size() * 8, net->cnt_host.data(),
+                                    net->cnt_version, "reading counters");
     if (st != RANC_OK)
         return st;
-    std::vector<unsigned long long> buf((size_t)p.C * CNT_N);
-    hipError_t e = hipMemcpy2D(buf.data(), CNT_N * 8, net->dn.cnt + (size_t)sample * CNT_N, (size_t)p.S * CNT_N * 8,
-                               CNT_N * 8, p.C, hipMemcpyDeviceToHost);
-    if (e != hipSuccess)
-        return hip_fail(e, "reading counters");
     unsigned long long sum[CNT_N] = {0, 0, 0, 0, 0};
     for (int c = 0; c < p.C; ++c)
         for (int k = 0; k < CNT_N; ++k)
-            sum[k] += buf[(size_t)c * CNT_N + k];
+            sum[k] += net->cnt_host[((size_t)c * p.S + sample) * CNT_N + k];
     out->emitted = sum[CNT_EMITTED];
     out->routed = sum[CNT_ROUTED];
     out->delivered = sum[CNT_DELIVERED];
