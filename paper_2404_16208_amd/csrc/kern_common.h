@@ -15,6 +15,25 @@ __device__ inline unsigned wave_sum(unsigned v)
     return v;
 }
 
+// Workgroup barrier that orders LDS only: wait for this wave's LDS accesses,
+// then s_barrier. __syncthreads() (and an LDS-scoped fence, which also covers
+// global-to-LDS DMA) makes every wave wait for all of its outstanding global
+// loads, including prefetches meant to stay in flight across the barrier.
+// Kernels whose waves exchange data only through ordinary LDS accesses use
+// this; the "memory" clobber keeps the compiler from moving memory accesses
+// across it. A wave reading its own global-to-LDS DMA data waits for it
+// separately (s_waitcnt vmcnt).
+__device__ inline void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Compiler-only barrier: keeps issued memory operations where they are.
+__device__ inline void compiler_fence()
+{
+    asm volatile("" ::: "memory");
+}
+
 // Potential update shared by every path (GPU-RANC Sec. II, LIF): the sum
 // V + I + leak saturates to the potential range once per tick, the neuron
 // fires when the result reaches its threshold and then takes its reset value.

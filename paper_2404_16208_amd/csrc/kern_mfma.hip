@@ -6,91 +6,140 @@
 // Sec. II: sum over spiking connected axons of the neuron's weight for the
 // axon's type) is the dense product X[samples x A] * B[A x N] with X the 0/1
 // axon spikes and B[a][n] = crossbar(a, n) * weight(n, type(a)). It runs on
-// V_MFMA_I32_16X16X64_I8 with int32 accumulation, which is exact:
+// V_MFMA_I32_32X32X32_I8 with int32 accumulation, which is exact:
 //   - weights of up to 8 bits are int8 as they are (one B plane);
 //   - 9-bit weights w in [-256, 255] are split as w = 128*hi + lo with
-//     lo = w & 127 in [0, 127] and hi = w >> 7 in [-2, 1]. The hi term is
-//     formed as (-128 * x) * (-hi): the spike byte shifted left by 7 is the
-//     int8 value -128, and -hi lies in [-1, 2], so both planes accumulate into
-//     the same int32 register and no rescaling pass is needed.
-//   |sum| <= 512 * 256 < 2^31, so int32 never overflows.
+//     hi = w >> 7 in [-2, 1] and lo = w & 127 in [0, 127]; the two planes
+//     accumulate separately and combine as lo + 128*hi;
+//   |sum| <= 512 * 256 < 2^31, so int32 never overflows. The lo accumulator
+//   starts at the neuron's leak, so the products give I + leak directly.
 //
 // Scheduler. A spike fired at tick t by neuron g with destination
 // (core, axon, delay d) must reach that axon at tick t + d (Sec. III-D/E;
 // several spikes to one (core, axon, tick) merge into one bit). On this path
 // the scheduler holds the last Q = D + 1 ticks of every neuron's spikes,
-// sample-sliced (one u16 = 16 samples of one neuron), and delivery is done by
+// sample-sliced (one u64 = 64 samples of one neuron), and delivery is done by
 // the destination: at tick t the workgroup of a core ORs, for each of its
 // axons, the history bits of its sources at tick t - d. Every scheduler word
-// has exactly one writer (the firing neuron's workgroup, at tick t, slot
-// t % Q) and no atomics are used. A 64-lane ballot turns the per-axon sample
-// bits back into per-sample axon words.
+// has exactly one writer (the firing neuron's wavefront, at tick t, slot
+// t % Q) and no atomics are used.
 //
-// Mapping: one workgroup of 16 wavefronts per (core, chunk of samples); the
-// core's B tiles stay in VGPRs for the whole chunk (A*N*planes/4096 VGPRs per
-// lane). Samples are taken 64 at a time in a software pipeline:
-//   - history bits of tile i+2 are loaded and those of tile i+1 transposed
-//     into LDS while tile i runs, so no load latency sits on the critical path;
-//   - the axon spikes of tile i (delivered OR external input) are expanded to
-//     an int8 [64 x A] tile in LDS, double-buffered so one barrier per tile
-//     suffices; delivered spikes and synaptic events (sum over spiking axons
-//     of their connected-neuron counts) are reduced per sample in the same pass;
-//   - each wavefront loads its potentials as one 16-byte vector per lane (V is
-//     stored in "bricks" matching the MFMA result layout, so a wave's load is
-//     a contiguous 1 KiB), multiplies its 16-sample sub-tiles against its
-//     16-neuron block and applies leak / threshold / reset in the epilogue,
-//     which also writes this tick's spikes to the history, the output raster
-//     and per-sample counters (accumulated in LDS, written once per chunk).
+// Mapping: one workgroup of 8 wavefronts per (core, chunk of samples); wave w
+// owns the 32 neurons of block w % (N/32), whose B tiles stay in VGPRs for
+// the whole chunk (A*planes/8 VGPRs per lane). Samples go 64 at a time
+// (two 32-sample sub-tiles) through a software pipeline:
+//   - the potentials of tile i+1 travel from HBM straight into LDS
+//     (global_load_lds) while tile i is processed; history bits of tile i+2
+//     are loaded and those of tile i+1 transposed into LDS meanwhile;
+//   - the axon spikes of tile i (delivered OR external input) are expanded,
+//     one lane per sample, to an int8 [64 x A] tile in LDS, double-buffered
+//     so one barrier per tile suffices; delivered spikes and synaptic events
+//     (sum over spiking axons of their connected-neuron counts, by dot4) are
+//     counted in the same pass;
+//   - products, potential update, and the neuron's 32-sample spike word
+//     (16 bits per lane, two lanes combined); a 32 x 32 bit transpose of the
+//     wave's spike words gives each sample's spike word, whose popcounts are
+//     the per-sample spike counters;
+//   - the results of tile i (potentials, spike history and raster words,
+//     counter updates in LDS) are written at the top of iteration i+1, so the
+//     stores have a whole iteration to drain before the next wait.
+// Waves exchange data only through LDS, so barriers order LDS alone
+// (lds_barrier); the single wait for vector memory per iteration is explicit.
 //
 // MFMA operand convention used for both A and B: in k-step k, lane l holds 16
-// bytes for row/column l % 16 and axons 64k + 16*(l/16) + [0, 16). The sum
-// over k does not depend on which hardware k each byte stands for as long as
-// A and B agree. Result: lane l, element r is row 4*(l/16) + r, column l % 16.
+// bytes for row/column l % 32 and axons 32k + 16*(l/32) + [0, 16). Result:
+// lane l, element r is row 8*(r/4) + 4*(l/32) + r%4, column l % 32. Bit
+// p = r + 16*(l/32) of a neuron's 32-sample spike word is therefore sample
+// sigma(p) = 8*((p%16)/4) + 4*(p/16) + p%4 of the 32-sample group.
 #include "kern_common.h"
 #include "ranc_internal.h"
 
 namespace ranc {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
-static constexpr int MFMA_TS = 64;        // samples per LDS tile
-static constexpr int MFMA_SPW_MAX = 1024; // samples per workgroup (LDS counters)
+static constexpr int MFMA_TS = 64;        // samples per tile
+static constexpr int MFMA_SPW_MAX = 512;  // samples per workgroup (LDS counters)
+
+// s_waitcnt immediates (gfx9 encoding: vmcnt in [3:0] and [15:14], expcnt in
+// [6:4], lgkmcnt in [11:8]): wait for all vector-memory operations / all LDS
+// operations of this wave.
+static constexpr int WAIT_VMCNT0 = 0x0F70;
+static constexpr int WAIT_LGKMCNT0 = 0xC07F;
+
+typedef __attribute__((address_space(3))) void lds_void;
 
 int mfma_max_samples_per_wg() { return MFMA_SPW_MAX; }
 
-template <int A_, int N_, bool TWO>
-__global__ __launch_bounds__(1024) void k_integrate_mfma(DevNet n, TickArgs ta, int spw)
+// sample (within its 32-sample group) of bit b of a spike word
+__device__ inline int sigma32(int b) { return 8 * ((b & 15) >> 2) + 4 * (b >> 4) + (b & 3); }
+
+// One stage of a recursive bit-matrix transpose: lanes whose index has bit K
+// clear exchange the bits with index bit K set for their partner's (lane ^ K)
+// bits with index bit K clear.
+template <int K>
+__device__ inline uint32_t transpose_stage(uint32_t x, int lane)
 {
-    constexpr int NB = N_ / 16;                     // 16-neuron blocks (<= 16)
-    constexpr int KS = A_ / 64;                     // 64-axon k-steps
-    constexpr int PL = TWO ? 2 : 1;                 // B planes
-    constexpr int WPB = 16 / NB;                    // waves sharing a neuron block
-    constexpr int STW = 4 / WPB;                    // 16-sample sub-tiles per wave per tile
-    constexpr int W_ = A_ / 32;
-    constexpr int NW_ = N_ / 32;
-    constexpr int ROWB = A_ + 16;                   // padded LDS row (bytes)
-    constexpr int QD = A_ / 4;                      // axon dwords per sample row
-    constexpr int QPL = (QD + 63) / 64;             // axon dwords per lane in the expansion
-    constexpr unsigned EV_BITS = 18;                // events per (sample, core) <= 512*256 < 2^18
-    constexpr int APW = A_ / 64;                    // 64-axon blocks
-    constexpr int PARTS = 16 / APW;                 // sample parts in the history gather
-    constexpr int SPT = MFMA_TS / PARTS;            // samples per gathering lane (4..32)
+    constexpr uint32_t M = K == 16 ? 0x0000FFFFu : K == 8 ? 0x00FF00FFu : K == 4 ? 0x0F0F0F0Fu
+                         : K == 2  ? 0x33333333u : 0x55555555u;
+    // ds_swizzle bit-mask mode: partner = lane ^ K within each 32-lane half
+    const uint32_t p = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1F | (K << 10));
+    const bool up = (lane & K) != 0;
+    const uint32_t r = __builtin_rotateright32(p, up ? K : 32 - K);
+    const uint32_t keep = up ? ~M : M;
+    return (x & keep) | (r & ~keep);
+}
+
+// 32 x 32 bit transpose within each half-wave: lane i of a half receives, as
+// bit j, bit i of lane j of the same half. Every lane must be active.
+__device__ inline uint32_t transpose32(uint32_t x, int lane)
+{
+    x = transpose_stage<16>(x, lane);
+    x = transpose_stage<8>(x, lane);
+    x = transpose_stage<4>(x, lane);
+    x = transpose_stage<2>(x, lane);
+    return transpose_stage<1>(x, lane);
+}
+
+template <bool WIDE> struct RawWord { typedef uint32_t type; };
+template <> struct RawWord<true> { typedef uint64_t type; };
+
+template <int A_, int N_, bool TWO>
+__global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, int spw)
+{
+    constexpr int NB = N_ / 32;          // 32-neuron blocks (4 or 8)
+    constexpr int KS = A_ / 32;          // 32-axon k-steps
+    constexpr int PL = TWO ? 2 : 1;      // B planes
+    constexpr int STW = NB / 4;          // 32-sample sub-tiles per wave per tile
+    constexpr int W_ = A_ / 32;          // axon words
+    constexpr int ROWB = A_ + 16;        // padded LDS row of the int8 tile (bytes)
+    constexpr int WPW = (W_ + 7) / 8;    // axon words expanded per wave
+    constexpr int APW = A_ / 64;         // 64-axon blocks of the gather
+    constexpr int GPW = APW == 8 ? 2 : 1;  // 32-sample groups gathered per wave
+    typedef typename RawWord<GPW == 2>::type RawT;
+    static_assert(NB == 4 || NB == 8, "N must be 128 or 256");
 
     __shared__ __attribute__((aligned(16))) int8_t a_lds[2][MFMA_TS * ROWB];
-    __shared__ uint32_t x_lds[2][MFMA_TS][W_];      // delivered axon spikes of a tile
-    __shared__ unsigned s_cnt[5][MFMA_SPW_MAX];     // emitted, routed, out, delivered, events
+    __shared__ __attribute__((aligned(16))) v4i v_lds[8][STW][4][64];   // next tile's potentials, per wave
+    __shared__ uint32_t x_lds[2][MFMA_TS][W_ + 1];                     // delivered axon words per sample
+    // per sample of the chunk: [0] emitted | routed << 10 | out << 20 (each
+    // <= N per tick), [1] events | delivered << 18 (<= 512*256 and <= 512)
+    __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int c = blockIdx.x % n.C;
     const int chunk = blockIdx.x / n.C;
     const int s_begin = chunk * spw;
     const int s_end = min(n.S, s_begin + spw);
-    const int s_end16 = min(n.S16, s_begin + spw);
-    const int g4 = lane >> 4, jj = lane & 15;
+    const int h = lane >> 5, jj = lane & 31;
+    const int sig = sigma32(jj);
     const int nb = wave % NB;
     const int stg = wave / NB;
+    const int neuron = nb * 32 + jj;
 
-    for (int i = threadIdx.x; i < 5 * MFMA_SPW_MAX; i += blockDim.x)
+    for (int i = threadIdx.x; i < 2 * MFMA_SPW_MAX; i += blockDim.x)
         (&s_cnt[0][0])[i] = 0u;
 
     // B tiles of this wave's neuron block, resident for the whole chunk.
@@ -101,232 +150,332 @@ __global__ __launch_bounds__(1024) void k_integrate_mfma(DevNet n, TickArgs ta, 
 #pragma unroll
         for (int p = 0; p < PL; ++p)
             breg[k][p] = planes[((((size_t)c * NB + nb) * KS + k) * PL + p) * 64 + lane];
-    const size_t cj = (size_t)c * N_ + nb * 16 + jj;
+    const size_t cj = (size_t)c * N_ + neuron;
     const int32_t lk = n.leak[cj], th = n.thr[cj], rs = n.rst[cj];
-    const size_t mword = (size_t)c * NW_ + (nb >> 1);
-    const int hsh = 16 * (nb & 1);
-    const uint32_t cm16 = (n.coremask[mword] >> hsh) & 0xFFFFu;
-    const uint32_t om16 = (n.outmask[mword] >> hsh) & 0xFFFFu;
-    const int ow = n.outword[mword];
+    const int32_t vmin = n.vmin, vmax = n.vmax;
+    const int oi = n.outidx[cj];
+    const uint32_t cm32 = n.coremask[(size_t)c * NB + nb];
+    const uint32_t om32 = n.outmask[(size_t)c * NB + nb];
 
-    // Connected-neuron counts of the axons this lane expands.
-    int degv[QPL][4];
+    // Connected-neuron counts of this wave's expansion words, low and high
+    // bytes, 4 axons per word, for the dot4 event count.
+    uint32_t degl[WPW][8], degh[WPW][8];
+    bool any_hi = false;
 #pragma unroll
-    for (int qi = 0; qi < QPL; ++qi) {
-        const int q = lane + 64 * qi;
+    for (int k = 0; k < WPW; ++k) {
+        const int wi = wave + 8 * k;
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            degv[qi][b] = q < QD ? n.deg[(size_t)c * A_ + 4 * q + b] : 0;
+        for (int q = 0; q < 8; ++q) {
+            degl[k][q] = wi < W_ ? n.degb[((size_t)c * 2 + 0) * (A_ / 4) + wi * 8 + q] : 0u;
+            degh[k][q] = wi < W_ ? n.degb[((size_t)c * 2 + 1) * (A_ / 4) + wi * 8 + q] : 0u;
+            any_hi |= degh[k][q] != 0u;
+        }
     }
 
     const int ci = n.in_index[c];
     const uint32_t *ext_c = (ta.ext_t != nullptr && ci >= 0) ? ta.ext_t + (size_t)ci * W_ : nullptr;
-    const size_t groups = (size_t)n.S16 / 16;
-    const v4i *vb_in = reinterpret_cast<const v4i *>(n.V) + (((size_t)c * NB + nb) * groups) * 64 + lane;
-    v4i *vb_out = reinterpret_cast<v4i *>(n.V) + (((size_t)c * NB + nb) * groups) * 64 + lane;
+    const size_t G32 = (size_t)n.S64 / 32;   // 32-sample groups
+    const size_t HG = (size_t)n.S64 / 64;    // 64-sample history words per neuron
+    const size_t vbase = ((size_t)c * NB + nb) * G32 * 256 + lane;
+    const v4i *vb_in = reinterpret_cast<const v4i *>(n.V) + vbase;
+    v4i *vb_out = reinterpret_cast<v4i *>(n.V) + vbase;
     const size_t CN = (size_t)n.C * N_;
-    uint16_t *hist_out = n.hist + ((size_t)ta.q_now * CN + (size_t)c * N_ + nb * 16 + jj) * groups;
+    uint64_t *hist_out = n.hist + ((size_t)ta.q_now * CN + cj) * HG;
+    uint64_t *rast_out =
+        oi >= 0 ? reinterpret_cast<uint64_t *>(n.raster) + ((size_t)ta.r_row * n.Nout + oi) * HG : nullptr;
 
-    // History gather: this lane collects axon ga of the core for SPT samples.
-    const int ga = (wave % APW) * 64 + lane;
-    const int part = wave / APW;
-    const uint32_t e_beg = n.rtx_ptr[(size_t)c * A_ + ga], e_end = n.rtx_ptr[(size_t)c * A_ + ga + 1];
-    auto load_mask = [&](int s0) -> uint32_t {
-        const int sp = s0 + part * SPT;
-        uint32_t m = 0;
-        if (sp < s_end) {
-            for (uint32_t e = e_beg; e < e_end; ++e) {
+    // ---- history gather: wave w collects, for axon block w % APW, the
+    // history bits of group w / APW of each tile (both groups when A = 512).
+    const bool gatherer = wave < 2 * APW;   // wave-uniform
+    const int axb = wave % APW;
+    const int grp = GPW == 2 ? 0 : wave / APW;
+    const int ga = axb * 64 + lane;
+    uint32_t e_beg = 0, e_end = 0;
+    if (gatherer) {
+        e_beg = n.rtx_ptr[(size_t)c * A_ + ga];
+        e_end = n.rtx_ptr[(size_t)c * A_ + ga + 1];
+    }
+    // The first FMAX sources of the axon stay in registers as history rows of
+    // (slot of their delay, source neuron); unused ones point at a zero row.
+    constexpr int FMAX = 4;
+    const uint64_t *src_row[FMAX];
+#pragma unroll
+    for (int k = 0; k < FMAX; ++k) {
+        src_row[k] = n.hist_zero;
+        if (e_beg + k < e_end) {
+            const uint32_t ent = n.rtx_ent[e_beg + k];
+            int slot = ta.q_now - (int)(ent & 15u) - 1;
+            if (slot < 0)
+                slot += n.Q;
+            src_row[k] = n.hist + ((size_t)slot * CN + (ent >> 4)) * HG;
+        }
+    }
+    const bool multi = __ballot(e_end - e_beg > 1) != 0;         // wave-uniform
+    const bool long_lists = __ballot(e_end - e_beg > FMAX) != 0;  // wave-uniform
+    auto raw_word = [&](const uint64_t *row, int tile) -> RawT {
+        if constexpr (GPW == 2)
+            return row[tile];
+        else
+            return reinterpret_cast<const uint32_t *>(row + tile)[grp];
+    };
+    // Each source's word goes straight into a register that carries it to its
+    // use one iteration later (no arithmetic on it before then, so the loads
+    // stay in flight); sources past the first FMAX (rare) are ORed in at once.
+    // Tiles past the chunk load an in-range word that is never used.
+    auto load_mask = [&](int s0, RawT (&raw)[FMAX]) {
+        const int tile = (s0 < s_end ? s0 : s_begin) / MFMA_TS;
+        raw[0] = raw_word(src_row[0], tile);
+        if (multi) {
+#pragma unroll
+            for (int k = 1; k < FMAX; ++k)
+                raw[k] = raw_word(src_row[k], tile);
+            for (uint32_t e = e_beg + FMAX; long_lists && e < e_end; ++e) {
                 const uint32_t ent = n.rtx_ent[e];
                 int slot = ta.q_now - (int)(ent & 15u) - 1;
                 if (slot < 0)
                     slot += n.Q;
-                const uint16_t *h = n.hist + ((size_t)slot * CN + (ent >> 4)) * groups + (sp >> 4);
-                if (SPT < 16) {
-                    m |= ((uint32_t)h[0] >> (sp & 15)) & ((1u << SPT) - 1u);
-                } else if (SPT == 16) {
-                    m |= (uint32_t)h[0];
-                } else {
-                    m |= (uint32_t)h[0] | (sp + 16 < s_end ? (uint32_t)h[1] << 16 : 0u);
-                }
+                raw[1] |= raw_word(n.hist + ((size_t)slot * CN + (ent >> 4)) * HG, tile);
             }
+        }
+    };
+    auto mask_of = [&](const RawT (&raw)[FMAX]) -> RawT {
+        RawT m = raw[0];
+        if (multi) {
+#pragma unroll
+            for (int k = 1; k < FMAX; ++k)
+                m |= raw[k];
         }
         return m;
     };
-    // Transpose: bit i of lane l's mask -> bit l of the axon word of sample i.
-    auto transpose = [&](uint32_t m, int buf) {
+    // Lane (h, j) holds, for axon 64*axb + 32h + j, the bits of a 32-sample
+    // group; after the transpose lane (h, i) holds the axon word 2*axb + h of
+    // the sample of bit i.
+    auto transpose_store = [&](RawT m, int buf) {
 #pragma unroll
-        for (int i = 0; i < SPT; ++i) {
-            const unsigned long long b = __ballot((m >> i) & 1u);
-            if (lane == 0) {
-                x_lds[buf][part * SPT + i][2 * (wave % APW)] = (uint32_t)b;
-                x_lds[buf][part * SPT + i][2 * (wave % APW) + 1] = (uint32_t)(b >> 32);
-            }
+        for (int g = 0; g < GPW; ++g) {
+            const uint32_t t = transpose32((uint32_t)(m >> (32 * g)), lane);
+            x_lds[buf][32 * (GPW == 2 ? g : grp) + sig][2 * axb + h] = t;
         }
     };
-    // external input words of the 4 samples this wave expands
-    uint32_t xe[4][QPL];
+    // external input words of sample s0 + lane (clamped into the chunk; lanes
+    // past its end are masked where the words are used)
+    uint32_t xe[WPW];
+#pragma unroll
+    for (int k = 0; k < WPW; ++k)
+        xe[k] = 0u;
     auto load_ext = [&](int s0) {
+        if (!ext_c)
+            return;
+        const int s = min(s0 + lane, s_end - 1);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int s = s0 + wave + 16 * m;
-#pragma unroll
-            for (int qi = 0; qi < QPL; ++qi) {
-                const int q = lane + 64 * qi;
-                xe[m][qi] = (q < QD && s < s_end && ext_c) ? ext_c[(size_t)s * ta.ext_sstride + (q >> 3)] : 0u;
-            }
+        for (int k = 0; k < WPW; ++k) {
+            const int wi = wave + 8 * k;
+            if (wi < W_)
+                xe[k] = ext_c[(size_t)s * ta.ext_sstride + wi];
         }
+    };
+    // Potentials of a tile go from HBM straight into this wave's LDS region,
+    // one tile ahead of their use.
+    auto prefetch_v = [&](int s0) {
+#pragma unroll
+        for (int t = 0; t < STW; ++t) {
+            const int g = (s0 >> 5) + stg * STW + t;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                __builtin_amdgcn_global_load_lds((const void *)(vb_in + ((size_t)g * 4 + q) * 64),
+                                                 (lds_void *)&v_lds[wave][t][q][0], 16, 0, 0);
+        }
+        compiler_fence();   // issue now, not later in the iteration
     };
 
-    transpose(load_mask(s_begin), 0);
-    uint32_t mnext = load_mask(s_begin + MFMA_TS);
+    // results of the previous tile, written at the top of the next iteration
+    v4i vnew[STW][4];
+    uint32_t hword[STW];   // lanes h = 0: the neuron's 32-sample spike word
+    unsigned pcnt[STW];    // lanes h = 0: packed spike counts of sample sigma(jj)
+    unsigned pdlev = 0;    // events | delivered << 18 of sample ps0 + lane
+    int ps0 = -1;
+    auto flush = [&]() {
+        if (ps0 < 0)
+            return;
+#pragma unroll
+        for (int t = 0; t < STW; ++t) {
+            const int sg = (ps0 >> 5) + stg * STW + t;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                __builtin_nontemporal_store(vnew[t][q], vb_out + ((size_t)sg * 4 + q) * 64);
+        }
+        const int tile = ps0 / MFMA_TS;
+        if (h == 0) {
+            if constexpr (STW == 2) {
+                const uint64_t w64 = (uint64_t)hword[0] | ((uint64_t)hword[STW - 1] << 32);
+                hist_out[tile] = w64;
+                if (rast_out)
+                    rast_out[tile] = w64;
+            } else {
+                reinterpret_cast<uint32_t *>(hist_out + tile)[stg] = hword[0];
+                if (rast_out)
+                    reinterpret_cast<uint32_t *>(rast_out + tile)[stg] = hword[0];
+            }
+#pragma unroll
+            for (int t = 0; t < STW; ++t) {
+                const int s = ps0 + 32 * (stg * STW + t) + sig;
+                if (s < s_end && pcnt[t])
+                    atomicAdd(&s_cnt[0][s - s_begin], pcnt[t]);
+            }
+        }
+        const int s = ps0 + lane;
+        if (s < s_end && pdlev)
+            atomicAdd(&s_cnt[1][s - s_begin], pdlev);
+    };
+
+    prefetch_v(s_begin);
+    RawT mraw[FMAX] = {};
+    if (gatherer) {
+        load_mask(s_begin, mraw);
+        transpose_store(mask_of(mraw), 0);
+        load_mask(s_begin + MFMA_TS, mraw);
+    }
     load_ext(s_begin);
-    __syncthreads();
+    lds_barrier();
 
     int it = 0;
     for (int s0 = s_begin; s0 < s_end; s0 += MFMA_TS, ++it) {
         int8_t *A = a_lds[it & 1];
-        // 1. expand delivered | external spikes to int8, count delivered spikes
-        //    and synaptic events
+        const bool more = s0 + MFMA_TS < s_end;
+        // 0. everything issued in the previous iteration has completed: write
+        //    out the previous tile, move this tile's potentials to VGPRs and
+        //    start the next tile's potential transfer
+        __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+        flush();
+        v4i vold[STW][4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int i = wave + 16 * m;
-            unsigned pk = 0;
+        for (int t = 0; t < STW; ++t)
 #pragma unroll
-            for (int qi = 0; qi < QPL; ++qi) {
-                const int q = lane + 64 * qi;
-                if (q < QD) {
-                    const uint32_t xd = x_lds[it & 1][i][q >> 3];
-                    const uint32_t x = xd | xe[m][qi];
-                    const uint32_t nib = (x >> (4 * (q & 7))) & 0xFu;
-                    // nibble b3b2b1b0 -> bytes 0/1: bit i moves to bit 8i, no carries
-                    *reinterpret_cast<uint32_t *>(&A[i * ROWB + 4 * q]) = (nib * 0x00204081u) & 0x01010101u;
-                    pk += (nib & 1u) * degv[qi][0] + ((nib >> 1) & 1u) * degv[qi][1] +
-                          ((nib >> 2) & 1u) * degv[qi][2] + ((nib >> 3) & 1u) * degv[qi][3];
-                    if ((q & 7) == 0)
-                        pk += (unsigned)__popc(xd) << EV_BITS;
+            for (int q = 0; q < 4; ++q)
+                vold[t][q] = v_lds[wave][t][q][lane];
+        __builtin_amdgcn_s_waitcnt(WAIT_LGKMCNT0);
+        if (more)
+            prefetch_v(s0 + MFMA_TS);
+
+        // 1. expansion, one lane per sample: delivered | external spikes of
+        //    this wave's axon words to int8, delivered and event counts
+        {
+            const bool svalid = s0 + lane < s_end;
+            unsigned pdl = 0u, pev = 0u, pevh = 0u;
+#pragma unroll
+            for (int k = 0; k < WPW; ++k) {
+                const int wi = wave + 8 * k;
+                if (wi < W_) {
+                    const uint32_t xd = x_lds[it & 1][lane][wi];
+                    const uint32_t x = xd | (svalid ? xe[k] : 0u);
+                    pdl += (unsigned)__popc(xd);
+                    uint32_t d[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        // nibble b3b2b1b0 -> bytes: bit i moves to bit 8i, no carries
+                        d[q] = (((x >> (4 * q)) & 0xFu) * 0x00204081u) & 0x01010101u;
+                        pev = __builtin_amdgcn_udot4(d[q], degl[k][q], pev, false);
+                        if (any_hi)
+                            pevh = __builtin_amdgcn_udot4(d[q], degh[k][q], pevh, false);
+                    }
+                    v4i *dst = reinterpret_cast<v4i *>(&A[lane * ROWB + 32 * wi]);
+                    dst[0] = v4i{(int)d[0], (int)d[1], (int)d[2], (int)d[3]};
+                    dst[1] = v4i{(int)d[4], (int)d[5], (int)d[6], (int)d[7]};
                 }
             }
-            pk = wave_sum(pk);
-            const int s = s0 + i;
-            if (lane == 0 && s < s_end) {
-                s_cnt[3][s - s_begin] += pk >> EV_BITS;
-                s_cnt[4][s - s_begin] += pk & ((1u << EV_BITS) - 1u);
+            pdlev = (pev + (pevh << 8)) | (pdl << 18);
+        }
+        ps0 = s0;
+        // 2. delivered spikes of the next tile into LDS, then the loads for
+        //    the tiles after (history bits two tiles ahead, input one ahead)
+        if (more) {
+            if (gatherer) {
+                transpose_store(mask_of(mraw), (it + 1) & 1);
+                load_mask(s0 + 2 * MFMA_TS, mraw);
             }
-        }
-        // 2. potentials of this tile; delivered spikes of the next tile into
-        //    LDS; history loads of the tile after; next tile's external input
-        v4i vold[STW];
-#pragma unroll
-        for (int t = 0; t < STW; ++t) {
-            const int sb = s0 + (stg * STW + t) * 16;
-            vold[t] = sb < s_end16 ? __builtin_nontemporal_load(vb_in + (size_t)(sb >> 4) * 64) : v4i{0, 0, 0, 0};
-        }
-        if (s0 + MFMA_TS < s_end) {
-            transpose(mnext, (it + 1) & 1);
-            mnext = load_mask(s0 + 2 * MFMA_TS);
             load_ext(s0 + MFMA_TS);
         }
-        __syncthreads();
+        lds_barrier();
 
         // 3. products and potential update
 #pragma unroll
         for (int t = 0; t < STW; ++t) {
             const int st = stg * STW + t;
-            const int sb = s0 + st * 16;
-            if (sb >= s_end16)
-                continue;
-            v4i acc = {0, 0, 0, 0};
-            const int8_t *arow = &A[(st * 16 + jj) * ROWB + 16 * g4];
+            const int sg = (s0 >> 5) + st;   // 32-sample group
+            v16i acc_lo, acc_hi;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc_lo[r] = lk;
+                acc_hi[r] = 0;
+            }
+            const int8_t *arow = &A[(st * 32 + jj) * ROWB + 16 * h];
 #pragma unroll
             for (int k = 0; k < KS; ++k) {
-                const v4i a = *reinterpret_cast<const v4i *>(arow + 64 * k);
-                if (TWO) {
-                    const v4i ah = a << 7;
-                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, breg[k][0], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, breg[k][1], acc, 0, 0, 0);
+                const v4i a = *reinterpret_cast<const v4i *>(arow + 32 * k);
+                if constexpr (TWO) {
+                    acc_hi = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][0], acc_hi, 0, 0, 0);
+                    acc_lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][1], acc_lo, 0, 0, 0);
                 } else {
-                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, breg[k][0], acc, 0, 0, 0);
+                    acc_lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][0], acc_lo, 0, 0, 0);
                 }
             }
-            v4i vnew;
-            unsigned long long bal[4];
+            const bool partial = sg * 32 + 32 > s_end;   // wave-uniform
+            uint32_t hb = 0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int s = sb + 4 * g4 + r;
+            for (int r = 0; r < 16; ++r) {
+                const int32_t in_leak = TWO ? acc_lo[r] + acc_hi[r] * 128 : acc_lo[r];
                 int32_t vn;
-                const bool fire = lif_update(vold[t][r], acc[r], lk, th, rs, n.vmin, n.vmax, vn) && s < s_end;
-                vnew[r] = vn;
-                bal[r] = __ballot(fire);
+                bool fire = lif_update(vold[t][r >> 2][r & 3], in_leak, 0, th, rs, vmin, vmax, vn);
+                if (partial)
+                    fire = fire && (sg * 32 + 8 * (r >> 2) + 4 * h + (r & 3) < s_end);
+                vnew[t][r >> 2][r & 3] = vn;
+                hb |= (uint32_t)fire << r;
             }
-            __builtin_nontemporal_store(vnew, vb_out + (size_t)(sb >> 4) * 64);
-            // this tick's spikes of neuron 16nb + jj for the 16 samples of the
-            // sub-tile, sample-sliced, into history slot t % Q
-            uint32_t m16 = 0;
-#pragma unroll
-            for (int g = 0; g < 4; ++g)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t half = (uint32_t)(bal[r] >> (16 * g)) & 0xFFFFu;
-                    m16 |= ((half >> jj) & 1u) << (4 * g + r);
-                }
-            if (g4 == 0)
-                hist_out[sb >> 4] = (uint16_t)m16;
-            if (jj < 4) {
-                const int i = st * 16 + 4 * g4 + jj;
-                const int s = s0 + i;
-                if (s < s_end) {
-                    const unsigned long long bs = jj == 0 ? bal[0] : jj == 1 ? bal[1] : jj == 2 ? bal[2] : bal[3];
-                    const uint32_t hw = (uint32_t)(bs >> (16 * g4)) & 0xFFFFu;
-                    if (hw) {
-                        atomicAdd(&s_cnt[0][s - s_begin], (unsigned)__popc(hw));
-                        atomicAdd(&s_cnt[1][s - s_begin], (unsigned)__popc(hw & cm16));
-                        atomicAdd(&s_cnt[2][s - s_begin], (unsigned)__popc(hw & om16));
-                    }
-                    if (ow >= 0)
-                        reinterpret_cast<uint16_t *>(n.raster)[(((size_t)ta.r_row * n.S + s) * n.Wout + ow) * 2 +
-                                                               (nb & 1)] = (uint16_t)(hw & om16);
-                }
-            }
+            // the neuron's spike word: bits r from lane jj, bits 16 + r from lane jj + 32
+            const uint32_t hw = hb | ((uint32_t)__shfl_xor((int)hb, 32, 64) << 16);
+            hword[t] = hw;
+            // per-sample spike words of the wave's 32 neurons, and their counts
+            const uint32_t sw = transpose32(hw, lane);
+            pcnt[t] = (unsigned)__popc(sw) | ((unsigned)__popc(sw & cm32) << 10) |
+                      ((unsigned)__popc(sw & om32) << 20);
         }
     }
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+    flush();
+    lds_barrier();
     for (int i = threadIdx.x; i < s_end - s_begin; i += blockDim.x) {
         unsigned long long *cp = n.cnt + ((size_t)c * n.S + s_begin + i) * CNT_N;
-        cp[CNT_EMITTED] += s_cnt[0][i];
-        cp[CNT_ROUTED] += s_cnt[1][i];
-        cp[CNT_OUT] += s_cnt[2][i];
-        cp[CNT_DELIVERED] += s_cnt[3][i];
-        cp[CNT_EVENTS] += s_cnt[4][i];
+        const unsigned sp = s_cnt[0][i], ev = s_cnt[1][i];
+        cp[CNT_EMITTED] += sp & 1023u;
+        cp[CNT_ROUTED] += (sp >> 10) & 1023u;
+        cp[CNT_OUT] += sp >> 20;
+        cp[CNT_DELIVERED] += ev >> 18;
+        cp[CNT_EVENTS] += ev & ((1u << 18) - 1u);
     }
 }
 
 bool mfma_shape_supported(int A, int N, int two_planes)
 {
     const bool ok_a = A == 64 || A == 128 || A == 256 || A == 512;
-    const bool ok_n = N == 64 || N == 128 || N == 256 || N == 512;
-    // B tiles must fit in 32 VGPRs per lane (A * N * planes / 4096) with one
-    // neuron block per wavefront; larger cores would spill. 512-axon cores
-    // with two planes also spill (wider expansion state).
-    return ok_a && ok_n && N <= 256 && (long)A * N * (two_planes ? 2 : 1) <= (1L << 17) &&
-           !(A == 512 && two_planes);
+    // 32-neuron blocks over 8 wavefronts (4 or 8 blocks); the B tiles take
+    // A * planes / 8 VGPRs per lane, at most 64.
+    return ok_a && (N == 128 || N == 256) && A * (two_planes ? 2 : 1) <= 512;
 }
 
 template <int A_, int N_>
 static hipError_t launch_mfma_an(const DevNet &n, const TickArgs &a, int two, int spw, hipStream_t st)
 {
     const int chunks = (n.S + spw - 1) / spw;
-    const dim3 grid(n.C * chunks), block(1024);
-    if constexpr ((long)A_ * N_ * 2 <= (1L << 17) && A_ < 512) {
+    const dim3 grid(n.C * chunks), block(512);
+    if constexpr (A_ <= 256) {
         if (two)
             hipLaunchKernelGGL((k_integrate_mfma<A_, N_, true>), grid, block, 0, st, n, a, spw);
         else
             hipLaunchKernelGGL((k_integrate_mfma<A_, N_, false>), grid, block, 0, st, n, a, spw);
-    } else if constexpr ((long)A_ * N_ <= (1L << 17)) {
+    } else {
         if (two)
             return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_integrate_mfma<A_, N_, false>), grid, block, 0, st, n, a, spw);
-    } else {
-        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -335,7 +484,6 @@ template <int A_>
 static hipError_t launch_mfma_a(const DevNet &n, const TickArgs &a, int two, int spw, hipStream_t st)
 {
     switch (n.N) {
-    case 64: return launch_mfma_an<A_, 64>(n, a, two, spw, st);
     case 128: return launch_mfma_an<A_, 128>(n, a, two, spw, st);
     case 256: return launch_mfma_an<A_, 256>(n, a, two, spw, st);
     default: return hipErrorInvalidValue;
@@ -346,7 +494,7 @@ hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_pla
                                  hipStream_t st)
 {
     if (!mfma_shape_supported(n.A, n.N, two_planes) || samples_per_wg <= 0 || samples_per_wg % MFMA_TS ||
-        samples_per_wg > MFMA_SPW_MAX || n.vlayout != VLAYOUT_BRICK)
+        samples_per_wg > MFMA_SPW_MAX || n.vlayout != VLAYOUT_BRICK || n.S64 % MFMA_TS || n.S > n.S64)
         return hipErrorInvalidValue;
     switch (n.A) {
     case 64: return launch_mfma_a<64>(n, a, two_planes, samples_per_wg, st);

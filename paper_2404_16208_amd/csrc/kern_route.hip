@@ -181,18 +181,19 @@ hipError_t launch_route(const DevNet &n, int q_now, const RouteCfg &cfg, hipStre
 
 __global__ void k_reset_potentials(DevNet n)
 {
-    const size_t total = n.vlayout == VLAYOUT_BRICK ? (size_t)n.C * n.S16 * n.N : (size_t)n.C * n.S * n.N;
-    const int NB = n.N / 16;
-    const size_t groups = (size_t)n.S16 / 16;
+    const bool brick = n.vlayout == VLAYOUT_BRICK;
+    const size_t total = (size_t)n.C * (brick ? n.S64 : n.S) * n.N;
+    const int NB = n.N / 32;
+    const size_t groups = (size_t)n.S64 / 32;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (size_t)gridDim.x * blockDim.x) {
         size_t c, j;
-        if (n.vlayout == VLAYOUT_BRICK) {
+        if (brick) {
+            // [C][N/32][S64/32][4][64][4]: 1024 values per brick
             const size_t lane = (i >> 2) & 63;
-            const size_t brick = i >> 8;              // (c * NB + nb) * groups + g
-            const size_t cnb = brick / groups;
+            const size_t cnb = (i >> 10) / groups;   // c * NB + nb
             c = cnb / NB;
-            j = (cnb % NB) * 16 + (lane & 15);
+            j = (cnb % NB) * 32 + (lane & 31);
         } else {
             c = i / ((size_t)n.S * n.N);
             j = i % n.N;
@@ -214,8 +215,8 @@ hipError_t launch_reset_state(const DevNet &n, hipStream_t st)
     const bool hist = n.vlayout == VLAYOUT_BRICK;
     const size_t ring_words = hist ? 0 : (size_t)n.Q * n.S * n.C * n.W;
     const size_t spk_words = hist ? 0 : (size_t)n.S * n.C * n.NW;
-    const size_t hist_words = hist ? (size_t)n.Q * n.C * n.N * (n.S16 / 16) / 2 : 0;
-    const size_t raster_words = (size_t)n.RT * n.S * n.Wout;
+    const size_t hist_words = hist ? (size_t)n.Q * n.C * n.N * (n.S64 / 64) * 2 : 0;
+    const size_t raster_words = hist ? (size_t)n.RT * n.Nout * (n.S64 / 64) * 2 : (size_t)n.RT * n.S * n.Wout;
     const size_t cnt_words = (size_t)n.C * n.S * CNT_N * 2;
     if (ring_words)
         hipLaunchKernelGGL(k_fill_u32, dim3(2048), dim3(256), 0, st, n.ring, ring_words);

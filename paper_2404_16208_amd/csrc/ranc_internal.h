@@ -1,9 +1,9 @@
 // ranc_internal.h -- device data layout shared by the host runtime and the kernels.
 //
 // Notation: C cores, A axons and N neurons per core, G axon types,
-// W = A/32 axon words, NW = N/32 neuron words, NB = N/16 neuron blocks,
-// D = max delay, Q = D + 1 scheduler slots, S samples (S16: S rounded up to
-// 16), RT retained raster ticks, Wout output words.
+// W = A/32 axon words, NW = N/32 neuron words, D = max delay, Q = D + 1
+// scheduler slots, S samples (S64: S rounded up to 64), HG = S64/64,
+// RT retained raster ticks, Wout output words, Nout output neurons.
 //
 // Parameters (written once at load):
 //   colbits  u32 [C][W][N]     bit b of colbits[c][w][n] = crossbar(c, 32w+b, n)   (plain path)
@@ -12,29 +12,36 @@
 //   leak, thr, rst, vinit i32 [C][N]
 //   coremask, outmask u32 [C][NW]  neurons whose destination is a core / the output bus
 //   outword  i32 [C][NW]       raster column of that neuron word, -1 if it has no output neuron
+//   outidx   i32 [C][N]        (MFMA path) index of the neuron among output-bus neurons, -1 if none
 //   in_index i32 [C]           input slot of the core, -1 if it takes no external input
-//   routing table (destination-owned, one list per destination axon word dw = c*W + w),
-//   stored wave-interleaved: words are grouped by 64; group g holds its
-//   words' lists as rt_ent[rt_goff[g] + k*64 + (dw % 64)], each list sorted by
-//   delay; rt_dcnt u16 [C*W][DMAX] counts the entries of each delay
-//   (DMAX = max delay rounded up to 4, 8 or 16). Entry bits: [0,5)
+//   routing table (plain path; destination-owned, one list per destination axon
+//   word dw = c*W + w), stored wave-interleaved: words are grouped by 64; group
+//   g holds its words' lists as rt_ent[rt_goff[g] + k*64 + (dw % 64)], each
+//   list sorted by delay; rt_dcnt u16 [C*W][DMAX] counts the entries of each
+//   delay (DMAX = max delay rounded up to 4, 8 or 16). Entry bits: [0,5)
 //   destination axon % 32, [5,9) delay - 1, [9,32) source neuron c*N + n.
-//   deg      i32 [C][A]        connected neurons per axon (synaptic-event counter, MFMA path)
+//   degb     u32 [C][2][A/4]   (MFMA path) connected neurons per axon, low byte
+//                              plane then high byte plane, 4 axons per word
 //   planes   int8 MFMA B operand tiles (MFMA path), see kern_mfma.hip
 //   rtx_ptr  u32 [C*A + 1], rtx_ent u32 [E]  (MFMA path) the same routing table keyed by
 //                              destination axon: entries (source neuron c*N + n) << 4 | (delay - 1)
 // State:
 //   V        i32, layout by path:
 //              plain: [C][S][N]
-//              MFMA:  [C][NB][S16/16][64][4], element (lane l, r) of brick
-//                     (c, nb, g) = sample 16g + 4(l/16) + r, neuron 16nb + l%16
+//              MFMA:  [C][N/32][S64/32][4][64][4]: brick (c, nb, g) holds 32 samples
+//                     x 32 neurons; element (q, lane l, e) = sample 32g + 8q + 4(l/32) + e,
+//                     neuron 32nb + l%32 (the MFMA result layout)
 //   plain path:
 //   ring     u32 [Q][S][C][W]  scheduler: slot t%Q holds the axon spikes of tick t
 //   spk      u32 [S][C][NW]    spikes of the current tick
-//   MFMA path:
-//   hist     u16 [Q][C*N][S16/16]  spikes of tick t in slot t%Q, bit i of element
-//                              (slot, neuron, g) = sample 16g + i
 //   raster   u32 [RT][S][Wout] output-bus spikes of tick t in row t%RT
+//   MFMA path:
+//   hist     u64 [Q][C*N][HG]  spikes of tick t in slot t%Q; word (slot, neuron, i)
+//                              covers samples 64i .. 64i+63, bit p = sample
+//                              64i + 32(p/32) + sigma(p%32) with
+//                              sigma(b) = 8((b%16)/4) + 4(b/16) + b%4
+//   raster   u64 [RT][Nout][HG] output-bus spikes of tick t in row t%RT, words as hist
+//   both:
 //   cnt      u64 [C][S][5]     emitted, routed, delivered, out, events
 #pragma once
 
@@ -51,7 +58,7 @@ static constexpr int RT_POS_BITS = 5, RT_DELAY_SHIFT = 5, RT_SRC_SHIFT = 9;
 static constexpr long long RT_MAX_NEURONS = 1LL << 23;
 
 struct DevNet {
-    int C, A, N, G, W, NW, D, Q, S, S16, RT, Wout, Cin, vlayout;
+    int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, vlayout;
     int32_t vmin, vmax;
     // parameters
     const uint32_t *colbits, *typemask;
@@ -60,13 +67,15 @@ struct DevNet {
     const int32_t *outword, *in_index;
     const uint16_t *rt_dcnt;
     const uint32_t *rt_goff, *rt_ent;
-    const int32_t *deg;
+    const int32_t *outidx;
+    const uint32_t *degb;
     const uint4 *planes;
     const uint32_t *rtx_ptr, *rtx_ent;
+    const uint64_t *hist_zero;   // HG zero words (a history row with no spikes)
     // state
     int32_t *V;
     uint32_t *ring, *spk, *raster;
-    uint16_t *hist;
+    uint64_t *hist;
     unsigned long long *cnt;
 };
 

@@ -41,13 +41,13 @@ ranc_status hip_fail(hipError_t e, const char *what)
 
 enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
-    R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEG, R_PLANES, R_RTXPTR, R_RTXENT,
+    R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
     R_PARAMS_END,  // everything before this is uploaded once at load
     R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_EXT, R_NREG
 };
 
 struct Plan {
-    int C, A, N, G, W, NW, D, Q, S, S16, RT, Wout, Cin, path, two, spw;
+    int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, path, two, spw;
     long long E;         // routed (CORE) neurons
     long long ell_words; // u32 words of the wave-interleaved routing table
     size_t off[R_NREG], size[R_NREG], params_bytes, total;
@@ -155,7 +155,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.D = d->max_delay;
     p.Q = p.D + 1;
     p.S = S;
-    p.S16 = (S + 15) / 16 * 16;
+    p.S64 = (S + 63) / 64 * 64;
     p.RT = RT;
     p.Cin = d->num_input_cores;
     p.two = d->weight_bits > 8;
@@ -178,9 +178,11 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
                 p.spw = v;
         }
     }
-    long long E = 0, wout = 0;
-    for (size_t i = 0; i < (size_t)p.C * p.N; ++i)
+    long long E = 0, wout = 0, nout = 0;
+    for (size_t i = 0; i < (size_t)p.C * p.N; ++i) {
         E += d->dest_kind[i] == RANC_DEST_CORE;
+        nout += d->dest_kind[i] == RANC_DEST_OUT;
+    }
     {
         // wave-interleaved table: every group of 64 destination words is padded
         // to its longest list
@@ -210,6 +212,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
         }
     p.E = E;
     p.Wout = (int)wout;
+    p.Nout = (int)nout;
     const size_t C = p.C, A = p.A, N = p.N, G = p.G, W = p.W, NW = p.NW;
     const bool mf = p.path == RANC_PATH_MFMA;
     p.size[R_COLBITS] = mf ? 0 : C * W * N * 4;
@@ -223,13 +226,16 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_RTENT] = mf ? 0 : std::max<size_t>((size_t)p.ell_words, 1) * 4;
     p.size[R_RTXPTR] = mf ? (C * A + 1) * 4 : 0;
     p.size[R_RTXENT] = mf ? std::max<size_t>((size_t)E, 1) * 4 : 0;
-    p.size[R_DEG] = C * A * 4;
+    const size_t HG = (size_t)p.S64 / 64;
+    p.size[R_HZERO] = mf ? HG * 8 : 0;
+    p.size[R_DEGB] = mf ? C * 2 * A : 0;
+    p.size[R_OUTIDX] = mf ? C * N * 4 : 0;
     p.size[R_PLANES] = mf ? C * A * N * (p.two ? 2 : 1) : 0;
-    p.size[R_V] = C * (mf ? (size_t)p.S16 : (size_t)S) * N * 4;
+    p.size[R_V] = C * (mf ? (size_t)p.S64 : (size_t)S) * N * 4;
     p.size[R_RING] = mf ? 0 : (size_t)p.Q * S * C * W * 4;
     p.size[R_SPK] = mf ? 0 : (size_t)S * C * NW * 4;
-    p.size[R_HIST] = mf ? (size_t)p.Q * C * N * (p.S16 / 16) * 2 : 0;
-    p.size[R_RASTER] = (size_t)RT * S * p.Wout * 4;
+    p.size[R_HIST] = mf ? (size_t)p.Q * C * N * HG * 8 : 0;
+    p.size[R_RASTER] = mf ? (size_t)RT * p.Nout * HG * 8 : (size_t)RT * S * p.Wout * 4;
     p.size[R_CNT] = C * S * CNT_N * 8;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
     size_t off = 0;
@@ -351,34 +357,43 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
             if (d->dest_kind[i] == RANC_DEST_CORE)
                 ent[fill[dest_of(i)]++] = ((uint32_t)i << 4) | (uint32_t)(d->dest_delay[i] - 1);
     }
-    int32_t *deg = (int32_t *)at(R_DEG);
-    for (int c = 0; c < C; ++c)
-        for (int a = 0; a < A; ++a) {
-            int k = 0;
-            for (int w = 0; w < NW; ++w)
-                k += __builtin_popcount(d->crossbar[((size_t)c * A + a) * NW + w]);
-            deg[(size_t)c * A + a] = k;
-        }
+    if (p.size[R_DEGB]) {
+        // connected neurons per axon, as a low-byte and a high-byte plane
+        uint8_t *db = at(R_DEGB);
+        for (int c = 0; c < C; ++c)
+            for (int a = 0; a < A; ++a) {
+                int k = 0;
+                for (int w = 0; w < NW; ++w)
+                    k += __builtin_popcount(d->crossbar[((size_t)c * A + a) * NW + w]);
+                db[((size_t)c * 2 + 0) * A + a] = (uint8_t)(k & 255);
+                db[((size_t)c * 2 + 1) * A + a] = (uint8_t)(k >> 8);
+            }
+    }
+    if (p.size[R_OUTIDX]) {
+        int32_t *oi = (int32_t *)at(R_OUTIDX);
+        int32_t next = 0;
+        for (size_t i = 0; i < (size_t)C * N; ++i)
+            oi[i] = d->dest_kind[i] == RANC_DEST_OUT ? next++ : -1;
+    }
     if (p.size[R_PLANES]) {
-        // B tiles: [C][N/16][A/64][planes][64 lanes][16 bytes]; lane l, byte b of
-        // k-step k covers axon 64k + 16(l/16) + b and neuron 16nb + l%16.
+        // B tiles: [C][N/32][A/32][planes][64 lanes][16 bytes]; lane l, byte b of
+        // k-step k covers axon 32k + 16(l/32) + b and neuron 32nb + l%32.
+        // Two planes: hi = w >> 7 (floor(w / 128)) first, then lo = w & 127.
         int8_t *pl = (int8_t *)at(R_PLANES);
-        const int NB = N / 16, KS = A / 64, PL = p.two ? 2 : 1;
+        const int NB = N / 32, KS = A / 32, PL = p.two ? 2 : 1;
         for (int c = 0; c < C; ++c)
             for (int nb = 0; nb < NB; ++nb)
                 for (int k = 0; k < KS; ++k)
                     for (int l = 0; l < 64; ++l)
                         for (int b = 0; b < 16; ++b) {
-                            const int a = 64 * k + 16 * (l / 16) + b, j = 16 * nb + l % 16;
+                            const int a = 32 * k + 16 * (l / 32) + b, j = 32 * nb + l % 32;
                             const int w = conn(c, a, j) ? d->weight[((size_t)c * N + j) * G +
                                                                     d->axon_type[(size_t)c * A + a]]
                                                         : 0;
                             const size_t base = ((((size_t)c * NB + nb) * KS + k) * PL) * 1024 + (size_t)l * 16 + b;
                             if (PL == 2) {
-                                const int hi = w >> 7;      // arithmetic shift: floor(w / 128)
-                                const int lo = w & 127;
-                                pl[base] = (int8_t)(-hi);
-                                pl[base + 1024] = (int8_t)lo;
+                                pl[base] = (int8_t)(w >> 7);
+                                pl[base + 1024] = (int8_t)(w & 127);
                             } else {
                                 pl[base] = (int8_t)w;
                             }
@@ -409,7 +424,8 @@ struct ranc_net {
     hipStream_t last_stream;
     int64_t tick;
     uint64_t version, raster_version;
-    std::vector<int> out_words;        // (core, word) pairs of raster columns
+    std::vector<int> out_words;        // (core, word) pairs of raster columns (plain path)
+    std::vector<int> out_neurons;      // (core, neuron) of each output-bus neuron (MFMA path)
     std::vector<uint32_t> raster_host; // mirror of the raster
     uint64_t v_version = 0;
     std::vector<int32_t> v_host;       // mirror of the potentials
@@ -502,7 +518,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     auto reg = [&](Region r) -> uint8_t * { return net->ws + p.off[r]; };
     DevNet &n = net->dn;
     n.C = p.C; n.A = p.A; n.N = p.N; n.G = p.G; n.W = p.W; n.NW = p.NW; n.D = p.D; n.Q = p.Q;
-    n.S = p.S; n.S16 = p.S16; n.RT = p.RT; n.Wout = p.Wout; n.Cin = p.Cin;
+    n.S = p.S; n.S64 = p.S64; n.RT = p.RT; n.Wout = p.Wout; n.Nout = p.Nout; n.Cin = p.Cin;
     n.vlayout = p.path == RANC_PATH_MFMA ? VLAYOUT_BRICK : VLAYOUT_CSN;
     n.vmin = (int32_t)(-(1LL << (desc->potential_bits - 1)));
     n.vmax = (int32_t)((1LL << (desc->potential_bits - 1)) - 1);
@@ -520,18 +536,25 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.rt_dcnt = (const uint16_t *)reg(R_RTDCNT);
     n.rt_goff = (const uint32_t *)reg(R_RTGOFF);
     n.rt_ent = (const uint32_t *)reg(R_RTENT);
-    n.deg = (const int32_t *)reg(R_DEG);
+    n.degb = (const uint32_t *)reg(R_DEGB);
+    n.outidx = (const int32_t *)reg(R_OUTIDX);
     n.planes = (const uint4 *)reg(R_PLANES);
     n.V = (int32_t *)reg(R_V);
     n.ring = (uint32_t *)reg(R_RING);
     n.spk = (uint32_t *)reg(R_SPK);
-    n.hist = (uint16_t *)reg(R_HIST);
+    n.hist = (uint64_t *)reg(R_HIST);
     n.rtx_ptr = (const uint32_t *)reg(R_RTXPTR);
     n.rtx_ent = (const uint32_t *)reg(R_RTXENT);
+    n.hist_zero = (const uint64_t *)reg(R_HZERO);
     n.raster = (uint32_t *)reg(R_RASTER);
     n.cnt = (unsigned long long *)reg(R_CNT);
     std::vector<uint8_t> host;
     pack_params(desc, p, host, net->out_words);
+    for (size_t i = 0; i < (size_t)p.C * p.N; ++i)
+        if (desc->dest_kind[i] == RANC_DEST_OUT) {
+            net->out_neurons.push_back((int)(i / p.N));
+            net->out_neurons.push_back((int)(i % p.N));
+        }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(net->ws, host.data(), p.params_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -674,25 +697,44 @@ ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, 
     if (tick_begin < lo || tick_end > net->tick || tick_begin > tick_end)
         return fail(RANC_ESTATE, "ticks [%lld, %lld) outside the retained window [%lld, %lld)",
                     (long long)tick_begin, (long long)tick_end, (long long)lo, (long long)net->tick);
-    net->raster_host.resize((size_t)p.RT * p.S * p.Wout);
+    const bool mf = p.path == RANC_PATH_MFMA;
+    const size_t HG = (size_t)p.S64 / 64;
+    net->raster_host.resize(mf ? (size_t)p.RT * p.Nout * HG * 2 : (size_t)p.RT * p.S * p.Wout);
     ranc_status st = refresh_mirror(net, net->dn.raster, net->raster_host.size() * 4, net->raster_host.data(),
                                     net->raster_version, "reading the raster");
     if (st != RANC_OK)
         return st;
     int64_t k = 0;
-    for (int64_t t = tick_begin; t < tick_end; ++t) {
-        const uint32_t *row = net->raster_host.data() + ((size_t)(t % p.RT) * p.S + sample) * p.Wout;
-        for (int ow = 0; ow < p.Wout; ++ow) {
-            uint32_t w = row[ow];
-            while (w) {
-                const int b = __builtin_ctz(w);
-                w &= w - 1;
-                if (out && k < capacity) {
-                    out[k].tick = t;
-                    out[k].core = net->out_words[2 * ow];
-                    out[k].neuron = net->out_words[2 * ow + 1] * 32 + b;
+    auto emit = [&](int64_t t, int core, int neuron) {
+        if (out && k < capacity) {
+            out[k].tick = t;
+            out[k].core = core;
+            out[k].neuron = neuron;
+        }
+        ++k;
+    };
+    if (mf) {
+        // neuron-major words of 64 samples; the bit of a sample inverts the
+        // spike-word order sigma(b) = 8((b%16)/4) + 4(b/16) + b%4
+        const int i = sample % 32;
+        const int bit = 32 * ((sample % 64) / 32) + 16 * ((i % 8) / 4) + 4 * (i / 8) + i % 4;
+        const uint64_t *r64 = reinterpret_cast<const uint64_t *>(net->raster_host.data());
+        for (int64_t t = tick_begin; t < tick_end; ++t) {
+            const uint64_t *row = r64 + (size_t)(t % p.RT) * p.Nout * HG + sample / 64;
+            for (int o = 0; o < p.Nout; ++o)
+                if ((row[(size_t)o * HG] >> bit) & 1u)
+                    emit(t, net->out_neurons[2 * o], net->out_neurons[2 * o + 1]);
+        }
+    } else {
+        for (int64_t t = tick_begin; t < tick_end; ++t) {
+            const uint32_t *row = net->raster_host.data() + ((size_t)(t % p.RT) * p.S + sample) * p.Wout;
+            for (int ow = 0; ow < p.Wout; ++ow) {
+                uint32_t w = row[ow];
+                while (w) {
+                    const int b = __builtin_ctz(w);
+                    w &= w - 1;
+                    emit(t, net->out_words[2 * ow], net->out_words[2 * ow + 1] * 32 + b);
                 }
-                ++k;
             }
         }
     }
@@ -710,7 +752,7 @@ ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out)
     if (sample < 0 || sample >= p.S)
         return fail(RANC_EINVAL, "sample %d out of range", sample);
     const bool brick = net->dn.vlayout == VLAYOUT_BRICK;
-    net->v_host.resize((size_t)p.C * (brick ? p.S16 : p.S) * p.N);
+    net->v_host.resize((size_t)p.C * (brick ? p.S64 : p.S) * p.N);
     ranc_status st = refresh_mirror(net, net->dn.V, net->v_host.size() * 4, net->v_host.data(), net->v_version,
                                     "reading potentials");
     if (st != RANC_OK)
@@ -720,14 +762,15 @@ ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out)
             memcpy(out + (size_t)c * p.N, net->v_host.data() + ((size_t)c * p.S + sample) * p.N, (size_t)p.N * 4);
         return RANC_OK;
     }
-    const int NB = p.N / 16;
-    const size_t groups = (size_t)p.S16 / 16;
-    const int g = sample / 16, i = sample % 16, g4 = i / 4, r = i % 4;
+    // brick (c, nb, g): element (q, lane l, e) = sample 32g + 8q + 4(l/32) + e, neuron 32nb + l%32
+    const int NB = p.N / 32;
+    const size_t groups = (size_t)p.S64 / 32;
+    const int g = sample / 32, i = sample % 32, q = i / 8, hh = (i % 8) / 4, e = i % 4;
     for (int c = 0; c < p.C; ++c)
         for (int nb = 0; nb < NB; ++nb)
-            for (int jj = 0; jj < 16; ++jj)
-                out[(size_t)c * p.N + nb * 16 + jj] =
-                    net->v_host[((((size_t)c * NB + nb) * groups + g) * 64 + g4 * 16 + jj) * 4 + r];
+            for (int jj = 0; jj < 32; ++jj)
+                out[(size_t)c * p.N + nb * 32 + jj] =
+                    net->v_host[(((((size_t)c * NB + nb) * groups + g) * 4 + q) * 64 + 32 * hh + jj) * 4 + e];
     return RANC_OK;
 }
 

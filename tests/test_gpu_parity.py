@@ -42,6 +42,10 @@ SHAPES = [
     (3, 512, 128, 4, 8, 32, 5, 3, 66, 6),
     (2, 512, 512, 2, 9, 32, 3, 2, 5, 6),
     (4, 256, 64, 4, 9, 10, 1, 2, 129, 7),
+    (4, 64, 128, 2, 4, 8, 2, 2, 70, 10),
+    (4, 256, 128, 4, 9, 10, 1, 2, 129, 7),
+    (4, 128, 128, 2, 9, 16, 4, 2, 130, 8),
+    (2, 512, 256, 4, 8, 32, 3, 2, 100, 6),
 ]
 
 
@@ -71,7 +75,7 @@ def test_large_core_count_unstaged_route():
 
 
 def test_no_input_no_output_cores():
-    net = W.random_net(78, 4, 64, 64, 2, max_delay=2, grid_w=2, p_core=1.0, p_out=0.0,
+    net = W.random_net(78, 4, 64, 128, 2, max_delay=2, grid_w=2, p_core=1.0, p_out=0.0,
                        leak_range=(5, 20), thr_range=(10, 40), input_cores=[], config_id=702)
     assert len(net.input_cores) == 0 and not (net.dest_kind == W.DEST_OUT).any()
     for path in ("plain", "mfma"):
@@ -79,6 +83,18 @@ def test_no_input_no_output_cores():
         ref = oracle_results(net, None, 9, [0])[0]
         for s in (0, 31, 63):
             assert_sample_equal(g, ref, s, 9, what=f"noio/{path}")
+
+
+@pytest.mark.parametrize("spw", [128, 512])
+def test_mfma_many_tiles_per_workgroup(spw, monkeypatch):
+    # several 64-sample tiles per workgroup (the software pipeline), with a
+    # ragged last tile inside the last chunk; fan-in up to 6 per axon
+    monkeypatch.setenv("RANC_MFMA_SPW", str(spw))
+    net = W.random_net(81, 6, 256, 256, 4, weight_bits=9, max_delay=3, grid_w=3, density=0.2, p_core=0.9,
+                       p_out=0.1, input_cores=[0, 2, 4], config_id=705)
+    x = W.bernoulli_inputs(15, net, 300, 9, 0.3, config_id=705)
+    assert_parity(net, x, 9, "mfma", samples=[0, 1, 63, 64, 127, 128, 200, 255, 256, 298, 299],
+                  what=f"spw{spw}")
 
 
 # ----------------------------------------------------------- resume / state
@@ -175,7 +191,7 @@ def test_saturation_extremes(path, pbits):
     """Potentials at the ends of the P-bit range, leaks at +-2^30, thresholds
     at the int32 limits: the exact int64 oracle against the saturating 32-bit
     update of the kernels."""
-    net = W.random_net(80 + pbits, 4, 64, 64, 2, weight_bits=9, potential_bits=pbits, max_delay=2, grid_w=2,
+    net = W.random_net(80 + pbits, 4, 64, 128, 2, weight_bits=9, potential_bits=pbits, max_delay=2, grid_w=2,
                        density=0.5, p_core=0.5, p_out=0.5, input_cores=[0, 1, 2, 3], config_id=704)
     r = np.random.default_rng(pbits)
     lo, hi = -(1 << (pbits - 1)), (1 << (pbits - 1)) - 1
