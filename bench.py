@@ -7,8 +7,9 @@ crossbar density 0.2, 4 axon types, signed 9-bit weights, delays 1-4,
 rate-coded 784-pixel input), 1024 independent samples. One step advances all
 1024 samples by 32 ticks (every tick: scheduler slot + input, integration,
 leak/threshold/reset, routing into the delayed-delivery scheduler), on the
-batched int8-MFMA path. Inputs are synthetic and resident in HBM before
-timing starts. The same steps are also timed on the plain path.
+batched int8-MFMA path, as one replay of the captured 32-tick HIP graph.
+Inputs are synthetic and resident in HBM before timing starts. The same steps
+are also timed on the plain path.
 
 Output: one JSON line. ``value`` is synaptic events per second (events =
 (spiking axon, connected neuron) pairs, counted by the GPU itself over the
@@ -84,23 +85,29 @@ def read_traffic(src_hash: str):
         return None
 
 
-def time_steps(g, xd, T, warmup, steps, torch):
+def time_steps(g, xd, T, warmup, steps, torch, graph=False):
+    """Time `steps` calls of T ticks; the library's HIP events on the launch
+    stream time every kernel launch (or every graph launch) inside the same
+    timed region."""
     for _ in range(warmup):
-        g.run(xd, T)
+        g.run(xd, T, graph=graph)
     torch.cuda.synchronize()
     before = g.total_counters()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g.profile(True)
     torch.cuda.synchronize()
     e0.record(st)
     for _ in range(steps):
-        g.run(xd, T)
+        g.run(xd, T, graph=graph)
     e1.record(st)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    prof = g.profile_read()
+    g.profile(False)
     after = g.total_counters()
     delta = {k: after[k] - before[k] for k in after}
-    return ms, delta
+    return ms, delta, prof
 
 
 def kernel_profile(g, xd, T, steps, torch):
@@ -142,6 +149,65 @@ def cpu_baseline(net, x, T, n_samples, gpu_net, torch):
             "gpu_bit_exact_on_sample": exact}
 
 
+def sparse_mesh_algorithmic_bytes(net, S: int, delivered: float, ext_bits: float) -> dict:
+    """Bytes one tick of the sample-tiled paths must move on the large sparse
+    mesh: potentials read + written (8 N per (sample, core)), the tick's spike
+    bits out (N/8) and the history bits gathered (A/8 per (sample, core)), the
+    external input bits, plus per core the path's weights (MFMA: int8 planes;
+    sparse: crossbar rows A*N/8, G weights per neuron, type masks) and neuron
+    parameters."""
+    C, A, N, G = net.num_cores, net.num_axons, net.num_neurons, net.num_types
+    state = S * C * (8 * N + N // 8 + A // 8) + ext_bits / 8
+    planes = 2 if net.weight_bits > 8 else 1
+    return {"mfma": state + C * (A * N * planes + 12 * N),
+            "sparse": state + C * (A * N // 8 + 4 * G * N + G * A // 8 + 12 * N)}
+
+
+def bench_sparse_mesh(args, torch, np):
+    """Large sparse mesh (16384 cores of 256x256 on a 128x128 mesh, 64
+    samples): the event-driven path against dense MFMA integration, each as
+    graph replays of a 10-tick chunk with the inputs resident in HBM."""
+    from paper_2404_16208_amd import workloads as W
+    from paper_2404_16208_amd.ranc import RancNet
+
+    S, T = 64, 10
+    print("[bench] generating the 16384-core sparse mesh and 64x10 inputs", file=sys.stderr, flush=True)
+    net = W.sparse_mesh_net(0)
+    x = W.sparse_mesh_inputs(0, net, S, T)
+    ext_bits = float(np.unpackbits(x.view(np.uint8)).sum())
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    C, A = net.num_cores, net.num_axons
+    out = {"metric": "synaptic events/s and ms per tick, large sparse mesh: event-driven vs dense MFMA",
+           "unit": "synaptic events/s", "n_gpus": 1, "data": "synthetic", "dtype": "int32 (sparse), int8 (mfma)",
+           "config": {"workload": "16384-core sparse mesh (128x128 cores of 256 axons x 256 neurons, crossbar "
+                                  "density 0.05, delays 1-15, input rate 1-5% per sample), 64 samples x 10 ticks "
+                                  "per step", "cores": C, "samples": S, "ticks_per_step": T},
+           "steps": args.steps, "warmup": args.warmup}
+    for path in ("sparse", "mfma"):
+        print(f"[bench] {path} path", file=sys.stderr, flush=True)
+        g = RancNet(net, S, T, path=path)
+        ms, delta, prof = time_steps(g, xd, T, args.warmup, args.steps, torch, graph=True)
+        ticks = args.steps * T
+        per_tick = prof["graph_ms"] / max(1, prof["graph_launches"] * T)
+        byts = sparse_mesh_algorithmic_bytes(net, S, delta["delivered"] / ticks, ext_bits)[path]
+        out[path] = {"value": delta["events"] / (ms / 1e3), "ms_per_tick": ms / ticks,
+                     "core_ticks_per_s": S * C * ticks / (ms / 1e3),
+                     "integrate_avg_ms": per_tick,
+                     "roofline": {"bound": "hbm", "achieved": byts / (per_tick / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": byts / (per_tick / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                  "algorithmic_bytes_per_launch": byts},
+                     "delivered_axon_rate": delta["delivered"] / (S * C * A * ticks),
+                     "input_axon_rate": ext_bits / (S * C * A * T),
+                     "spike_rate": delta["emitted"] / (S * C * net.num_neurons * ticks)}
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    out["value"] = out["sparse"]["value"]
+    out["ms_per_step"] = out["sparse"]["ms_per_tick"] * T
+    out["sparse_speedup_vs_mfma"] = out["mfma"]["ms_per_tick"] / out["sparse"]["ms_per_tick"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +218,10 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=16)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time per-launch calls instead of graph replays")
+    ap.add_argument("--workload", default="mnist512", choices=["mnist512", "sparse-mesh"],
+                    help="mnist512: the headline line (default); sparse-mesh: the event-driven vs dense "
+                         "comparison on the 16384-core mesh")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -170,6 +240,9 @@ def main():
     from paper_2404_16208_amd.ranc import RancNet
 
     torch.cuda.set_device(0)
+    if args.workload == "sparse-mesh":
+        bench_sparse_mesh(args, torch, np)
+        return
     S, T = args.samples, args.ticks
     print(f"[bench] generating 512-core net and {S}x{T} inputs", file=sys.stderr, flush=True)
     net = W.mnist_net(0)
@@ -188,15 +261,24 @@ def main():
 
     print("[bench] mfma path: load + warmup + timed steps", file=sys.stderr, flush=True)
     g = RancNet(net, S, T, path="mfma")
-    ms, delta = time_steps(g, xd, T, args.warmup, args.steps, torch)
-    prof = kernel_profile(g, xd, T, max(2, min(args.steps, 10)), torch)
+    graph = not args.no_graph
+    ms, delta, prof = time_steps(g, xd, T, args.warmup, args.steps, torch, graph=graph)
     secs = ms / 1e3
     events_per_s = delta["events"] / secs
     core_ticks = S * C * T * args.steps
     ib = integrate_algorithmic_bytes(net, S, "mfma")
-    avg_int_ms = prof["integrate_ms"] / max(1, prof["integrate_launches"])
+    if graph:
+        # graph launches hold T integration launches and one tick-advance
+        # launch each: the per-tick share bounds the kernel's duration from above
+        avg_int_ms = prof["graph_ms"] / max(1, prof["graph_launches"] * T)
+        launches = prof["graph_launches"] * T
+    else:
+        avg_int_ms = prof["integrate_ms"] / max(1, prof["integrate_launches"])
+        launches = prof["integrate_launches"]
     avg_route_ms = prof["route_ms"] / max(1, prof["route_launches"])
     achieved = ib["total"] / (avg_int_ms / 1e3) / 1e9
+    eprof = kernel_profile(g, xd, T, max(2, min(args.steps, 10)), torch)
+    eager_int_ms = eprof["integrate_ms"] / max(1, eprof["integrate_launches"])
     src_hash = kernel_source_hash()
     traffic = read_traffic(src_hash)
     out = {
@@ -219,8 +301,13 @@ def main():
         "core_ticks_per_s": core_ticks / secs,
         "synaptic_events_per_step": delta["events"] / args.steps,
         "spikes_emitted_per_step": delta["emitted"] / args.steps,
+        "tick_loop": "hip graph replay" if graph else "per-tick launches",
         "kernels": {"integrate_mfma_avg_ms": avg_int_ms, "route_avg_ms": avg_route_ms,
-                    "launches_profiled": prof["integrate_launches"]},
+                    "launches_timed": launches,
+                    "timing": ("graph launch time / ticks, HIP events on the launch stream over the timed steps"
+                               if graph else "HIP events around each launch over the timed steps"),
+                    "integrate_mfma_eager_avg_ms": eager_int_ms,
+                    "eager_launches_profiled": eprof["integrate_launches"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (traffic / (avg_int_ms / 1e3) / 1e9) if traffic else None,
@@ -237,8 +324,7 @@ def main():
         print("[bench] plain path", file=sys.stderr, flush=True)
         gp = RancNet(net, S, T, path="plain")
         psteps = max(2, args.steps // 4)
-        pms, pdelta = time_steps(gp, xd, T, 1, psteps, torch)
-        pprof = kernel_profile(gp, xd, T, 2, torch)
+        pms, pdelta, pprof = time_steps(gp, xd, T, 1, psteps, torch)
         pint = pprof["integrate_ms"] / max(1, pprof["integrate_launches"])
         pib = integrate_algorithmic_bytes(net, S, "plain")
         out["plain"] = {"value": pdelta["events"] / (pms / 1e3), "unit": "synaptic events/s",

@@ -53,11 +53,20 @@ enum { RANC_DEST_NONE = 0, RANC_DEST_CORE = 1, RANC_DEST_OUT = 2 };
 enum {
     RANC_PATH_AUTO = 0,   /* pick per shape */
     RANC_PATH_PLAIN = 1,  /* per (core, sample) workgroups, crossbar words and popcounts */
-    RANC_PATH_MFMA = 2    /* per-core workgroups over sample tiles, exact int8 MFMA */
+    RANC_PATH_MFMA = 2,   /* per-core workgroups over sample tiles, exact int8 MFMA */
+    RANC_PATH_SPARSE = 3  /* per-core workgroups over sample tiles, event-driven: only spiking
+                             axons are visited (never chosen by RANC_PATH_AUTO) */
 };
 
 /* Flags of ranc_run_ticks. */
 #define RANC_INPUTS_ON_DEVICE 1u
+/* Run the call's ticks as one HIP graph: the tick loop for a given
+ * (num_ticks, input address) is captured on first use (on a stream the
+ * library owns, never on the caller's) and replayed with one graph launch on
+ * `stream` afterwards. The scheduler slot and raster row of each tick are
+ * read from a tick counter kept in the workspace, so a replay is exact from
+ * any starting tick. Results are identical to the per-launch form. */
+#define RANC_RUN_GRAPH 2u
 
 /*
  * Network description (host memory; the library copies it during
@@ -147,6 +156,18 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples,
  * RANC_INPUTS_ON_DEVICE, else in host memory (copied to the workspace's
  * staging area first). Consecutive calls continue the same simulation:
  * spikes whose delivery tick lies beyond the call stay scheduled.
+ * flags: RANC_INPUTS_ON_DEVICE, RANC_RUN_GRAPH (see above); other bits are
+ * rejected with RANC_EINVAL. With RANC_RUN_GRAPH and device inputs, the
+ * input buffer must stay at the same address to reuse a captured loop.
+ *
+ * With num_nets > 1 the networks (any shapes, paths and sample counts; each
+ * at most once) advance together: per tick, one persistent launch runs the
+ * units of every MFMA-path network from a shared work queue (largest units
+ * first), and one launch each integrates and routes every plain-path
+ * network. The batch tables are kept in the workspace of nets[0] (at most
+ * 128 networks per path); they are rebuilt, with a synchronization of
+ * `stream`, whenever the list of networks, the input addresses or num_ticks
+ * change. Results are identical to running each network alone.
  * Returns after queueing the work on `stream`.
  */
 ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets,
@@ -176,12 +197,15 @@ ranc_status ranc_current_tick(const ranc_net *net, int64_t *tick);
 ranc_status ranc_get_path(const ranc_net *net, int32_t *path);
 
 /* Kernel timing, recorded with HIP events on the launch stream around every
- * integration and routing launch while enabled. */
+ * integration and routing launch (per-launch form) or every tick-loop graph
+ * launch (RANC_RUN_GRAPH) while enabled. */
 typedef struct ranc_profile {
     double integrate_ms;         /* summed duration of integration launches */
     double route_ms;             /* summed duration of routing launches */
     int64_t integrate_launches;
     int64_t route_launches;
+    double graph_ms;             /* summed duration of tick-loop graph launches */
+    int64_t graph_launches;
 } ranc_profile;
 
 /* Enable (1) or disable (0) timing; enabling clears the totals. Host-side only. */
@@ -189,6 +213,34 @@ ranc_status ranc_profile_enable(ranc_net *net, int32_t enable);
 
 /* Totals since timing was enabled. Synchronizes the stream of the last run. */
 ranc_status ranc_profile_read(ranc_net *net, ranc_profile *out);
+
+/* Launch shape of a handle (path specific; fields of the other path are 0). */
+typedef struct ranc_tune {
+    int32_t samples_per_wg;          /* MFMA path: samples per workgroup (multiple of 64, <= 512) */
+    int32_t route_samples_per_block; /* plain path router: samples per block (1, 2, 4, 8) */
+    int32_t route_split;             /* plain path router: blocks sharing one group of samples */
+    int32_t route_stage;             /* plain path router: spike bitmaps staged in LDS (0/1) */
+    double ms_per_tick;              /* ranc_autotune: time per tick of the chosen shape */
+    int32_t candidates;              /* ranc_autotune: number of shapes timed */
+} ranc_tune;
+
+/*
+ * Autotuner: time every candidate launch shape of the handle's path (MFMA:
+ * samples per workgroup; plain: router samples per block x split x LDS
+ * staging) on num_ticks ticks of `inputs` (as for ranc_run_ticks; flags may
+ * hold RANC_INPUTS_ON_DEVICE), each from the initial state after one untimed
+ * pass, and keep the fastest. Results never depend on the shape. Leaves every
+ * instance in its initial state (as ranc_reset_state) and drops captured
+ * tick loops. Synchronizes `stream`; *out receives the chosen shape.
+ */
+ranc_status ranc_autotune(ranc_net *net, const uint32_t *inputs, uint32_t flags, int32_t num_ticks,
+                          void *stream, ranc_tune *out);
+
+/* Set a launch shape (e.g. one cached from an earlier ranc_autotune) or read
+ * the current one. Setting validates the shape (RANC_EINVAL) and drops
+ * captured tick loops; the simulation state is unchanged. */
+ranc_status ranc_set_launch_shape(ranc_net *net, const ranc_tune *shape);
+ranc_status ranc_get_launch_shape(const ranc_net *net, ranc_tune *out);
 
 /* Return every instance to its initial state (queued on `stream`). */
 ranc_status ranc_reset_state(ranc_net *net, void *stream);

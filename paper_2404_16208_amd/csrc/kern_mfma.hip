@@ -52,6 +52,7 @@
 // p = r + 16*(l/32) of a neuron's 32-sample spike word is therefore sample
 // sigma(p) = 8*((p%16)/4) + 4*(p/16) + p%4 of the 32-sample group.
 #include "kern_common.h"
+#include "kern_bits.h"
 #include "ranc_internal.h"
 
 namespace ranc {
@@ -72,41 +73,30 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 int mfma_max_samples_per_wg() { return MFMA_SPW_MAX; }
 
-// sample (within its 32-sample group) of bit b of a spike word
-__device__ inline int sigma32(int b) { return 8 * ((b & 15) >> 2) + 4 * (b >> 4) + (b & 3); }
-
-// One stage of a recursive bit-matrix transpose: lanes whose index has bit K
-// clear exchange the bits with index bit K set for their partner's (lane ^ K)
-// bits with index bit K clear.
-template <int K>
-__device__ inline uint32_t transpose_stage(uint32_t x, int lane)
-{
-    constexpr uint32_t M = K == 16 ? 0x0000FFFFu : K == 8 ? 0x00FF00FFu : K == 4 ? 0x0F0F0F0Fu
-                         : K == 2  ? 0x33333333u : 0x55555555u;
-    // ds_swizzle bit-mask mode: partner = lane ^ K within each 32-lane half
-    const uint32_t p = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1F | (K << 10));
-    const bool up = (lane & K) != 0;
-    const uint32_t r = __builtin_rotateright32(p, up ? K : 32 - K);
-    const uint32_t keep = up ? ~M : M;
-    return (x & keep) | (r & ~keep);
-}
-
-// 32 x 32 bit transpose within each half-wave: lane i of a half receives, as
-// bit j, bit i of lane j of the same half. Every lane must be active.
-__device__ inline uint32_t transpose32(uint32_t x, int lane)
-{
-    x = transpose_stage<16>(x, lane);
-    x = transpose_stage<8>(x, lane);
-    x = transpose_stage<4>(x, lane);
-    x = transpose_stage<2>(x, lane);
-    return transpose_stage<1>(x, lane);
-}
-
 template <bool WIDE> struct RawWord { typedef uint32_t type; };
 template <> struct RawWord<true> { typedef uint64_t type; };
 
-template <int A_, int N_, bool TWO>
-__global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, int spw)
+// LDS of one workgroup, by shape.
+template <int A_, int N_> struct MfmaLds {
+    static constexpr int STW = N_ / 128;   // 32-sample sub-tiles per wave per tile
+    static constexpr int ROWB = A_ + 16;   // padded LDS row of the int8 tile (bytes)
+    static constexpr int XW = A_ / 32 + 1; // padded axon words per sample
+    typedef int8_t ATile[MFMA_TS * ROWB];  // int8 axon spikes of a tile (x2, double buffer)
+    typedef v4i VTile[STW][4][64];         // next tile's potentials (one per wave)
+    typedef uint32_t XTile[MFMA_TS][XW];   // delivered axon words of a tile (x2)
+};
+
+// One unit of work: workgroup `bid` of the tick's grid (core bid % C, sample
+// chunk bid / C), on 512 threads. The LDS arrays come from the calling
+// kernel, so several shapes can share one kernel's LDS.
+// CLAMP: potentials narrower than 32 bits are clamped to [vmin, vmax] after
+// the saturating 32-bit add (with 32-bit potentials the add alone is exact).
+template <int A_, int N_, bool TWO, bool CLAMP>
+__device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickArgs &ta, int spw, int bid,
+                                                    typename MfmaLds<A_, N_>::ATile *a_lds,
+                                                    typename MfmaLds<A_, N_>::VTile *v_lds,
+                                                    typename MfmaLds<A_, N_>::XTile *x_lds,
+                                                    unsigned (*s_cnt)[MFMA_SPW_MAX])
 {
     constexpr int NB = N_ / 32;          // 32-neuron blocks (4 or 8)
     constexpr int KS = A_ / 32;          // 32-axon k-steps
@@ -120,17 +110,13 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
     typedef typename RawWord<GPW == 2>::type RawT;
     static_assert(NB == 4 || NB == 8, "N must be 128 or 256");
 
-    __shared__ __attribute__((aligned(16))) int8_t a_lds[2][MFMA_TS * ROWB];
-    __shared__ __attribute__((aligned(16))) v4i v_lds[8][STW][4][64];   // next tile's potentials, per wave
-    __shared__ uint32_t x_lds[2][MFMA_TS][W_ + 1];                     // delivered axon words per sample
-    // per sample of the chunk: [0] emitted | routed << 10 | out << 20 (each
-    // <= N per tick), [1] events | delivered << 18 (<= 512*256 and <= 512)
-    __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
+    // s_cnt, per sample of the chunk: [0] emitted | routed << 10 | out << 20
+    // (each <= N per tick), [1] events | delivered << 18 (<= 512*256, <= 512)
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x % n.C;
-    const int chunk = blockIdx.x / n.C;
+    const int c = bid % n.C;
+    const int chunk = bid / n.C;
     const int s_begin = chunk * spw;
     const int s_end = min(n.S, s_begin + spw);
     const int h = lane >> 5, jj = lane & 31;
@@ -174,15 +160,16 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
 
     const int ci = n.in_index[c];
     const uint32_t *ext_c = (ta.ext_t != nullptr && ci >= 0) ? ta.ext_t + (size_t)ci * W_ : nullptr;
+    const int q_now = tick_slot(n, ta.k), r_row = tick_row(n, ta.k);
     const size_t G32 = (size_t)n.S64 / 32;   // 32-sample groups
     const size_t HG = (size_t)n.S64 / 64;    // 64-sample history words per neuron
     const size_t vbase = ((size_t)c * NB + nb) * G32 * 256 + lane;
     const v4i *vb_in = reinterpret_cast<const v4i *>(n.V) + vbase;
     v4i *vb_out = reinterpret_cast<v4i *>(n.V) + vbase;
     const size_t CN = (size_t)n.C * N_;
-    uint64_t *hist_out = n.hist + ((size_t)ta.q_now * CN + cj) * HG;
+    uint64_t *hist_out = n.hist + ((size_t)q_now * CN + cj) * HG;
     uint64_t *rast_out =
-        oi >= 0 ? reinterpret_cast<uint64_t *>(n.raster) + ((size_t)ta.r_row * n.Nout + oi) * HG : nullptr;
+        oi >= 0 ? reinterpret_cast<uint64_t *>(n.raster) + ((size_t)r_row * n.Nout + oi) * HG : nullptr;
 
     // ---- history gather: wave w collects, for axon block w % APW, the
     // history bits of group w / APW of each tile (both groups when A = 512).
@@ -204,7 +191,7 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
         src_row[k] = n.hist_zero;
         if (e_beg + k < e_end) {
             const uint32_t ent = n.rtx_ent[e_beg + k];
-            int slot = ta.q_now - (int)(ent & 15u) - 1;
+            int slot = q_now - (int)(ent & 15u) - 1;
             if (slot < 0)
                 slot += n.Q;
             src_row[k] = n.hist + ((size_t)slot * CN + (ent >> 4)) * HG;
@@ -231,7 +218,7 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
                 raw[k] = raw_word(src_row[k], tile);
             for (uint32_t e = e_beg + FMAX; long_lists && e < e_end; ++e) {
                 const uint32_t ent = n.rtx_ent[e];
-                int slot = ta.q_now - (int)(ent & 15u) - 1;
+                int slot = q_now - (int)(ent & 15u) - 1;
                 if (slot < 0)
                     slot += n.Q;
                 raw[1] |= raw_word(n.hist + ((size_t)slot * CN + (ent >> 4)) * HG, tile);
@@ -419,17 +406,25 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
                     acc_lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][0], acc_lo, 0, 0, 0);
                 }
             }
-            const bool partial = sg * 32 + 32 > s_end;   // wave-uniform
+            // spike bits r of this lane, built from r = 15 down by doubling
             uint32_t hb = 0;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 15; r >= 0; --r) {
                 const int32_t in_leak = TWO ? acc_lo[r] + acc_hi[r] * 128 : acc_lo[r];
-                int32_t vn;
-                bool fire = lif_update(vold[t][r >> 2][r & 3], in_leak, 0, th, rs, vmin, vmax, vn);
-                if (partial)
-                    fire = fire && (sg * 32 + 8 * (r >> 2) + 4 * h + (r & 3) < s_end);
-                vnew[t][r >> 2][r & 3] = vn;
-                hb |= (uint32_t)fire << r;
+                int32_t u = __builtin_elementwise_add_sat(vold[t][r >> 2][r & 3], in_leak);
+                if constexpr (CLAMP)
+                    u = min(max(u, vmin), vmax);
+                const bool fire = u >= th;
+                vnew[t][r >> 2][r & 3] = fire ? rs : u;
+                hb = hb + hb + (uint32_t)fire;
+            }
+            // samples past the end never fire (their potentials are never read)
+            if (sg * 32 + 32 > s_end) {   // wave-uniform
+                uint32_t vm = 0;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    vm |= (uint32_t)(sg * 32 + 8 * (r >> 2) + 4 * h + (r & 3) < s_end) << r;
+                hb &= vm;
             }
             // the neuron's spike word: bits r from lane jj, bits 16 + r from lane jj + 32
             const uint32_t hw = hb | ((uint32_t)__shfl_xor((int)hb, 32, 64) << 16);
@@ -454,6 +449,106 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
     }
 }
 
+template <int A_, int N_, bool TWO, bool CLAMP>
+__global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, int spw)
+{
+    typedef MfmaLds<A_, N_> L;
+    __shared__ __attribute__((aligned(16))) typename L::ATile a_lds[2];
+    __shared__ __attribute__((aligned(16))) typename L::VTile v_lds[8];
+    __shared__ typename L::XTile x_lds[2];
+    __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
+    integrate_mfma_unit<A_, N_, TWO, CLAMP>(n, ta, spw, blockIdx.x, a_lds, v_lds, x_lds, s_cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Several networks (shapes may differ) advanced by one tick in one persistent
+// launch: a grid of one workgroup per CU pulls units (network, workgroup of
+// that network's tick grid) from a queue counter until every unit is done.
+// Units are numbered network after network in the order of the batch table,
+// which the host sorts by decreasing cost per unit, so the largest units go
+// first. LDS is sized for the largest shape; each unit uses it through views
+// of its own shape.
+
+int mfma_shape_code(int A, int N, int two_planes)
+{
+    const int ai = A == 64 ? 0 : A == 128 ? 1 : A == 256 ? 2 : 3;
+    return (ai * 2 + (N == 256 ? 1 : 0)) * 2 + (two_planes ? 1 : 0);
+}
+
+template <int A_, int N_, bool TWO>
+__device__ __forceinline__ void batch_unit(const BatchEntry &e, const TickArgs &ta, int bid, int8_t *a_raw,
+                                           v4i *v_raw, uint32_t *x_raw, unsigned (*s_cnt)[MFMA_SPW_MAX])
+{
+    typedef MfmaLds<A_, N_> L;
+    integrate_mfma_unit<A_, N_, TWO, true>(e.n, ta, e.spw, bid, reinterpret_cast<typename L::ATile *>(a_raw),
+                                           reinterpret_cast<typename L::VTile *>(v_raw),
+                                           reinterpret_cast<typename L::XTile *>(x_raw), s_cnt);
+}
+
+__global__ __launch_bounds__(512) void k_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k,
+                                                              unsigned *queue)
+{
+    typedef MfmaLds<512, 256> Lmax;
+    __shared__ __attribute__((aligned(16))) int8_t a_raw[2 * sizeof(Lmax::ATile)];
+    __shared__ __attribute__((aligned(16))) v4i v_raw[8 * sizeof(Lmax::VTile) / sizeof(v4i)];
+    __shared__ uint32_t x_raw[2 * sizeof(Lmax::XTile) / 4];
+    __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
+    __shared__ int s_unit;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        queue[(k + 1) & 1] = 0u;   // the next tick's counter (no unit of this launch uses it)
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_unit = (int)atomicAdd(&queue[k & 1], 1u);
+        __syncthreads();
+        const int u = __builtin_amdgcn_readfirstlane(s_unit);
+        __syncthreads();
+        if (u >= total)
+            break;
+        // network of unit u: the last entry whose first unit is <= u
+        int lo = 0, hi = num - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].unit_begin <= u)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchEntry &e = tab[lo];
+        TickArgs ta;
+        ta.k = k;
+        ta.ext_t = e.ext_base ? e.ext_base + (size_t)k * e.tick_words : nullptr;
+        ta.ext_sstride = e.ext_sstride;
+        const int bid = u - e.unit_begin;
+        switch (e.code) {
+        case 0: batch_unit<64, 128, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 1: batch_unit<64, 128, true>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 2: batch_unit<64, 256, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 3: batch_unit<64, 256, true>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 4: batch_unit<128, 128, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 5: batch_unit<128, 128, true>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 6: batch_unit<128, 256, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 7: batch_unit<128, 256, true>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 8: batch_unit<256, 128, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 9: batch_unit<256, 128, true>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 10: batch_unit<256, 256, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 11: batch_unit<256, 256, true>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 12: batch_unit<512, 128, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 14: batch_unit<512, 256, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        default: break;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k, unsigned *queue,
+                                       int workgroups, hipStream_t st)
+{
+    if (num < 1 || total < 1 || workgroups < 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_integrate_mfma_batch, dim3(workgroups), dim3(512), 0, st, tab, num, total, k, queue);
+    return hipGetLastError();
+}
+
 bool mfma_shape_supported(int A, int N, int two_planes)
 {
     const bool ok_a = A == 64 || A == 128 || A == 256 || A == 512;
@@ -462,20 +557,29 @@ bool mfma_shape_supported(int A, int N, int two_planes)
     return ok_a && (N == 128 || N == 256) && A * (two_planes ? 2 : 1) <= 512;
 }
 
-template <int A_, int N_>
-static hipError_t launch_mfma_an(const DevNet &n, const TickArgs &a, int two, int spw, hipStream_t st)
+template <int A_, int N_, bool TWO>
+static void launch_mfma_k(const DevNet &n, const TickArgs &a, int spw, hipStream_t st)
 {
     const int chunks = (n.S + spw - 1) / spw;
     const dim3 grid(n.C * chunks), block(512);
+    if (n.vmin == INT32_MIN && n.vmax == INT32_MAX)
+        hipLaunchKernelGGL((k_integrate_mfma<A_, N_, TWO, false>), grid, block, 0, st, n, a, spw);
+    else
+        hipLaunchKernelGGL((k_integrate_mfma<A_, N_, TWO, true>), grid, block, 0, st, n, a, spw);
+}
+
+template <int A_, int N_>
+static hipError_t launch_mfma_an(const DevNet &n, const TickArgs &a, int two, int spw, hipStream_t st)
+{
     if constexpr (A_ <= 256) {
         if (two)
-            hipLaunchKernelGGL((k_integrate_mfma<A_, N_, true>), grid, block, 0, st, n, a, spw);
+            launch_mfma_k<A_, N_, true>(n, a, spw, st);
         else
-            hipLaunchKernelGGL((k_integrate_mfma<A_, N_, false>), grid, block, 0, st, n, a, spw);
+            launch_mfma_k<A_, N_, false>(n, a, spw, st);
     } else {
         if (two)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_integrate_mfma<A_, N_, false>), grid, block, 0, st, n, a, spw);
+        launch_mfma_k<A_, N_, false>(n, a, spw, st);
     }
     return hipGetLastError();
 }

@@ -14,18 +14,20 @@
 
 namespace ranc {
 
+// One (core, sample) on a workgroup of at least N threads (threads past N
+// take part in the ballots and the barrier only).
 template <int W_, int G_>
-__global__ __launch_bounds__(512) void k_integrate_plain(DevNet n, TickArgs ta)
+__device__ __forceinline__ void integrate_plain_unit(const DevNet &n, const TickArgs &ta, int c, int s,
+                                                     unsigned (*red)[4])
 {
-    const int c = blockIdx.x;
-    const int s = blockIdx.y;
-    const int j = threadIdx.x;
     const int N = n.N;
+    const int jt = threadIdx.x;
+    const bool live = jt < N;
+    const int j = live ? jt : N - 1;   // idle threads mirror the last neuron's loads
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __shared__ unsigned red[8][4];
 
     // Axon spikes of this tick: scheduler slot t%Q OR the external input.
-    const uint32_t *slot = n.ring + (((size_t)ta.q_now * n.S + s) * n.C + c) * W_;
+    const uint32_t *slot = n.ring + (((size_t)tick_slot(n, ta.k) * n.S + s) * n.C + c) * W_;
     const int ci = n.in_index[c];
     const uint32_t *ext = (ta.ext_t != nullptr && ci >= 0)
                               ? ta.ext_t + (size_t)s * ta.ext_sstride + (size_t)ci * W_
@@ -68,13 +70,16 @@ __global__ __launch_bounds__(512) void k_integrate_plain(DevNet n, TickArgs ta)
     const size_t cj = (size_t)c * N + j;
     const size_t vi = ((size_t)c * n.S + s) * N + j;
     int32_t vnew;
-    const bool fire = lif_update(n.V[vi], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, vnew);
-    n.V[vi] = vnew;
+    const bool fire = lif_update(n.V[vi], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, vnew) && live;
+    if (live)
+        n.V[vi] = vnew;
+    if (!live)
+        ev = 0;
 
     // Spike words (ballot), counters, output raster.
     const unsigned long long b = __ballot(fire);
     ev = wave_sum(ev);
-    if (lane == 0) {
+    if (lane == 0 && wave < (N >> 6)) {
         unsigned em = 0, ro = 0, ou = 0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -88,7 +93,7 @@ __global__ __launch_bounds__(512) void k_integrate_plain(DevNet n, TickArgs ta)
             ou += __popc(om);
             const int ow = n.outword[m];
             if (ow >= 0)
-                n.raster[((size_t)ta.r_row * n.S + s) * n.Wout + ow] = om;
+                n.raster[((size_t)tick_row(n, ta.k) * n.S + s) * n.Wout + ow] = om;
         }
         red[wave][0] = em;
         red[wave][1] = ro;
@@ -98,7 +103,7 @@ __global__ __launch_bounds__(512) void k_integrate_plain(DevNet n, TickArgs ta)
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long em = 0, ro = 0, ou = 0, e = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        for (int w = 0; w < (N >> 6); ++w) {
             em += red[w][0];
             ro += red[w][1];
             ou += red[w][2];
@@ -111,6 +116,62 @@ __global__ __launch_bounds__(512) void k_integrate_plain(DevNet n, TickArgs ta)
         cp[CNT_OUT] += ou;
         cp[CNT_EVENTS] += e;
     }
+}
+
+template <int W_, int G_>
+__global__ __launch_bounds__(512) void k_integrate_plain(DevNet n, TickArgs ta)
+{
+    __shared__ unsigned red[8][4];
+    integrate_plain_unit<W_, G_>(n, ta, blockIdx.x, blockIdx.y, red);
+}
+
+int plain_shape_code(int W, int G)
+{
+    const int wi = W == 2 ? 0 : W == 4 ? 1 : W == 8 ? 2 : 3;
+    const int gi = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : 3;
+    return wi * 4 + gi;
+}
+
+// Several networks on the plain path, one tick, one launch: unit u is
+// (core, sample) of the network whose unit range holds u.
+__global__ __launch_bounds__(512) void k_integrate_plain_batch(const BatchEntry *tab, int num, int k)
+{
+    __shared__ unsigned red[8][4];
+    const int u = blockIdx.x;
+    int lo = 0, hi = num - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].unit_begin <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchEntry &e = tab[lo];
+    const int local = u - e.unit_begin;
+    const int c = local % e.n.C, s = local / e.n.C;
+    TickArgs ta;
+    ta.k = k;
+    ta.ext_t = e.ext_base ? e.ext_base + (size_t)k * e.tick_words : nullptr;
+    ta.ext_sstride = e.ext_sstride;
+    switch (e.code) {
+#define RANC_PLAIN_CASE(WI, W, GI, G) \
+    case WI * 4 + GI: integrate_plain_unit<W, G>(e.n, ta, c, s, red); break;
+        RANC_PLAIN_CASE(0, 2, 0, 1) RANC_PLAIN_CASE(0, 2, 1, 2) RANC_PLAIN_CASE(0, 2, 2, 4) RANC_PLAIN_CASE(0, 2, 3, 8)
+        RANC_PLAIN_CASE(1, 4, 0, 1) RANC_PLAIN_CASE(1, 4, 1, 2) RANC_PLAIN_CASE(1, 4, 2, 4) RANC_PLAIN_CASE(1, 4, 3, 8)
+        RANC_PLAIN_CASE(2, 8, 0, 1) RANC_PLAIN_CASE(2, 8, 1, 2) RANC_PLAIN_CASE(2, 8, 2, 4) RANC_PLAIN_CASE(2, 8, 3, 8)
+        RANC_PLAIN_CASE(3, 16, 0, 1) RANC_PLAIN_CASE(3, 16, 1, 2) RANC_PLAIN_CASE(3, 16, 2, 4)
+        RANC_PLAIN_CASE(3, 16, 3, 8)
+#undef RANC_PLAIN_CASE
+    default: break;
+    }
+}
+
+hipError_t launch_integrate_plain_batch(const BatchEntry *tab, int num, int total, int k, hipStream_t st)
+{
+    if (num < 1 || total < 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_integrate_plain_batch, dim3(total), dim3(512), 0, st, tab, num, k);
+    return hipGetLastError();
 }
 
 template <int W_>

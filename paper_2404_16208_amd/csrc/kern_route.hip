@@ -33,10 +33,10 @@ static constexpr size_t ROUTE_LDS_BYTES = 128 * 1024;
 // statically), then OR all non-zero words into their scheduler slots together
 // so their read-modify-writes overlap.
 template <int SB, int DMAX, bool STAGE>
-__global__ __launch_bounds__(ROUTE_THREADS) void k_route(DevNet n, int q_now)
+__device__ __forceinline__ void route_unit(const DevNet &n, int k, int bx, int by, int gx, uint32_t *sp)
 {
-    extern __shared__ uint32_t sp[];
-    const int s_base = blockIdx.y * SB;
+    const int q_now = tick_slot(n, k);
+    const int s_base = by * SB;
     const int nsb = min(SB, n.S - s_base);
     const size_t words = (size_t)n.C * n.NW;
     const uint32_t *spk = n.spk + (size_t)s_base * words;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route(DevNet n, int q_now)
     const int CW = n.C * n.W;
     const size_t slot_stride = (size_t)n.S * CW;
     uint32_t *ring_b = n.ring + (size_t)s_base * CW;
-    for (int dw = blockIdx.x * blockDim.x + threadIdx.x; dw < CW; dw += gridDim.x * blockDim.x) {
+    for (int dw = bx * ROUTE_THREADS + threadIdx.x; dw < CW; dw += gx * ROUTE_THREADS) {
 #pragma unroll
         for (int b = 0; b < SB; ++b)
             if (b < nsb)
@@ -97,7 +97,98 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route(DevNet n, int q_now)
     }
 }
 
+template <int SB, int DMAX, bool STAGE>
+__global__ __launch_bounds__(ROUTE_THREADS) void k_route(DevNet n, int k)
+{
+    extern __shared__ uint32_t sp[];
+    route_unit<SB, DMAX, STAGE>(n, k, blockIdx.x, blockIdx.y, gridDim.x, sp);
+}
+
 int route_dmax(int D) { return D <= 4 ? 4 : D <= 8 ? 8 : 16; }
+
+// Router variants usable in a batch launch: (samples per block, delay
+// registers) with SB * DMAX <= 32, staged or not.
+static constexpr int ROUTE_VARIANTS[9][2] = {{1, 4}, {1, 8}, {1, 16}, {2, 4}, {2, 8}, {2, 16}, {4, 4}, {4, 8}, {8, 4}};
+
+int route_shape_code(const RouteCfg &cfg, int max_delay)
+{
+    const int dmax = route_dmax(max_delay);
+    for (int i = 0; i < 9; ++i)
+        if (ROUTE_VARIANTS[i][0] == cfg.samples_per_block && ROUTE_VARIANTS[i][1] == dmax)
+            return i * 2 + (cfg.stage ? 1 : 0);
+    return -1;
+}
+
+// Several plain-path networks routed in one launch: unit u is block
+// (x, y) of the network whose router unit range holds u.
+__global__ __launch_bounds__(ROUTE_THREADS) void k_route_batch(const BatchEntry *tab, int num, int k)
+{
+    extern __shared__ uint32_t sp[];
+    const int u = blockIdx.x;
+    int lo = 0, hi = num - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].route_begin <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchEntry &e = tab[lo];
+    const int local = u - e.route_begin;
+    const int bx = local % e.route_split, by = local / e.route_split;
+    switch (e.route_code) {
+#define RANC_ROUTE_CASE(I, SB, D)                                                      \
+    case 2 * I: route_unit<SB, D, false>(e.n, k, bx, by, e.route_split, sp); break; \
+    case 2 * I + 1: route_unit<SB, D, true>(e.n, k, bx, by, e.route_split, sp); break;
+        RANC_ROUTE_CASE(0, 1, 4) RANC_ROUTE_CASE(1, 1, 8) RANC_ROUTE_CASE(2, 1, 16) RANC_ROUTE_CASE(3, 2, 4)
+        RANC_ROUTE_CASE(4, 2, 8) RANC_ROUTE_CASE(5, 2, 16) RANC_ROUTE_CASE(6, 4, 4) RANC_ROUTE_CASE(7, 4, 8)
+        RANC_ROUTE_CASE(8, 8, 4)
+#undef RANC_ROUTE_CASE
+    default: break;
+    }
+}
+
+hipError_t launch_route_batch(const BatchEntry *tab, int num, int total, int k, size_t lds_bytes, hipStream_t st)
+{
+    if (num < 1 || total < 1 || lds_bytes > ROUTE_LDS_BYTES)
+        return hipErrorInvalidValue;
+    if (lds_bytes > 64 * 1024) {
+        static bool raised = false;
+        if (!raised) {
+            hipError_t e = hipFuncSetAttribute((const void *)k_route_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)ROUTE_LDS_BYTES);
+            if (e != hipSuccess)
+                return e;
+            raised = true;
+        }
+    }
+    hipLaunchKernelGGL(k_route_batch, dim3(total), dim3(ROUTE_THREADS), lds_bytes, st, tab, num, k);
+    return hipGetLastError();
+}
+
+// End of a batch call: every network's tick moves forward, and the batch
+// queue counters are cleared for the next call.
+__global__ void k_advance_batch(const BatchEntry *tab, int num, int num_ticks, unsigned *queue)
+{
+    for (int i = threadIdx.x; i < num; i += blockDim.x) {
+        int *t = tab[i].n.tick;
+        t[0] = (t[0] + num_ticks) % tab[i].n.Q;
+        t[1] = (t[1] + num_ticks) % tab[i].n.RT;
+        const unsigned long long v = ((unsigned long long)(unsigned)t[3] << 32 | (unsigned)t[2]) + (unsigned)num_ticks;
+        t[2] = (int)(unsigned)v;
+        t[3] = (int)(unsigned)(v >> 32);
+    }
+    if (threadIdx.x == 0) {
+        queue[0] = 0u;
+        queue[1] = 0u;
+    }
+}
+
+hipError_t launch_advance_batch(const BatchEntry *tab, int num, int num_ticks, unsigned *queue, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance_batch, dim3(1), dim3(256), 0, st, tab, num, num_ticks, queue);
+    return hipGetLastError();
+}
 
 RouteCfg route_default_cfg(const DevNet &n)
 {
@@ -123,7 +214,7 @@ RouteCfg route_default_cfg(const DevNet &n)
 }
 
 template <int SB, int DMAX, bool STAGE>
-static hipError_t launch_route_v(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st)
+static hipError_t launch_route_v(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st)
 {
     const dim3 grid(cfg.blocks_per_group, (n.S + SB - 1) / SB);
     const size_t lds = STAGE ? (size_t)n.C * n.NW * 4 * SB : 0;
@@ -137,32 +228,32 @@ static hipError_t launch_route_v(const DevNet &n, int q_now, const RouteCfg &cfg
             raised = true;
         }
     }
-    hipLaunchKernelGGL((k_route<SB, DMAX, STAGE>), grid, dim3(ROUTE_THREADS), lds, st, n, q_now);
+    hipLaunchKernelGGL((k_route<SB, DMAX, STAGE>), grid, dim3(ROUTE_THREADS), lds, st, n, k);
     return hipGetLastError();
 }
 
 template <int SB, int DMAX>
-static hipError_t launch_route_sd(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st)
+static hipError_t launch_route_sd(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st)
 {
     // more than 32 accumulators per lane would spill
     if constexpr (SB * DMAX <= 32)
-        return cfg.stage ? launch_route_v<SB, DMAX, true>(n, q_now, cfg, st)
-                         : launch_route_v<SB, DMAX, false>(n, q_now, cfg, st);
+        return cfg.stage ? launch_route_v<SB, DMAX, true>(n, k, cfg, st)
+                         : launch_route_v<SB, DMAX, false>(n, k, cfg, st);
     else
         return hipErrorInvalidValue;
 }
 
 template <int SB>
-static hipError_t launch_route_s(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st)
+static hipError_t launch_route_s(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st)
 {
     switch (route_dmax(n.D)) {
-    case 4: return launch_route_sd<SB, 4>(n, q_now, cfg, st);
-    case 8: return launch_route_sd<SB, 8>(n, q_now, cfg, st);
-    default: return launch_route_sd<SB, 16>(n, q_now, cfg, st);
+    case 4: return launch_route_sd<SB, 4>(n, k, cfg, st);
+    case 8: return launch_route_sd<SB, 8>(n, k, cfg, st);
+    default: return launch_route_sd<SB, 16>(n, k, cfg, st);
     }
 }
 
-hipError_t launch_route(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st)
+hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st)
 {
     if (cfg.blocks_per_group < 1)
         return hipErrorInvalidValue;
@@ -171,10 +262,10 @@ hipError_t launch_route(const DevNet &n, int q_now, const RouteCfg &cfg, hipStre
     if ((n.S + cfg.samples_per_block - 1) / cfg.samples_per_block > 65535)
         return hipErrorInvalidValue;
     switch (cfg.samples_per_block) {
-    case 1: return launch_route_s<1>(n, q_now, cfg, st);
-    case 2: return launch_route_s<2>(n, q_now, cfg, st);
-    case 4: return launch_route_s<4>(n, q_now, cfg, st);
-    case 8: return launch_route_s<8>(n, q_now, cfg, st);
+    case 1: return launch_route_s<1>(n, k, cfg, st);
+    case 2: return launch_route_s<2>(n, k, cfg, st);
+    case 4: return launch_route_s<4>(n, k, cfg, st);
+    case 8: return launch_route_s<8>(n, k, cfg, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -182,7 +273,8 @@ hipError_t launch_route(const DevNet &n, int q_now, const RouteCfg &cfg, hipStre
 __global__ void k_reset_potentials(DevNet n)
 {
     const bool brick = n.vlayout == VLAYOUT_BRICK;
-    const size_t total = (size_t)n.C * (brick ? n.S64 : n.S) * n.N;
+    const size_t SV = n.vlayout == VLAYOUT_CSN ? (size_t)n.S : (size_t)n.S64;   // samples per core
+    const size_t total = (size_t)n.C * SV * n.N;
     const int NB = n.N / 32;
     const size_t groups = (size_t)n.S64 / 32;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -195,7 +287,7 @@ __global__ void k_reset_potentials(DevNet n)
             c = cnb / NB;
             j = (cnb % NB) * 32 + (lane & 31);
         } else {
-            c = i / ((size_t)n.S * n.N);
+            c = i / (SV * n.N);
             j = i % n.N;
         }
         n.V[i] = n.vinit[c * n.N + j];
@@ -212,7 +304,7 @@ __global__ void k_fill_u32(uint32_t *p, size_t count)
 hipError_t launch_reset_state(const DevNet &n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reset_potentials, dim3(2048), dim3(256), 0, st, n);
-    const bool hist = n.vlayout == VLAYOUT_BRICK;
+    const bool hist = n.vlayout != VLAYOUT_CSN;
     const size_t ring_words = hist ? 0 : (size_t)n.Q * n.S * n.C * n.W;
     const size_t spk_words = hist ? 0 : (size_t)n.S * n.C * n.NW;
     const size_t hist_words = hist ? (size_t)n.Q * n.C * n.N * (n.S64 / 64) * 2 : 0;
@@ -227,6 +319,26 @@ hipError_t launch_reset_state(const DevNet &n, hipStream_t st)
     if (raster_words)
         hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, n.raster, raster_words);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, (uint32_t *)n.cnt, cnt_words);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)n.tick, (size_t)4);
+    return hipGetLastError();
+}
+
+// End of a call of num_ticks ticks: move the device tick forward.
+__global__ void k_advance_tick(DevNet n, int num_ticks)
+{
+    if (threadIdx.x == 0) {
+        n.tick[0] = (n.tick[0] + num_ticks) % n.Q;
+        n.tick[1] = (n.tick[1] + num_ticks) % n.RT;
+        const unsigned long long t =
+            ((unsigned long long)(unsigned)n.tick[3] << 32 | (unsigned)n.tick[2]) + (unsigned)num_ticks;
+        n.tick[2] = (int)(unsigned)t;
+        n.tick[3] = (int)(unsigned)(t >> 32);
+    }
+}
+
+hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance_tick, dim3(1), dim3(64), 0, st, n, num_ticks);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@
 //   degb     u32 [C][2][A/4]   (MFMA path) connected neurons per axon, low byte
 //                              plane then high byte plane, 4 axons per word
 //   planes   int8 MFMA B operand tiles (MFMA path), see kern_mfma.hip
+//   xrow     u32 [C][A][NW]    (sparse path) crossbar rows as given: bit n%32 of word n/32
 //   rtx_ptr  u32 [C*A + 1], rtx_ent u32 [E]  (MFMA path) the same routing table keyed by
 //                              destination axon: entries (source neuron c*N + n) << 4 | (delay - 1)
 // State:
@@ -31,11 +32,12 @@
 //              MFMA:  [C][N/32][S64/32][4][64][4]: brick (c, nb, g) holds 32 samples
 //                     x 32 neurons; element (q, lane l, e) = sample 32g + 8q + 4(l/32) + e,
 //                     neuron 32nb + l%32 (the MFMA result layout)
+//              sparse: [C][S64][N]
 //   plain path:
 //   ring     u32 [Q][S][C][W]  scheduler: slot t%Q holds the axon spikes of tick t
 //   spk      u32 [S][C][NW]    spikes of the current tick
 //   raster   u32 [RT][S][Wout] output-bus spikes of tick t in row t%RT
-//   MFMA path:
+//   MFMA and sparse paths:
 //   hist     u64 [Q][C*N][HG]  spikes of tick t in slot t%Q; word (slot, neuron, i)
 //                              covers samples 64i .. 64i+63, bit p = sample
 //                              64i + 32(p/32) + sigma(p%32) with
@@ -43,6 +45,10 @@
 //   raster   u64 [RT][Nout][HG] output-bus spikes of tick t in row t%RT, words as hist
 //   both:
 //   cnt      u64 [C][S][5]     emitted, routed, delivered, out, events
+//   tick     i32 [4]           scheduler slot (t % Q) and raster row (t % RT) of the
+//                              first tick of the next call, and t as two u32 halves;
+//                              kept on the device so a captured tick loop replays
+//                              correctly from any starting tick
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,7 +57,7 @@
 namespace ranc {
 
 enum { CNT_EMITTED = 0, CNT_ROUTED, CNT_DELIVERED, CNT_OUT, CNT_EVENTS, CNT_N };
-enum { VLAYOUT_CSN = 0, VLAYOUT_BRICK = 1 };
+enum { VLAYOUT_CSN = 0, VLAYOUT_BRICK = 1, VLAYOUT_SPARSE = 2 };
 
 // Routing entry fields.
 static constexpr int RT_POS_BITS = 5, RT_DELAY_SHIFT = 5, RT_SRC_SHIFT = 9;
@@ -68,6 +74,7 @@ struct DevNet {
     const uint16_t *rt_dcnt;
     const uint32_t *rt_goff, *rt_ent;
     const int32_t *outidx;
+    const uint32_t *xrow;        // crossbar rows [C][A][NW] (sparse path)
     const uint32_t *degb;
     const uint4 *planes;
     const uint32_t *rtx_ptr, *rtx_ent;
@@ -77,14 +84,33 @@ struct DevNet {
     uint32_t *ring, *spk, *raster;
     uint64_t *hist;
     unsigned long long *cnt;
+    int *tick;
 };
 
-// Per-tick launch arguments.
+// Per-tick launch arguments: the tick's position k in the call (the tick is
+// the device tick of the call's start plus k, k < RT).
 struct TickArgs {
-    int q_now;              // t % Q
-    int r_row;              // t % RT
+    int k;
     const uint32_t *ext_t;  // external input of this tick for sample 0, or nullptr
     long long ext_sstride;  // words between consecutive samples of the input block
+};
+
+// Scheduler slot and raster row of the tick at position k of the call.
+__device__ inline int tick_slot(const DevNet &n, int k) { return (n.tick[0] + k) % n.Q; }
+__device__ inline int tick_row(const DevNet &n, int k) { return (n.tick[1] + k) % n.RT; }
+
+// One network of a batch advanced together (several networks per launch).
+// unit_begin: the network's first unit in the launch's numbering; code:
+// kernel variant of the network's shape (path specific).
+struct BatchEntry {
+    DevNet n;
+    const uint32_t *ext_base;   // inputs of the call ([S][T][Cin][W]), or nullptr
+    long long tick_words;       // Cin * W
+    long long ext_sstride;      // num_ticks * tick_words
+    int spw;                    // samples per workgroup (MFMA path)
+    int code;
+    int unit_begin, units;      // integration units
+    int route_begin, route_units, route_code, route_split;   // plain path: router units and shape
 };
 
 // Route launch shape (chosen per network by the runtime).
@@ -96,11 +122,23 @@ struct RouteCfg {
 
 // Launchers (return the first HIP error, hipSuccess otherwise).
 hipError_t launch_integrate_plain(const DevNet &n, const TickArgs &a, hipStream_t st);
+hipError_t launch_integrate_sparse(const DevNet &n, const TickArgs &a, int samples_per_wg, hipStream_t st);
+bool sparse_shape_supported(int A, int N, int G);
+int sparse_max_samples_per_wg();
 hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes,
                                  int samples_per_wg, hipStream_t st);
-hipError_t launch_route(const DevNet &n, int q_now, const RouteCfg &cfg, hipStream_t st);
+hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st);
 hipError_t launch_reset_state(const DevNet &n, hipStream_t st);
+hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st);
 bool mfma_shape_supported(int A, int N, int two_planes);
+int mfma_shape_code(int A, int N, int two_planes);
+int plain_shape_code(int W, int G);
+int route_shape_code(const RouteCfg &cfg, int max_delay);
+hipError_t launch_integrate_plain_batch(const BatchEntry *tab, int num, int total, int k, hipStream_t st);
+hipError_t launch_route_batch(const BatchEntry *tab, int num, int total, int k, size_t lds_bytes, hipStream_t st);
+hipError_t launch_advance_batch(const BatchEntry *tab, int num, int num_ticks, unsigned *queue, hipStream_t st);
+hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k, unsigned *queue,
+                                       int workgroups, hipStream_t st);
 RouteCfg route_default_cfg(const DevNet &n);
 int route_dmax(int max_delay);
 int mfma_max_samples_per_wg();

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -41,9 +42,9 @@ ranc_status hip_fail(hipError_t e, const char *what)
 
 enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
-    R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
+    R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_XROW, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
     R_PARAMS_END,  // everything before this is uploaded once at load
-    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_EXT, R_NREG
+    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_TICK, R_BATCH, R_EXT, R_NREG
 };
 
 struct Plan {
@@ -54,6 +55,12 @@ struct Plan {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Batch tables (several networks advanced by one launch per tick) live in the
+// workspace of the batch's first network: up to BATCH_MAX entries for the
+// MFMA path, then up to BATCH_MAX for the plain path, then two queue counters.
+constexpr int BATCH_MAX = 128;
+constexpr size_t BATCH_TABLE_BYTES = 2 * BATCH_MAX * sizeof(BatchEntry) + 256;
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
@@ -69,7 +76,7 @@ ranc_status validate(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t path
         return fail(RANC_EUNSUPPORTED, "num_samples must be <= 65535 (got %d)", S);
     if (RT < 1)
         return fail(RANC_EINVAL, "max_ticks_per_call must be >= 1 (got %d)", RT);
-    if (path < RANC_PATH_AUTO || path > RANC_PATH_MFMA)
+    if (path < RANC_PATH_AUTO || path > RANC_PATH_SPARSE)
         return fail(RANC_EINVAL, "unknown path %d", path);
     if (d->num_cores < 1)
         return fail(RANC_EINVAL, "num_cores must be >= 1");
@@ -164,14 +171,16 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     if (path == RANC_PATH_MFMA && !mfma_shape_supported(p.A, p.N, p.two))
         return fail(RANC_EUNSUPPORTED, "MFMA path does not support A=%d N=%d with %d-bit weights", p.A, p.N,
                     d->weight_bits);
+    if (path == RANC_PATH_SPARSE && !sparse_shape_supported(p.A, p.N, p.G))
+        return fail(RANC_EUNSUPPORTED, "sparse path does not support N=%d with G=%d", p.N, p.G);
     p.path = path;
-    // Samples per MFMA workgroup: aim for >= 1024 workgroups, in 64-sample tiles.
+    // Samples per workgroup (sample-tiled paths): aim for >= 1024 workgroups, in 64-sample tiles.
     {
         const int tiles = (S + 63) / 64;
         int chunks = (1024 + p.C - 1) / p.C;
         chunks = std::max(1, std::min(chunks, tiles));
         const int tiles_per = (tiles + chunks - 1) / chunks;
-        p.spw = std::min(64 * tiles_per, mfma_max_samples_per_wg());
+        p.spw = std::min(64 * tiles_per, std::min(mfma_max_samples_per_wg(), sparse_max_samples_per_wg()));
         if (const char *e = getenv("RANC_MFMA_SPW")) {
             const int v = atoi(e);
             if (v > 0 && v % 64 == 0 && v <= mfma_max_samples_per_wg())
@@ -215,28 +224,33 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.Nout = (int)nout;
     const size_t C = p.C, A = p.A, N = p.N, G = p.G, W = p.W, NW = p.NW;
     const bool mf = p.path == RANC_PATH_MFMA;
-    p.size[R_COLBITS] = mf ? 0 : C * W * N * 4;
+    const bool sp = p.path == RANC_PATH_SPARSE;
+    const bool tiled = mf || sp;   // sample-tiled paths: spike history, neuron-major raster
+    p.size[R_COLBITS] = tiled ? 0 : C * W * N * 4;
+    p.size[R_XROW] = sp ? C * A * NW * 4 : 0;
     p.size[R_TYPEMASK] = C * G * W * 4;
     p.size[R_WTS] = C * G * N * 4;
     p.size[R_LEAK] = p.size[R_THR] = p.size[R_RST] = p.size[R_VINIT] = C * N * 4;
     p.size[R_COREMASK] = p.size[R_OUTMASK] = p.size[R_OUTWORD] = C * NW * 4;
     p.size[R_ININDEX] = C * 4;
-    p.size[R_RTDCNT] = mf ? 0 : (C * W + 63) / 64 * 64 * route_dmax(p.D) * 2;
-    p.size[R_RTGOFF] = mf ? 0 : (C * W + 63) / 64 * 4;
-    p.size[R_RTENT] = mf ? 0 : std::max<size_t>((size_t)p.ell_words, 1) * 4;
-    p.size[R_RTXPTR] = mf ? (C * A + 1) * 4 : 0;
-    p.size[R_RTXENT] = mf ? std::max<size_t>((size_t)E, 1) * 4 : 0;
+    p.size[R_RTDCNT] = tiled ? 0 : (C * W + 63) / 64 * 64 * route_dmax(p.D) * 2;
+    p.size[R_RTGOFF] = tiled ? 0 : (C * W + 63) / 64 * 4;
+    p.size[R_RTENT] = tiled ? 0 : std::max<size_t>((size_t)p.ell_words, 1) * 4;
+    p.size[R_RTXPTR] = tiled ? (C * A + 1) * 4 : 0;
+    p.size[R_RTXENT] = tiled ? std::max<size_t>((size_t)E, 1) * 4 : 0;
     const size_t HG = (size_t)p.S64 / 64;
-    p.size[R_HZERO] = mf ? HG * 8 : 0;
+    p.size[R_HZERO] = tiled ? HG * 8 : 0;
     p.size[R_DEGB] = mf ? C * 2 * A : 0;
-    p.size[R_OUTIDX] = mf ? C * N * 4 : 0;
+    p.size[R_OUTIDX] = tiled ? C * N * 4 : 0;
     p.size[R_PLANES] = mf ? C * A * N * (p.two ? 2 : 1) : 0;
-    p.size[R_V] = C * (mf ? (size_t)p.S64 : (size_t)S) * N * 4;
-    p.size[R_RING] = mf ? 0 : (size_t)p.Q * S * C * W * 4;
-    p.size[R_SPK] = mf ? 0 : (size_t)S * C * NW * 4;
-    p.size[R_HIST] = mf ? (size_t)p.Q * C * N * HG * 8 : 0;
-    p.size[R_RASTER] = mf ? (size_t)RT * p.Nout * HG * 8 : (size_t)RT * S * p.Wout * 4;
+    p.size[R_V] = C * (tiled ? (size_t)p.S64 : (size_t)S) * N * 4;
+    p.size[R_RING] = tiled ? 0 : (size_t)p.Q * S * C * W * 4;
+    p.size[R_SPK] = tiled ? 0 : (size_t)S * C * NW * 4;
+    p.size[R_HIST] = tiled ? (size_t)p.Q * C * N * HG * 8 : 0;
+    p.size[R_RASTER] = tiled ? (size_t)RT * p.Nout * HG * 8 : (size_t)RT * S * p.Wout * 4;
     p.size[R_CNT] = C * S * CNT_N * 8;
+    p.size[R_TICK] = 16;
+    p.size[R_BATCH] = BATCH_TABLE_BYTES;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
     size_t off = 0;
     for (int r = 0; r < R_NREG; ++r) {
@@ -375,6 +389,8 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
         for (size_t i = 0; i < (size_t)C * N; ++i)
             oi[i] = d->dest_kind[i] == RANC_DEST_OUT ? next++ : -1;
     }
+    if (p.size[R_XROW])
+        memcpy(at(R_XROW), d->crossbar, (size_t)C * A * NW * 4);
     if (p.size[R_PLANES]) {
         // B tiles: [C][N/32][A/32][planes][64 lanes][16 bytes]; lane l, byte b of
         // k-step k covers axon 32k + 16(l/32) + b and neuron 32nb + l%32.
@@ -410,13 +426,39 @@ struct EventPair {
 struct Profiler {
     bool on = false;
     std::vector<EventPair> pool;          // created on demand, reused
-    std::vector<std::pair<int, int>> used; // (pool index, kind 0=integrate 1=route)
-    double ms[2] = {0, 0};
-    int64_t launches[2] = {0, 0};
+    std::vector<std::pair<int, int>> used; // (pool index, kind 0=integrate 1=route 2=graph)
+    double ms[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
+};
+
+// A captured tick loop: num_ticks ticks reading inputs at `base`.
+struct CapturedLoop {
+    int num_ticks;
+    const uint32_t *base;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+// A batch of networks run together, as last set up by ranc_run_ticks with
+// this handle first; its tables are in this handle's workspace.
+struct Batch {
+    std::vector<ranc_net *> nets;
+    std::vector<uint64_t> uids;   // identity of the networks (a freed handle's address may be reused)
+    std::vector<const uint32_t *> bases;
+    int num_ticks = 0;
+    std::vector<BatchEntry> mf, pl;
+    int mf_units = 0, pl_units = 0, rt_units = 0, mf_workgroups = 0;
+    size_t rt_lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 struct ranc_net {
     Plan p;
+    uint64_t uid = 0;   // unique per loaded handle
+    Batch batch;
+    std::vector<CapturedLoop> loops;
+    hipStream_t cap_stream = nullptr;  // private stream used only for capture
     RouteCfg rcfg;
     Profiler prof;
     DevNet dn;
@@ -477,6 +519,331 @@ static hipError_t prof_collect(ranc_net *net)
     return hipSuccess;
 }
 
+// Queue num_ticks ticks on stream s: per tick the integration (and on the
+// plain path the router), then the device tick advance. With `timed`, HIP
+// event pairs are recorded around each launch while profiling is on.
+static ranc_status queue_ticks(ranc_net *net, const uint32_t *base, int num_ticks, hipStream_t s, bool timed)
+{
+    const Plan &p = net->p;
+    const size_t tick_words = (size_t)p.Cin * p.W;
+    timed = timed && net->prof.on;
+    for (int k = 0; k < num_ticks; ++k) {
+        TickArgs ta;
+        ta.k = k;
+        ta.ext_t = base ? base + (size_t)k * tick_words : nullptr;
+        ta.ext_sstride = (long long)num_ticks * tick_words;
+        // A long timed run folds finished event pairs in batches.
+        if (timed && net->prof.used.size() >= 4096) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e == hipSuccess)
+                e = prof_collect(net);
+            if (e != hipSuccess)
+                return hip_fail(e, "collecting kernel timings");
+        }
+        int slot = -1;
+        hipError_t e = timed ? prof_begin(net, 0, s, &slot) : hipSuccess;
+        if (e == hipSuccess)
+            e = p.path == RANC_PATH_MFMA     ? launch_integrate_mfma(net->dn, ta, p.two, p.spw, s)
+                : p.path == RANC_PATH_SPARSE ? launch_integrate_sparse(net->dn, ta, p.spw, s)
+                                             : launch_integrate_plain(net->dn, ta, s);
+        if (e == hipSuccess && timed)
+            e = prof_end(net, slot, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "launching integration");
+        // The MFMA path delivers spikes inside the next tick's integration
+        // (spike history gathered by destination); the plain path routes
+        // into the scheduler ring here.
+        if (p.path == RANC_PATH_PLAIN) {
+            e = timed ? prof_begin(net, 1, s, &slot) : hipSuccess;
+            if (e == hipSuccess)
+                e = launch_route(net->dn, k, net->rcfg, s);
+            if (e == hipSuccess && timed)
+                e = prof_end(net, slot, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "launching routing");
+        }
+    }
+    hipError_t e = launch_advance_tick(net->dn, num_ticks, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "advancing the tick");
+    return RANC_OK;
+}
+
+// Run num_ticks ticks as one captured graph: the tick loop is captured once
+// per (num_ticks, input address) on a private stream and replayed on s.
+// Every launch argument is position-in-call relative (the scheduler slot and
+// raster row come from the device tick), so one graph serves every call.
+static ranc_status run_captured(ranc_net *net, const uint32_t *base, int num_ticks, hipStream_t s)
+{
+    CapturedLoop *loop = nullptr;
+    for (auto &g : net->loops)
+        if (g.num_ticks == num_ticks && g.base == base)
+            loop = &g;
+    if (!loop) {
+        hipError_t e = hipSuccess;
+        if (!net->cap_stream)
+            e = hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return hip_fail(e, "creating the capture stream");
+        e = hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            return hip_fail(e, "beginning capture");
+        ranc_status st = queue_ticks(net, base, num_ticks, net->cap_stream, false);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(net->cap_stream, &graph);
+        if (st != RANC_OK) {
+            if (graph)
+                hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "ending capture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(graph);
+            return hip_fail(e, "instantiating the tick loop");
+        }
+        net->loops.push_back({num_ticks, base, graph, exec});
+        loop = &net->loops.back();
+    }
+    int slot = -1;
+    hipError_t e = prof_begin(net, 2, s, &slot);
+    if (e == hipSuccess)
+        e = hipGraphLaunch(loop->exec, s);
+    if (e == hipSuccess)
+        e = prof_end(net, slot, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "launching the tick loop");
+    return RANC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: several networks (any shapes) advanced together, one launch per
+// tick and path for all of them (plus one router launch for the plain path).
+
+static int device_cu_count()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    return cus;
+}
+
+// Build the host tables of a batch (entries sorted by decreasing work per
+// unit, so the persistent MFMA launch hands out the largest units first).
+static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *const *bases,
+                               int num_ticks, Batch &b)
+{
+    b.nets.assign(nets, nets + num);
+    b.uids.clear();
+    for (int i = 0; i < num; ++i)
+        b.uids.push_back(nets[i]->uid);
+    b.bases.assign(bases, bases + num);
+    b.num_ticks = num_ticks;
+    b.mf.clear();
+    b.pl.clear();
+    b.rt_lds = 0;
+    for (int i = 0; i < num; ++i) {
+        ranc_net *net = nets[i];
+        const Plan &p = net->p;
+        BatchEntry e;
+        memset(&e, 0, sizeof e);
+        e.n = net->dn;
+        e.ext_base = bases[i];
+        e.tick_words = (long long)p.Cin * p.W;
+        e.ext_sstride = (long long)num_ticks * e.tick_words;
+        e.spw = p.spw;
+        if (p.path == RANC_PATH_SPARSE)
+            return fail(RANC_EUNSUPPORTED, "nets[%d]: the sparse path runs one network per call", i);
+        if (p.path == RANC_PATH_MFMA) {
+            e.code = mfma_shape_code(p.A, p.N, p.two);
+            e.units = p.C * ((p.S + p.spw - 1) / p.spw);
+            b.mf.push_back(e);
+        } else {
+            e.code = plain_shape_code(p.W, p.G);
+            e.units = p.C * p.S;
+            e.route_code = route_shape_code(net->rcfg, p.D);
+            if (e.route_code < 0)
+                return fail(RANC_EUNSUPPORTED, "nets[%d]: router shape (%d samples per block, max delay %d) "
+                            "cannot run in a batch", i, net->rcfg.samples_per_block, p.D);
+            e.route_split = net->rcfg.blocks_per_group;
+            e.route_units = e.route_split * ((p.S + net->rcfg.samples_per_block - 1) / net->rcfg.samples_per_block);
+            if (net->rcfg.stage)
+                b.rt_lds = std::max(b.rt_lds, (size_t)p.C * p.NW * 4 * net->rcfg.samples_per_block);
+            b.pl.push_back(e);
+        }
+    }
+    if ((int)b.mf.size() > BATCH_MAX || (int)b.pl.size() > BATCH_MAX)
+        return fail(RANC_EUNSUPPORTED, "a batch holds at most %d networks per path", BATCH_MAX);
+    auto work = [](const BatchEntry &e) {
+        return (double)e.spw * e.n.N * (e.n.A + 64) * ((e.code & 1) ? 2 : 1);
+    };
+    std::stable_sort(b.mf.begin(), b.mf.end(),
+                     [&](const BatchEntry &x, const BatchEntry &y) { return work(x) > work(y); });
+    long long mu = 0, pu = 0, ru = 0;
+    for (auto &e : b.mf) {
+        e.unit_begin = (int)mu;
+        mu += e.units;
+    }
+    for (auto &e : b.pl) {
+        e.unit_begin = (int)pu;
+        pu += e.units;
+        e.route_begin = (int)ru;
+        ru += e.route_units;
+    }
+    if (mu > INT32_MAX || pu > INT32_MAX || ru > INT32_MAX)
+        return fail(RANC_EUNSUPPORTED, "batch has too many work units");
+    b.mf_units = (int)mu;
+    b.pl_units = (int)pu;
+    b.rt_units = (int)ru;
+    b.mf_workgroups = (int)std::min<long long>(mu, device_cu_count());
+    return RANC_OK;
+}
+
+static BatchEntry *batch_table(ranc_net *lead, int which)
+{
+    return (BatchEntry *)(lead->ws + lead->p.off[R_BATCH]) + (which ? BATCH_MAX : 0);
+}
+
+static unsigned *batch_queue(ranc_net *lead)
+{
+    return (unsigned *)(batch_table(lead, 0) + 2 * BATCH_MAX);
+}
+
+static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t s, bool timed)
+{
+    const BatchEntry *tmf = batch_table(lead, 0), *tpl = batch_table(lead, 1);
+    unsigned *queue = batch_queue(lead);
+    timed = timed && lead->prof.on;
+    for (int k = 0; k < b.num_ticks; ++k) {
+        int slot = -1;
+        hipError_t e = hipSuccess;
+        if (!b.mf.empty()) {
+            e = timed ? prof_begin(lead, 0, s, &slot) : hipSuccess;
+            if (e == hipSuccess)
+                e = launch_integrate_mfma_batch(tmf, (int)b.mf.size(), b.mf_units, k, queue, b.mf_workgroups, s);
+            if (e == hipSuccess && timed)
+                e = prof_end(lead, slot, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "launching batch integration (MFMA)");
+        }
+        if (!b.pl.empty()) {
+            e = timed ? prof_begin(lead, 0, s, &slot) : hipSuccess;
+            if (e == hipSuccess)
+                e = launch_integrate_plain_batch(tpl, (int)b.pl.size(), b.pl_units, k, s);
+            if (e == hipSuccess && timed)
+                e = prof_end(lead, slot, s);
+            if (e == hipSuccess)
+                e = timed ? prof_begin(lead, 1, s, &slot) : hipSuccess;
+            if (e == hipSuccess)
+                e = launch_route_batch(tpl, (int)b.pl.size(), b.rt_units, k, b.rt_lds, s);
+            if (e == hipSuccess && timed)
+                e = prof_end(lead, slot, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "launching batch integration (plain)");
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!b.mf.empty())
+        e = launch_advance_batch(tmf, (int)b.mf.size(), b.num_ticks, queue, s);
+    if (e == hipSuccess && !b.pl.empty())
+        e = launch_advance_batch(tpl, (int)b.pl.size(), b.num_ticks, queue, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "advancing batch ticks");
+    return RANC_OK;
+}
+
+// Run num_ticks ticks of several networks together. The batch set-up (tables
+// in the first network's workspace, and the captured graph with
+// RANC_RUN_GRAPH) is reused while the same networks, input addresses and
+// tick count repeat.
+static ranc_status run_batch(ranc_net *const *nets, int num, const uint32_t *const *bases, int num_ticks,
+                             bool graph, hipStream_t s)
+{
+    ranc_net *lead = nets[0];
+    Batch &b = lead->batch;
+    bool same = b.num_ticks == num_ticks && (int)b.nets.size() == num &&
+                std::equal(b.nets.begin(), b.nets.end(), nets) && std::equal(b.bases.begin(), b.bases.end(), bases);
+    for (int i = 0; same && i < num; ++i)
+        same = b.uids[i] == nets[i]->uid;
+    if (!same) {
+        if (b.exec)
+            hipGraphExecDestroy(b.exec);
+        if (b.graph)
+            hipGraphDestroy(b.graph);
+        b.exec = nullptr;
+        b.graph = nullptr;
+        b.num_ticks = 0;
+        Batch nb;
+        ranc_status st = build_batch(nets, num, bases, num_ticks, nb);
+        if (st != RANC_OK)
+            return st;
+        // the previous tables may still be read by queued work
+        hipError_t e = hipStreamSynchronize(s);
+        if (e == hipSuccess && !nb.mf.empty())
+            e = hipMemcpy(batch_table(lead, 0), nb.mf.data(), nb.mf.size() * sizeof(BatchEntry), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !nb.pl.empty())
+            e = hipMemcpy(batch_table(lead, 1), nb.pl.data(), nb.pl.size() * sizeof(BatchEntry), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            const unsigned zero[2] = {0u, 0u};
+            e = hipMemcpy(batch_queue(lead), zero, sizeof zero, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "uploading the batch table");
+        b.nets = std::move(nb.nets);
+        b.uids = std::move(nb.uids);
+        b.bases = std::move(nb.bases);
+        b.mf = std::move(nb.mf);
+        b.pl = std::move(nb.pl);
+        b.mf_units = nb.mf_units;
+        b.pl_units = nb.pl_units;
+        b.rt_units = nb.rt_units;
+        b.mf_workgroups = nb.mf_workgroups;
+        b.rt_lds = nb.rt_lds;
+        b.num_ticks = num_ticks;
+    }
+    if (!graph)
+        return queue_batch_ticks(lead, b, s, true);
+    if (!b.exec) {
+        hipError_t e = hipSuccess;
+        if (!lead->cap_stream)
+            e = hipStreamCreateWithFlags(&lead->cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipStreamBeginCapture(lead->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            return hip_fail(e, "beginning batch capture");
+        ranc_status st = queue_batch_ticks(lead, b, lead->cap_stream, false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(lead->cap_stream, &g);
+        if (st != RANC_OK) {
+            if (g)
+                hipGraphDestroy(g);
+            return st;
+        }
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (g)
+                hipGraphDestroy(g);
+            return hip_fail(e, "capturing the batch tick loop");
+        }
+        b.graph = g;
+    }
+    int slot = -1;
+    hipError_t e = prof_begin(lead, 2, s, &slot);
+    if (e == hipSuccess)
+        e = hipGraphLaunch(b.exec, s);
+    if (e == hipSuccess)
+        e = prof_end(lead, slot, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "launching the batch tick loop");
+    return RANC_OK;
+}
+
 extern "C" {
 
 const char *ranc_last_error(void) { return g_err.c_str(); }
@@ -513,13 +880,15 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     ranc_net *net = new (std::nothrow) ranc_net();
     if (!net)
         return fail(RANC_ENOMEM, "host allocation failed");
+    static std::atomic<uint64_t> next_uid{1};
     net->p = p;
+    net->uid = next_uid++;
     net->ws = (uint8_t *)workspace;
     auto reg = [&](Region r) -> uint8_t * { return net->ws + p.off[r]; };
     DevNet &n = net->dn;
     n.C = p.C; n.A = p.A; n.N = p.N; n.G = p.G; n.W = p.W; n.NW = p.NW; n.D = p.D; n.Q = p.Q;
     n.S = p.S; n.S64 = p.S64; n.RT = p.RT; n.Wout = p.Wout; n.Nout = p.Nout; n.Cin = p.Cin;
-    n.vlayout = p.path == RANC_PATH_MFMA ? VLAYOUT_BRICK : VLAYOUT_CSN;
+    n.vlayout = p.path == RANC_PATH_MFMA ? VLAYOUT_BRICK : p.path == RANC_PATH_SPARSE ? VLAYOUT_SPARSE : VLAYOUT_CSN;
     n.vmin = (int32_t)(-(1LL << (desc->potential_bits - 1)));
     n.vmax = (int32_t)((1LL << (desc->potential_bits - 1)) - 1);
     n.colbits = (const uint32_t *)reg(R_COLBITS);
@@ -538,6 +907,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.rt_ent = (const uint32_t *)reg(R_RTENT);
     n.degb = (const uint32_t *)reg(R_DEGB);
     n.outidx = (const int32_t *)reg(R_OUTIDX);
+    n.xrow = (const uint32_t *)reg(R_XROW);
     n.planes = (const uint4 *)reg(R_PLANES);
     n.V = (int32_t *)reg(R_V);
     n.ring = (uint32_t *)reg(R_RING);
@@ -548,6 +918,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.hist_zero = (const uint64_t *)reg(R_HZERO);
     n.raster = (uint32_t *)reg(R_RASTER);
     n.cnt = (unsigned long long *)reg(R_CNT);
+    n.tick = (int *)reg(R_TICK);
     std::vector<uint8_t> host;
     pack_params(desc, p, host, net->out_words);
     for (size_t i = 0; i < (size_t)p.C * p.N; ++i)
@@ -599,9 +970,14 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
         if (num_ticks < 1 || num_ticks > nets[i]->p.RT)
             return fail(RANC_EINVAL, "num_ticks %d outside [1, max_ticks_per_call=%d]", num_ticks, nets[i]->p.RT);
     }
-    if (flags & ~RANC_INPUTS_ON_DEVICE)
+    if (flags & ~(RANC_INPUTS_ON_DEVICE | RANC_RUN_GRAPH))
         return fail(RANC_EINVAL, "unknown flags 0x%x", flags);
+    for (int i = 0; i < num_nets; ++i)
+        for (int j = 0; j < i; ++j)
+            if (nets[i] == nets[j])
+                return fail(RANC_EINVAL, "nets[%d] and nets[%d] are the same network", j, i);
     hipStream_t s = (hipStream_t)stream;
+    std::vector<const uint32_t *> bases(num_nets, nullptr);
     for (int i = 0; i < num_nets; ++i) {
         ranc_net *net = nets[i];
         const Plan &p = net->p;
@@ -617,45 +993,22 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
         }
         if (p.Cin == 0)
             base = nullptr;
-        for (int k = 0; k < num_ticks; ++k) {
-            TickArgs ta;
-            ta.q_now = (int)(net->tick % p.Q);
-            ta.r_row = (int)(net->tick % p.RT);
-            ta.ext_t = base ? base + (size_t)k * tick_words : nullptr;
-            ta.ext_sstride = (long long)num_ticks * tick_words;
-            // A long timed run folds finished event pairs in batches.
-            if (net->prof.used.size() >= 4096) {
-                hipError_t e = hipStreamSynchronize(s);
-                if (e == hipSuccess)
-                    e = prof_collect(net);
-                if (e != hipSuccess)
-                    return hip_fail(e, "collecting kernel timings");
-            }
-            int slot;
-            hipError_t e = prof_begin(net, 0, s, &slot);
-            if (e == hipSuccess)
-                e = p.path == RANC_PATH_MFMA ? launch_integrate_mfma(net->dn, ta, p.two, p.spw, s)
-                                             : launch_integrate_plain(net->dn, ta, s);
-            if (e == hipSuccess)
-                e = prof_end(net, slot, s);
-            if (e != hipSuccess)
-                return hip_fail(e, "launching integration");
-            // The MFMA path delivers spikes inside the next tick's integration
-            // (spike history gathered by destination); the plain path routes
-            // into the scheduler ring here.
-            if (p.path != RANC_PATH_MFMA) {
-                e = prof_begin(net, 1, s, &slot);
-                if (e == hipSuccess)
-                    e = launch_route(net->dn, ta.q_now, net->rcfg, s);
-                if (e == hipSuccess)
-                    e = prof_end(net, slot, s);
-                if (e != hipSuccess)
-                    return hip_fail(e, "launching routing");
-            }
-            ++net->tick;
-        }
-        net->last_stream = s;
-        ++net->version;
+        bases[i] = base;
+    }
+    if (num_nets > 1) {
+        ranc_status st = run_batch(nets, num_nets, bases.data(), num_ticks, (flags & RANC_RUN_GRAPH) != 0, s);
+        if (st != RANC_OK)
+            return st;
+    } else {
+        ranc_status st = (flags & RANC_RUN_GRAPH) ? run_captured(nets[0], bases[0], num_ticks, s)
+                                                 : queue_ticks(nets[0], bases[0], num_ticks, s, true);
+        if (st != RANC_OK)
+            return st;
+    }
+    for (int i = 0; i < num_nets; ++i) {
+        nets[i]->tick += num_ticks;
+        nets[i]->last_stream = s;
+        ++nets[i]->version;
     }
     return RANC_OK;
 }
@@ -697,7 +1050,7 @@ ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, 
     if (tick_begin < lo || tick_end > net->tick || tick_begin > tick_end)
         return fail(RANC_ESTATE, "ticks [%lld, %lld) outside the retained window [%lld, %lld)",
                     (long long)tick_begin, (long long)tick_end, (long long)lo, (long long)net->tick);
-    const bool mf = p.path == RANC_PATH_MFMA;
+    const bool mf = p.path != RANC_PATH_PLAIN;   // sample-tiled paths: neuron-major raster
     const size_t HG = (size_t)p.S64 / 64;
     net->raster_host.resize(mf ? (size_t)p.RT * p.Nout * HG * 2 : (size_t)p.RT * p.S * p.Wout);
     ranc_status st = refresh_mirror(net, net->dn.raster, net->raster_host.size() * 4, net->raster_host.data(),
@@ -752,14 +1105,15 @@ ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out)
     if (sample < 0 || sample >= p.S)
         return fail(RANC_EINVAL, "sample %d out of range", sample);
     const bool brick = net->dn.vlayout == VLAYOUT_BRICK;
-    net->v_host.resize((size_t)p.C * (brick ? p.S64 : p.S) * p.N);
+    const size_t SV = net->dn.vlayout == VLAYOUT_CSN ? (size_t)p.S : (size_t)p.S64;
+    net->v_host.resize((size_t)p.C * SV * p.N);
     ranc_status st = refresh_mirror(net, net->dn.V, net->v_host.size() * 4, net->v_host.data(), net->v_version,
                                     "reading potentials");
     if (st != RANC_OK)
         return st;
     if (!brick) {
         for (int c = 0; c < p.C; ++c)
-            memcpy(out + (size_t)c * p.N, net->v_host.data() + ((size_t)c * p.S + sample) * p.N, (size_t)p.N * 4);
+            memcpy(out + (size_t)c * p.N, net->v_host.data() + ((size_t)c * SV + sample) * p.N, (size_t)p.N * 4);
         return RANC_OK;
     }
     // brick (c, nb, g): element (q, lane l, e) = sample 32g + 8q + 4(l/32) + e, neuron 32nb + l%32
@@ -823,8 +1177,10 @@ ranc_status ranc_profile_enable(ranc_net *net, int32_t enable)
         if (st != RANC_OK)
             return st;
         net->prof.used.clear();
-        net->prof.ms[0] = net->prof.ms[1] = 0;
-        net->prof.launches[0] = net->prof.launches[1] = 0;
+        for (int k = 0; k < 3; ++k) {
+            net->prof.ms[k] = 0;
+            net->prof.launches[k] = 0;
+        }
     }
     net->prof.on = enable != 0;
     return RANC_OK;
@@ -844,6 +1200,8 @@ ranc_status ranc_profile_read(ranc_net *net, ranc_profile *out)
     out->route_ms = net->prof.ms[1];
     out->integrate_launches = net->prof.launches[0];
     out->route_launches = net->prof.launches[1];
+    out->graph_ms = net->prof.ms[2];
+    out->graph_launches = net->prof.launches[2];
     return RANC_OK;
 }
 
@@ -861,11 +1219,204 @@ ranc_status ranc_reset_state(ranc_net *net, void *stream)
     return RANC_OK;
 }
 
+// Launch-shape autotuner: time every candidate shape of the handle's path on
+// num_ticks ticks of the given inputs and keep the fastest.
+static void drop_graphs(ranc_net *net)
+{
+    for (auto &g : net->loops) {
+        hipGraphExecDestroy(g.exec);
+        hipGraphDestroy(g.graph);
+    }
+    net->loops.clear();
+    if (net->batch.exec)
+        hipGraphExecDestroy(net->batch.exec);
+    if (net->batch.graph)
+        hipGraphDestroy(net->batch.graph);
+    net->batch = Batch();
+}
+
+ranc_status ranc_autotune(ranc_net *net, const uint32_t *inputs, uint32_t flags, int32_t num_ticks, void *stream,
+                          ranc_tune *out)
+{
+    if (!net || !out)
+        return fail(RANC_EINVAL, "net or out is NULL");
+    if (num_ticks < 1 || num_ticks > net->p.RT)
+        return fail(RANC_EINVAL, "num_ticks %d outside [1, max_ticks_per_call=%d]", num_ticks, net->p.RT);
+    if (flags & ~RANC_INPUTS_ON_DEVICE)
+        return fail(RANC_EINVAL, "unknown flags 0x%x", flags);
+    hipStream_t s = (hipStream_t)stream;
+    Plan &p = net->p;
+    struct Cand {
+        int spw;
+        RouteCfg rc;
+    };
+    std::vector<Cand> cands;
+    if (p.path != RANC_PATH_PLAIN) {
+        const int tiles = (p.S + 63) / 64;
+        int last_chunks = -1;
+        for (int spw = 64; spw <= mfma_max_samples_per_wg(); spw *= 2) {
+            const int chunks = (tiles * 64 + spw - 1) / spw;
+            if (chunks == last_chunks)
+                break;
+            last_chunks = chunks;
+            cands.push_back({spw, net->rcfg});
+        }
+    } else {
+        const RouteCfg def = route_default_cfg(net->dn);
+        const int dmax = route_dmax(p.D);
+        for (int sb = 1; sb <= 8; sb *= 2) {
+            if (sb * dmax > 32 || (sb > 1 && sb > p.S))
+                continue;
+            const size_t bitmap = (size_t)p.C * p.NW * 4 * sb;
+            const int groups = (p.S + sb - 1) / sb;
+            const int max_split = std::max(1, (p.C * p.W + 255) / 256);
+            int base = std::max(1, std::min(max_split, (2048 + groups - 1) / groups));
+            for (int f = 0; f < 3; ++f) {
+                const int split = f == 0 ? std::max(1, base / 2) : f == 1 ? base : std::min(max_split, base * 2);
+                if (f > 0 && split == (f == 1 ? std::max(1, base / 2) : base))
+                    continue;
+                for (int stage = 0; stage <= 1; ++stage) {
+                    if (stage && bitmap > 128 * 1024)
+                        continue;
+                    if ((p.S + sb - 1) / sb > 65535)
+                        continue;
+                    RouteCfg rc;
+                    rc.samples_per_block = sb;
+                    rc.blocks_per_group = split;
+                    rc.stage = stage;
+                    cands.push_back({p.spw, rc});
+                }
+            }
+        }
+        if (cands.empty())
+            cands.push_back({p.spw, def});
+    }
+    const uint32_t *base = inputs;
+    if (base && p.Cin > 0 && !(flags & RANC_INPUTS_ON_DEVICE)) {
+        uint32_t *stage = (uint32_t *)(net->ws + p.off[R_EXT]);
+        hipError_t e = hipMemcpyAsync(stage, base, (size_t)p.S * num_ticks * p.Cin * p.W * 4,
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "staging inputs");
+        base = stage;
+    }
+    if (p.Cin == 0)
+        base = nullptr;
+    drop_graphs(net);
+    const bool prof_on = net->prof.on;
+    net->prof.on = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    double best = -1.0;
+    Cand best_c = cands[0];
+    ranc_status st = RANC_OK;
+    for (const Cand &c : cands) {
+        if (e != hipSuccess || st != RANC_OK)
+            break;
+        p.spw = c.spw;
+        net->rcfg = c.rc;
+        // one untimed pass, then a timed pass, each from the initial state
+        e = launch_reset_state(net->dn, s);
+        if (e == hipSuccess && (st = queue_ticks(net, base, num_ticks, s, false)) == RANC_OK)
+            e = launch_reset_state(net->dn, s);
+        if (e == hipSuccess && st == RANC_OK)
+            e = hipEventRecord(e0, s);
+        if (e == hipSuccess && st == RANC_OK && (st = queue_ticks(net, base, num_ticks, s, false)) == RANC_OK)
+            e = hipEventRecord(e1, s);
+        if (e == hipSuccess && st == RANC_OK)
+            e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess && st == RANC_OK)
+            e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && st == RANC_OK && (best < 0 || ms < best)) {
+            best = ms;
+            best_c = c;
+        }
+    }
+    if (e0)
+        hipEventDestroy(e0);
+    if (e1)
+        hipEventDestroy(e1);
+    p.spw = best_c.spw;
+    net->rcfg = best_c.rc;
+    net->prof.on = prof_on;
+    if (st != RANC_OK)
+        return st;
+    if (e == hipSuccess)
+        e = launch_reset_state(net->dn, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "autotuning");
+    net->tick = 0;
+    net->last_stream = s;
+    ++net->version;
+    const bool tiled = p.path != RANC_PATH_PLAIN;
+    out->samples_per_wg = tiled ? p.spw : 0;
+    out->route_samples_per_block = tiled ? 0 : net->rcfg.samples_per_block;
+    out->route_split = tiled ? 0 : net->rcfg.blocks_per_group;
+    out->route_stage = tiled ? 0 : net->rcfg.stage;
+    out->ms_per_tick = best / num_ticks;
+    out->candidates = (int32_t)cands.size();
+    return RANC_OK;
+}
+
+ranc_status ranc_set_launch_shape(ranc_net *net, const ranc_tune *shape)
+{
+    if (!net || !shape)
+        return fail(RANC_EINVAL, "net or shape is NULL");
+    const Plan &p = net->p;
+    if (p.path != RANC_PATH_PLAIN) {
+        const int v = shape->samples_per_wg;
+        if (v <= 0 || v % 64 || v > mfma_max_samples_per_wg())
+            return fail(RANC_EINVAL, "samples_per_wg %d must be a multiple of 64 in [64, %d]", v,
+                        mfma_max_samples_per_wg());
+        drop_graphs(net);
+        net->p.spw = v;
+        return RANC_OK;
+    }
+    RouteCfg rc;
+    rc.samples_per_block = shape->route_samples_per_block;
+    rc.blocks_per_group = shape->route_split;
+    rc.stage = shape->route_stage != 0;
+    const int sb = rc.samples_per_block;
+    if ((sb != 1 && sb != 2 && sb != 4 && sb != 8) || sb * route_dmax(p.D) > 32)
+        return fail(RANC_EINVAL, "route_samples_per_block %d unsupported with max delay %d", sb, p.D);
+    if (rc.blocks_per_group < 1)
+        return fail(RANC_EINVAL, "route_split must be >= 1");
+    if (rc.stage && (size_t)p.C * p.NW * 4 * sb > 128 * 1024)
+        return fail(RANC_EINVAL, "staged spike bitmaps of %d samples exceed the router's LDS", sb);
+    if ((p.S + sb - 1) / sb > 65535)
+        return fail(RANC_EINVAL, "too many sample groups for the router grid");
+    drop_graphs(net);
+    net->rcfg = rc;
+    return RANC_OK;
+}
+
+ranc_status ranc_get_launch_shape(const ranc_net *net, ranc_tune *out)
+{
+    if (!net || !out)
+        return fail(RANC_EINVAL, "net or out is NULL");
+    const bool mf = net->p.path != RANC_PATH_PLAIN;
+    out->samples_per_wg = mf ? net->p.spw : 0;
+    out->route_samples_per_block = mf ? 0 : net->rcfg.samples_per_block;
+    out->route_split = mf ? 0 : net->rcfg.blocks_per_group;
+    out->route_stage = mf ? 0 : net->rcfg.stage;
+    out->ms_per_tick = 0.0;
+    out->candidates = 0;
+    return RANC_OK;
+}
+
 void ranc_free(ranc_net *net)
 {
     if (!net)
         return;
     hipStreamSynchronize(net->last_stream);
+    drop_graphs(net);
+    if (net->cap_stream)
+        hipStreamDestroy(net->cap_stream);
     for (auto &e : net->prof.pool) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);

@@ -21,13 +21,15 @@ RANC_OK, RANC_EINVAL, RANC_ERANGE, RANC_ENOMEM, RANC_EDEVICE, RANC_ESTATE, RANC_
     0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "RANC_OK", -1: "RANC_EINVAL", -2: "RANC_ERANGE", -3: "RANC_ENOMEM", -4: "RANC_EDEVICE",
                 -5: "RANC_ESTATE", -6: "RANC_ETRUNC", -7: "RANC_EUNSUPPORTED"}
-RANC_PATH_AUTO, RANC_PATH_PLAIN, RANC_PATH_MFMA = 0, 1, 2
-PATHS = {"auto": RANC_PATH_AUTO, "plain": RANC_PATH_PLAIN, "mfma": RANC_PATH_MFMA}
+RANC_PATH_AUTO, RANC_PATH_PLAIN, RANC_PATH_MFMA, RANC_PATH_SPARSE = 0, 1, 2, 3
+PATHS = {"auto": RANC_PATH_AUTO, "plain": RANC_PATH_PLAIN, "mfma": RANC_PATH_MFMA, "sparse": RANC_PATH_SPARSE}
 RANC_INPUTS_ON_DEVICE = 1
+RANC_RUN_GRAPH = 2
 
 EXPORTED = ("ranc_last_error", "ranc_workspace_bytes", "ranc_load_network", "ranc_run_ticks",
             "ranc_read_spikes", "ranc_read_potentials", "ranc_read_counters", "ranc_current_tick",
-            "ranc_get_path", "ranc_profile_enable", "ranc_profile_read", "ranc_reset_state", "ranc_free")
+            "ranc_get_path", "ranc_profile_enable", "ranc_profile_read", "ranc_reset_state", "ranc_free",
+            "ranc_autotune", "ranc_set_launch_shape", "ranc_get_launch_shape")
 
 
 class RancError(RuntimeError):
@@ -52,11 +54,18 @@ class ranc_spike(C.Structure):
 
 class ranc_profile(C.Structure):
     _fields_ = [("integrate_ms", C.c_double), ("route_ms", C.c_double),
-                ("integrate_launches", C.c_int64), ("route_launches", C.c_int64)]
+                ("integrate_launches", C.c_int64), ("route_launches", C.c_int64),
+                ("graph_ms", C.c_double), ("graph_launches", C.c_int64)]
 
 
 class ranc_counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("emitted", "routed", "delivered", "out", "events")]
+
+
+class ranc_tune(C.Structure):
+    _fields_ = [("samples_per_wg", C.c_int32), ("route_samples_per_block", C.c_int32),
+                ("route_split", C.c_int32), ("route_stage", C.c_int32),
+                ("ms_per_tick", C.c_double), ("candidates", C.c_int32)]
 
 
 SPIKE_DTYPE = np.dtype([("tick", "<i8"), ("core", "<i4"), ("neuron", "<i4")])
@@ -82,6 +91,9 @@ def _load_lib():
         "ranc_profile_read": (C.c_int, [vp, C.POINTER(ranc_profile)]),
         "ranc_reset_state": (C.c_int, [vp, vp]),
         "ranc_free": (None, [vp]),
+        "ranc_autotune": (C.c_int, [vp, vp, u32, i32, vp, C.POINTER(ranc_tune)]),
+        "ranc_set_launch_shape": (C.c_int, [vp, C.POINTER(ranc_tune)]),
+        "ranc_get_launch_shape": (C.c_int, [vp, C.POINTER(ranc_tune)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -192,6 +204,27 @@ def ranc_profile_read(handle: int) -> dict:
     return {k: (float(getattr(p, k)) if k.endswith("_ms") else int(getattr(p, k))) for k, _ in ranc_profile._fields_}
 
 
+def _tune_dict(t: ranc_tune) -> dict:
+    return {k: (float(getattr(t, k)) if k == "ms_per_tick" else int(getattr(t, k))) for k, _ in ranc_tune._fields_}
+
+
+def ranc_autotune(handle: int, inputs_ptr, flags: int, num_ticks: int, stream: int) -> dict:
+    t = ranc_tune()
+    _check(_lib.ranc_autotune(handle, inputs_ptr or None, flags, num_ticks, stream, C.byref(t)))
+    return _tune_dict(t)
+
+
+def ranc_set_launch_shape(handle: int, shape: dict) -> None:
+    t = ranc_tune(**{k: shape.get(k, 0) for k, _ in ranc_tune._fields_})
+    _check(_lib.ranc_set_launch_shape(handle, C.byref(t)))
+
+
+def ranc_get_launch_shape(handle: int) -> dict:
+    t = ranc_tune()
+    _check(_lib.ranc_get_launch_shape(handle, C.byref(t)))
+    return _tune_dict(t)
+
+
 def ranc_reset_state(handle: int, stream: int) -> None:
     _check(_lib.ranc_reset_state(handle, stream))
 
@@ -219,7 +252,7 @@ class RancNet:
         self.handle = ranc_load_network(self.desc, num_samples, max_ticks_per_call, p,
                                         self.workspace.data_ptr(), self.workspace.numel(),
                                         self.stream.cuda_stream)
-        self.path = {RANC_PATH_PLAIN: "plain", RANC_PATH_MFMA: "mfma"}[ranc_get_path(self.handle)]
+        self.path = {RANC_PATH_PLAIN: "plain", RANC_PATH_MFMA: "mfma", RANC_PATH_SPARSE: "sparse"}[ranc_get_path(self.handle)]
 
     def close(self):
         if getattr(self, "handle", None):
@@ -236,10 +269,11 @@ class RancNet:
     def tick(self) -> int:
         return ranc_current_tick(self.handle)
 
-    def run(self, inputs, num_ticks: int):
+    def run(self, inputs, num_ticks: int, graph: bool = False):
         """Advance by num_ticks. ``inputs``: None, a numpy uint32 array or a CUDA tensor
-        (int32/uint32 bits) of shape [S, num_ticks, C_in, A/32]."""
-        flags, ptr, keep = 0, None, None
+        (int32/uint32 bits) of shape [S, num_ticks, C_in, A/32]. ``graph``: run the
+        ticks as one captured HIP graph (captured on first use, then replayed)."""
+        flags, ptr, keep = (RANC_RUN_GRAPH if graph else 0), None, None
         if inputs is not None:
             if isinstance(inputs, np.ndarray):
                 keep = np.ascontiguousarray(inputs, dtype=np.uint32)
@@ -248,7 +282,7 @@ class RancNet:
             else:
                 assert inputs.is_cuda and inputs.is_contiguous() and inputs.element_size() == 4
                 assert tuple(inputs.shape[:2]) == (self.S, num_ticks), tuple(inputs.shape)
-                flags, ptr, keep = RANC_INPUTS_ON_DEVICE, inputs.data_ptr(), inputs
+                flags, ptr, keep = flags | RANC_INPUTS_ON_DEVICE, inputs.data_ptr(), inputs
         ranc_run_ticks([self.handle], [ptr] if ptr else None, flags, num_ticks, self.stream.cuda_stream)
         if isinstance(keep, np.ndarray):
             self.stream.synchronize()   # host buffer must outlive the staging copy
@@ -274,6 +308,25 @@ class RancNet:
         ranc_reset_state(self.handle, self.stream.cuda_stream)
         return self
 
+    def autotune(self, inputs, num_ticks: int) -> dict:
+        """Time every launch shape of this handle's path on num_ticks ticks of
+        ``inputs`` (None, numpy or CUDA tensor, as for :meth:`run`) and keep the
+        fastest; the state returns to tick 0."""
+        flags, ptr, keep = 0, None, None
+        if inputs is not None:
+            if isinstance(inputs, np.ndarray):
+                keep = np.ascontiguousarray(inputs, dtype=np.uint32)
+                ptr = keep.ctypes.data
+            else:
+                flags, ptr, keep = RANC_INPUTS_ON_DEVICE, inputs.data_ptr(), inputs
+        return ranc_autotune(self.handle, ptr, flags, num_ticks, self.stream.cuda_stream)
+
+    def launch_shape(self, shape: dict | None = None) -> dict:
+        """Set (if given) and return the launch shape."""
+        if shape is not None:
+            ranc_set_launch_shape(self.handle, shape)
+        return ranc_get_launch_shape(self.handle)
+
     def profile(self, enable: bool = True):
         ranc_profile_enable(self.handle, enable)
         return self
@@ -287,3 +340,38 @@ class RancNet:
             for k, v in self.counters(s).items():
                 tot[k] += v
         return tot
+
+
+def run_batch(nets, inputs, num_ticks: int, graph: bool = False):
+    """Advance several RancNets together: per tick one launch per path for all
+    of them (ranc_run_ticks with num_nets > 1). ``inputs``: one entry per net,
+    each None or an array as for :meth:`RancNet.run`; the non-None entries must
+    be all numpy arrays (host) or all CUDA tensors (device)."""
+    flags = RANC_RUN_GRAPH if graph else 0
+    ptrs, keep = [], []
+    kinds = set()
+    for g, x in zip(nets, inputs):
+        if x is None:
+            ptrs.append(None)
+            continue
+        if isinstance(x, np.ndarray):
+            a = np.ascontiguousarray(x, dtype=np.uint32)
+            assert a.shape[:2] == (g.S, num_ticks), a.shape
+            kinds.add("host")
+            keep.append(a)
+            ptrs.append(a.ctypes.data)
+        else:
+            assert x.is_cuda and x.is_contiguous() and x.element_size() == 4
+            assert tuple(x.shape[:2]) == (g.S, num_ticks), tuple(x.shape)
+            kinds.add("device")
+            keep.append(x)
+            ptrs.append(x.data_ptr())
+    if len(kinds) > 1:
+        raise ValueError("batch inputs must be all host arrays or all device tensors")
+    if kinds == {"device"}:
+        flags |= RANC_INPUTS_ON_DEVICE
+    stream = nets[0].stream
+    ranc_run_ticks([g.handle for g in nets], ptrs, flags, num_ticks, stream.cuda_stream)
+    if kinds == {"host"}:
+        stream.synchronize()   # host buffers must outlive the staging copies
+    return nets

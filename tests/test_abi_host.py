@@ -201,3 +201,33 @@ def test_tiny_validation_net_from_pins_rejected_shape(R):
     net = make_net(1, 1, 1, dest_kind=W.DEST_OUT)
     st, msg, _ = ws_status(R, net)
     assert R.STATUS_NAMES[st] == "RANC_EUNSUPPORTED"
+
+
+def test_sparse_path_shapes(R):
+    net = W.random_net(9, 4, 256, 256, 4, grid_w=2, config_id=602)
+    st, msg, b_sparse = ws_status(R, net, S=64, path=R.RANC_PATH_SPARSE)
+    assert st == R.RANC_OK, msg
+    st, msg, b_mfma = ws_status(R, net, S=64, path=R.RANC_PATH_MFMA)
+    assert st == R.RANC_OK, msg
+    # the sparse path keeps crossbar rows (A*N/8 bytes per core), not int8 weight planes
+    assert b_sparse < b_mfma
+    big = W.random_net(10, 2, 64, 512, 8, grid_w=2, config_id=603)
+    st, msg, _ = ws_status(R, big, S=64, path=R.RANC_PATH_SPARSE)
+    assert R.STATUS_NAMES[st] == "RANC_EUNSUPPORTED" and "sparse" in msg
+    st, msg, _ = ws_status(R, net, S=64, path=4)
+    assert st == R.RANC_EINVAL
+
+
+def test_tuning_calls_reject_null_handles(R):
+    t = R.ranc_tune()
+    assert R._lib.ranc_autotune(None, None, 0, 1, None, ctypes.byref(t)) == R.RANC_EINVAL
+    assert R._lib.ranc_set_launch_shape(None, ctypes.byref(t)) == R.RANC_EINVAL
+    assert R._lib.ranc_get_launch_shape(None, ctypes.byref(t)) == R.RANC_EINVAL
+    assert R._lib.ranc_run_ticks(None, 2, None, R.RANC_RUN_GRAPH, 1, None) == R.RANC_EINVAL
+
+
+def test_autotune_cache_key_names_the_shape():
+    from paper_2404_16208_amd import autotune
+    net = W.random_net(11, 4, 128, 256, 2, weight_bits=7, max_delay=3, grid_w=2, config_id=604)
+    k = autotune.shape_key(net, 96, "mfma", "MI355X")
+    assert k == "MI355X|mfma|C4A128N256G2b7D3S96"

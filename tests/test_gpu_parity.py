@@ -23,7 +23,7 @@ def _gpu():
 
 # ----------------------------------------------------------- tiny 5-core net
 
-@pytest.mark.parametrize("path", ["plain", "mfma"])
+@pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
 def test_tiny_net_all_samples(path):
     net = W.tiny_net(0)
     x = W.tiny_inputs(0, S=10, T=16)
@@ -50,7 +50,7 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "C{}A{}N{}G{}b{}P{}D{}".format(*s[:7]))
-@pytest.mark.parametrize("path", ["plain", "auto"])
+@pytest.mark.parametrize("path", ["plain", "auto", "sparse"])
 def test_random_shapes(shape, path):
     C, A, N, G, b, P, D, gw, S, T = shape
     wmax = (1 << (b - 1)) - 1
@@ -78,7 +78,7 @@ def test_no_input_no_output_cores():
     net = W.random_net(78, 4, 64, 128, 2, max_delay=2, grid_w=2, p_core=1.0, p_out=0.0,
                        leak_range=(5, 20), thr_range=(10, 40), input_cores=[], config_id=702)
     assert len(net.input_cores) == 0 and not (net.dest_kind == W.DEST_OUT).any()
-    for path in ("plain", "mfma"):
+    for path in ("plain", "mfma", "sparse"):
         g = gpu_run(net, None, 9, path, S=64)
         ref = oracle_results(net, None, 9, [0])[0]
         for s in (0, 31, 63):
@@ -99,7 +99,7 @@ def test_mfma_many_tiles_per_workgroup(spw, monkeypatch):
 
 # ----------------------------------------------------------- resume / state
 
-@pytest.mark.parametrize("path", ["plain", "mfma"])
+@pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
 def test_chunked_run_equals_single_run(path):
     net = W.random_net(79, 6, 128, 128, 4, max_delay=5, grid_w=3, density=0.3, p_core=0.7, p_out=0.3,
                        input_cores=[0, 1, 2], config_id=703)
@@ -108,7 +108,7 @@ def test_chunked_run_equals_single_run(path):
     assert_parity(net, x, 17, path, chunks=[5, 5, 7], what="chunked")
 
 
-@pytest.mark.parametrize("path", ["plain", "mfma"])
+@pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
 def test_device_inputs_and_reset(path):
     net = W.tiny_net(0)
     x = W.tiny_inputs(0, S=64, T=16)
@@ -121,6 +121,145 @@ def test_device_inputs_and_reset(path):
     for i, s in enumerate((0, 63)):
         assert np.array_equal(g.potentials(s), v_before[i])
         assert np.array_equal(g.spikes(s), e_before[i])
+
+
+@pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
+def test_graph_replay_matches_eager(path):
+    """The tick loop captured as one HIP graph (first call) and replayed
+    (later calls, with eager copies, reads and synchronizations between
+    them): every replay equals the per-launch run, the end state equals the
+    oracle, and a replay after reset starts again from tick 0."""
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.random_net(82, 6, 256, 256, 4, weight_bits=9, max_delay=4, grid_w=3, density=0.2, p_core=0.85,
+                       p_out=0.15, input_cores=[0, 1, 2], config_id=706)
+    S, TC, NC = 70, 6, 4          # 4 calls of 6 ticks; Q = 5, so the slot phase moves between calls
+    x = W.bernoulli_inputs(16, net, S, TC * NC, 0.3, config_id=706)
+    ge = RancNet(net, S, TC, path=path)
+    gg = RancNet(net, S, TC, path=path)
+    xbuf = torch.empty((S, TC) + x.shape[2:], dtype=torch.int32, device="cuda")
+    samples = [0, 5, 63, 64, 69]
+    first = {}
+    for call in range(NC):
+        log(f"[graph/{path}] call {call}")
+        chunk = np.ascontiguousarray(x[:, call * TC:(call + 1) * TC])
+        ge.run(chunk, TC)
+        xbuf.copy_(torch.from_numpy(chunk.view(np.int32)))
+        if call == NC - 1:
+            gg.profile(True)
+        gg.run(xbuf, TC, graph=True)
+        torch.cuda.synchronize()
+        for s in samples:
+            assert np.array_equal(ge.potentials(s), gg.potentials(s)), (call, s)
+            assert np.array_equal(ge.spikes(s), gg.spikes(s)), (call, s)
+            assert ge.counters(s) == gg.counters(s), (call, s)
+            if call == 0:
+                first[s] = (gg.potentials(s), gg.spikes(s), gg.counters(s))
+    prof = gg.profile_read()
+    assert prof["graph_launches"] == 1 and prof["integrate_launches"] == 0 and prof["graph_ms"] > 0
+    ref = oracle_results(net, x, TC * NC, samples)
+    for s in samples:
+        assert_sample_equal(gg, ref[s], s, TC * NC, what=f"graph/{path}")
+    gg.reset()
+    xbuf.copy_(torch.from_numpy(np.ascontiguousarray(x[:, :TC]).view(np.int32)))
+    gg.run(xbuf, TC, graph=True)
+    torch.cuda.synchronize()
+    assert gg.tick == TC
+    for s in samples:
+        v, e, c = first[s]
+        assert np.array_equal(gg.potentials(s), v) and np.array_equal(gg.spikes(s), e) and gg.counters(s) == c
+
+
+def _small_sweep_variants(limit_neuron_axons=1 << 22):
+    out = []
+    for v in range(64):
+        r = W.rng_for(0, 4, 7000 + v)
+        C = int(2 ** r.integers(4, 13))
+        A = int(r.choice([64, 128, 256, 512]))
+        N = int(r.choice([64, 128, 256, 512]))
+        if C * A * N <= limit_neuron_axons:
+            out.append(v)
+    return out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_of_uneven_variants(graph):
+    """Design-space sweep variants of different core counts, core sizes, axon
+    types and weight precisions (both paths) advanced together, one launch per
+    tick and path, in two calls; plus a 6-core net on each path with its own
+    sample count. Every network equals the oracle on sampled instances and
+    equals the same network run alone on every instance."""
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet, run_batch
+    vs = _small_sweep_variants()
+    assert len(vs) >= 8
+    nets = [W.sweep_variant(0, v)[0] for v in vs]
+    nets.append(W.random_net(83, 6, 256, 256, 4, weight_bits=9, max_delay=4, grid_w=3, input_cores=[0, 1],
+                             config_id=707))
+    nets.append(W.random_net(84, 4, 128, 512, 2, weight_bits=6, potential_bits=12, max_delay=3, grid_w=2,
+                             input_cores=[1, 3], config_id=708))
+    S = [64] * len(vs) + [70, 5]
+    T, TC = 12, 6
+    xs = [W.bernoulli_inputs(17, n, s, T, 0.1, config_id=709) for n, s in zip(nets, S)]
+    log(f"[batch] {len(nets)} networks, graph={graph}")
+    gs = [RancNet(n, s, TC) for n, s in zip(nets, S)]
+    paths = [g.path for g in gs]
+    assert "mfma" in paths and "plain" in paths
+    bufs = [torch.empty((s, TC) + x.shape[2:], dtype=torch.int32, device="cuda") for s, x in zip(S, xs)]
+    for call in range(T // TC):
+        for b, x in zip(bufs, xs):
+            b.copy_(torch.from_numpy(np.ascontiguousarray(x[:, call * TC:(call + 1) * TC]).view(np.int32)))
+        run_batch(gs, bufs, TC, graph=graph)
+        torch.cuda.synchronize()
+    alone = []
+    for n, s, x in zip(nets, S, xs):
+        g = RancNet(n, s, TC)
+        for call in range(T // TC):
+            g.run(np.ascontiguousarray(x[:, call * TC:(call + 1) * TC]), TC)
+        alone.append(g)
+    torch.cuda.synchronize()
+    for i, (g, a) in enumerate(zip(gs, alone)):
+        assert g.tick == T
+        for s in range(S[i]):
+            assert np.array_equal(g.potentials(s), a.potentials(s)), (nets[i].name, s)
+            assert g.counters(s) == a.counters(s), (nets[i].name, s)
+            assert np.array_equal(g.spikes(s), a.spikes(s)), (nets[i].name, s)
+        samples = [0, S[i] - 1]
+        ref = oracle_results(nets[i], xs[i], T, samples)
+        for s in samples:
+            assert_sample_equal(g, ref[s], s, T, what=f"batch/{nets[i].name}/{g.path}")
+
+
+@pytest.mark.parametrize("path", ["plain", "mfma"])
+def test_autotune_keeps_results_exact(path, tmp_path):
+    """The autotuner times every launch shape, keeps the fastest and returns
+    the state to tick 0; results with the tuned shape equal the oracle; the
+    JSON cache gives a second handle the same shape without tuning."""
+    from paper_2404_16208_amd import autotune
+    from paper_2404_16208_amd.ranc import RancNet
+    N = 512 if path == "plain" else 256
+    net = W.random_net(85, 6, 256, N, 4, weight_bits=9, max_delay=4, grid_w=3, input_cores=[0, 1, 2],
+                       config_id=710)
+    S, T = 200, 8
+    x = W.bernoulli_inputs(18, net, S, T, 0.2, config_id=710)
+    g = RancNet(net, S, T, path=path)
+    cache = str(tmp_path / "shapes.json")
+    shape = autotune.tuned(g, x, 4, cache_path=cache)
+    assert not shape["cached"] and shape["candidates"] >= 2 and shape["ms_per_tick"] > 0
+    assert g.tick == 0
+    if path == "mfma":
+        assert shape["samples_per_wg"] in (64, 128, 256)
+    else:
+        assert shape["route_samples_per_block"] in (1, 2, 4, 8) and shape["route_split"] >= 1
+    g.run(x, T)
+    ref = oracle_results(net, x, T, [0, 99, 199])
+    for s, r in ref.items():
+        assert_sample_equal(g, r, s, T, what=f"autotuned/{path}")
+    g2 = RancNet(net, S, T, path=path)
+    shape2 = autotune.tuned(g2, x, 4, cache_path=cache)
+    assert shape2["cached"]
+    for k in ("samples_per_wg", "route_samples_per_block", "route_split", "route_stage"):
+        assert shape2[k] == shape[k], k
 
 
 def test_read_window_errors():
@@ -185,7 +324,7 @@ def test_mnist512_batched_1024_samples():
 
 # ----------------------------------------------------------- saturation edges
 
-@pytest.mark.parametrize("path", ["plain", "mfma"])
+@pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
 @pytest.mark.parametrize("pbits", [32, 2, 7])
 def test_saturation_extremes(path, pbits):
     """Potentials at the ends of the P-bit range, leaks at +-2^30, thresholds
@@ -203,3 +342,34 @@ def test_saturation_extremes(path, pbits):
     net.threshold[:] = r.choice(np.array([2**31 - 1, -2**31, hi, lo, 0, 100], np.int64), size=shape)
     x = W.bernoulli_inputs(14, net, 70, 12, 0.4, config_id=704)
     assert_parity(net, x, 12, path, what=f"saturation_P{pbits}")
+
+
+# ----------------------------------------------------------- large sparse mesh (reduced)
+
+def test_sparse_mesh_paths_agree():
+    """The large sparse mesh shape (random destinations over the mesh, delays
+    up to 15, 1-5% input rates) at 16 x 16 cores: the event-driven path
+    against the oracle on sampled instances and against the MFMA path on
+    every instance, over 2 calls of 10 ticks."""
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.sparse_mesh_net(0, side=16)
+    S, T, TC = 64, 20, 10
+    x = W.sparse_mesh_inputs(0, net, S, T)
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    gs = RancNet(net, S, TC, path="sparse")
+    gm = RancNet(net, S, TC, path="mfma")
+    for call in range(T // TC):
+        chunk = xd[:, call * TC:(call + 1) * TC].contiguous()
+        gs.run(chunk, TC)
+        gm.run(chunk, TC)
+    torch.cuda.synchronize()
+    for s in range(S):
+        assert np.array_equal(gs.potentials(s), gm.potentials(s)), s
+        assert np.array_equal(gs.spikes(s), gm.spikes(s)), s
+        assert gs.counters(s) == gm.counters(s), s
+    ref = oracle_results(net, x, T, [0, 37, 63])
+    for s, r in ref.items():
+        assert_sample_equal(gs, r, s, T, what="sparse16x16/sparse")
+    tot = gs.total_counters()
+    assert tot["delivered"] > 0 and tot["events"] > 0
