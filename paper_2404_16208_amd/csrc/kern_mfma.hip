@@ -71,6 +71,9 @@ static constexpr int WAIT_LGKMCNT0 = 0xC07F;
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// cache-policy bits of a global-to-LDS load: non-temporal
+static constexpr int CPOL_NT = 2;
+
 int mfma_max_samples_per_wg() { return MFMA_SPW_MAX; }
 
 template <bool WIDE> struct RawWord { typedef uint32_t type; };
@@ -262,7 +265,9 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
         }
     };
     // Potentials of a tile go from HBM straight into this wave's LDS region,
-    // one tile ahead of their use.
+    // one tile ahead of their use, as non-temporal (streaming) loads: they are
+    // used once per tick, and keeping them out of L2 leaves it to the weight
+    // planes and the history words that later tiles read again.
     auto prefetch_v = [&](int s0) {
 #pragma unroll
         for (int t = 0; t < STW; ++t) {
@@ -270,7 +275,7 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 __builtin_amdgcn_global_load_lds((const void *)(vb_in + ((size_t)g * 4 + q) * 64),
-                                                 (lds_void *)&v_lds[wave][t][q][0], 16, 0, 0);
+                                                 (lds_void *)&v_lds[wave][t][q][0], 16, 0, CPOL_NT);
         }
         compiler_fence();   // issue now, not later in the iteration
     };

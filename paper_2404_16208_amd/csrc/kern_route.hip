@@ -309,7 +309,7 @@ hipError_t launch_reset_state(const DevNet &n, hipStream_t st)
     const size_t spk_words = hist ? 0 : (size_t)n.S * n.C * n.NW;
     const size_t hist_words = hist ? (size_t)n.Q * n.C * n.N * (n.S64 / 64) * 2 : 0;
     const size_t raster_words = hist ? (size_t)n.RT * n.Nout * (n.S64 / 64) * 2 : (size_t)n.RT * n.S * n.Wout;
-    const size_t cnt_words = (size_t)n.C * n.S * CNT_N * 2;
+    const size_t cnt_words = (size_t)n.C * n.cnt_rows * n.S * CNT_N * 2;
     if (ring_words)
         hipLaunchKernelGGL(k_fill_u32, dim3(2048), dim3(256), 0, st, n.ring, ring_words);
     if (spk_words)

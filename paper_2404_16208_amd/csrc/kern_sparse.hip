@@ -27,6 +27,8 @@
 // from LDS and adds bit * weight for its neurons. The neurons' spike bits of
 // the wave's samples are collected per lane and ORed across the eight waves
 // in LDS, giving each neuron's 64-sample history word of the tile.
+#include <type_traits>
+
 #include "kern_bits.h"
 #include "kern_common.h"
 #include "ranc_internal.h"
@@ -35,8 +37,6 @@ namespace ranc {
 
 static constexpr int SP_TS = 64;        // samples per tile
 static constexpr int SP_SPW_MAX = 512;  // samples per workgroup (LDS counters)
-
-template <int NPL> struct RowWords { typedef uint32_t type[NPL]; };
 
 template <int A_, int N_, int G_>
 __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
@@ -228,14 +228,34 @@ __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta,
 #pragma unroll
                 for (int w = 0; w < W_; ++w) {
                     uint32_t bits = xw[w] & tm[g * W_ + w];   // wave-uniform
+                    // up to four spiking axons per round, their row reads in flight together
                     while (bits) {
-                        const int a = 32 * w + __builtin_ctz(bits);
-                        bits &= bits - 1u;
-                        events += dg[a];
-                        const uint32_t *row = &xr[a * NW_ + h * NPL];
+                        int a[4];
+                        bool v[4];
 #pragma unroll
-                        for (int j = 0; j < NPL; ++j)
-                            acc[j] += (int32_t)((row[j] >> lj) & 1u) * wt[g][j];
+                        for (int u = 0; u < 4; ++u) {
+                            v[u] = bits != 0u;
+                            a[u] = v[u] ? 32 * w + __builtin_ctz(bits) : 0;
+                            bits &= bits - 1u;
+                        }
+                        uint32_t row[4][NPL];
+                        unsigned d[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            d[u] = dg[a[u]];
+#pragma unroll
+                            for (int j = 0; j < NPL; ++j)
+                                row[u][j] = xr[a[u] * NW_ + h * NPL + j];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (v[u]) {   // wave-uniform
+                                events += d[u];
+#pragma unroll
+                                for (int j = 0; j < NPL; ++j)
+                                    acc[j] += (int32_t)((row[u][j] >> lj) & 1u) * wt[g][j];
+                            }
+                        }
                     }
                 }
             }

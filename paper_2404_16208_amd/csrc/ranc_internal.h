@@ -44,7 +44,8 @@
 //                              sigma(b) = 8((b%16)/4) + 4(b/16) + b%4
 //   raster   u64 [RT][Nout][HG] output-bus spikes of tick t in row t%RT, words as hist
 //   both:
-//   cnt      u64 [C][S][5]     emitted, routed, delivered, out, events
+//   cnt      u64 [C*cnt_rows][S][5]  emitted, routed, delivered, out, events (summed over
+//                              the rows of a core when read)
 //   tick     i32 [4]           scheduler slot (t % Q) and raster row (t % RT) of the
 //                              first tick of the next call, and t as two u32 halves;
 //                              kept on the device so a captured tick loop replays
@@ -65,6 +66,7 @@ static constexpr long long RT_MAX_NEURONS = 1LL << 23;
 
 struct DevNet {
     int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, vlayout;
+    int cnt_rows;   // counter rows per core, summed when read
     int32_t vmin, vmax;
     // parameters
     const uint32_t *colbits, *typemask;

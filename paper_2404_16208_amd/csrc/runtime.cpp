@@ -888,6 +888,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     DevNet &n = net->dn;
     n.C = p.C; n.A = p.A; n.N = p.N; n.G = p.G; n.W = p.W; n.NW = p.NW; n.D = p.D; n.Q = p.Q;
     n.S = p.S; n.S64 = p.S64; n.RT = p.RT; n.Wout = p.Wout; n.Nout = p.Nout; n.Cin = p.Cin;
+    n.cnt_rows = 1;
     n.vlayout = p.path == RANC_PATH_MFMA ? VLAYOUT_BRICK : p.path == RANC_PATH_SPARSE ? VLAYOUT_SPARSE : VLAYOUT_CSN;
     n.vmin = (int32_t)(-(1LL << (desc->potential_bits - 1)));
     n.vmax = (int32_t)((1LL << (desc->potential_bits - 1)) - 1);
@@ -1135,13 +1136,14 @@ ranc_status ranc_read_counters(ranc_net *net, int32_t sample, ranc_counters *out
     const Plan &p = net->p;
     if (sample < 0 || sample >= p.S)
         return fail(RANC_EINVAL, "sample %d out of range", sample);
-    net->cnt_host.resize((size_t)p.C * p.S * CNT_N);
+    const int rows = p.C * net->dn.cnt_rows;   // counter rows: one per core, or per 128-neuron group
+    net->cnt_host.resize((size_t)rows * p.S * CNT_N);
     ranc_status st = refresh_mirror(net, net->dn.cnt, net->cnt_host.size() * 8, net->cnt_host.data(),
                                     net->cnt_version, "reading counters");
     if (st != RANC_OK)
         return st;
     unsigned long long sum[CNT_N] = {0, 0, 0, 0, 0};
-    for (int c = 0; c < p.C; ++c)
+    for (int c = 0; c < rows; ++c)
         for (int k = 0; k < CNT_N; ++k)
             sum[k] += net->cnt_host[((size_t)c * p.S + sample) * CNT_N + k];
     out->emitted = sum[CNT_EMITTED];
