@@ -3,14 +3,16 @@
 // axon's weights to its connected neurons, leak/threshold/reset, and the
 // scheduler write of this tick's spikes.
 //
-// Integration (GPU-RANC Sec. II) visits only spiking axons: for every axon a
-// that spikes in a sample, every neuron n connected to it adds its weight for
-// a's type. With spike rates of a few percent this is a few hundred additions
-// per (core, sample) instead of the dense A x N contraction, and it needs
-// neither the weight planes of the MFMA path nor the per-neuron crossbar
-// columns of the plain path: only the core's crossbar rows (A x N bits), its
-// axon-type masks and the neurons' G weights, all held on chip for the
-// workgroup's whole chunk of samples.
+// Integration (GPU-RANC Sec. II) touches only the spiking axons' part of the
+// crossbar: a neuron's input is the sum over axon types g of (number of
+// spiking axons of type g connected to it) * its weight for g, and the count
+// is a popcount of (the neuron's crossbar column word) AND (the sample's
+// spiking axons of type g) per 32-axon word. Words with no spiking axon, and
+// types with no spiking axon in a word, are skipped (wave-uniform tests), so
+// the work follows the activity: with spike rates of a few percent most of
+// the A/32 x G buckets are empty. It needs neither the weight planes of the
+// MFMA path nor LDS tiles per sample: the core's crossbar columns, type masks
+// and the neurons' G weights are loaded once per workgroup.
 //
 // Scheduler and delivery are those of the MFMA path (same layouts): a
 // sample-sliced spike history of the last Q = D + 1 ticks, gathered by the
@@ -21,12 +23,11 @@
 // Mapping: one workgroup of 8 wavefronts per (core, chunk of samples), 64
 // samples per tile; wave w handles samples w, w + 8, ..., w + 56 of the tile,
 // one at a time, with lane l owning neurons l, l + 64, ... (N/64 per lane). A
-// sample's axon words are wave-uniform, so the loop over its spiking axons
-// (per axon type, so the type is static inside the loop) runs in scalar
-// registers; per spiking axon each lane reads its part of the crossbar row
-// from LDS and adds bit * weight for its neurons. The neurons' spike bits of
-// the wave's samples are collected per lane and ORed across the eight waves
-// in LDS, giving each neuron's 64-sample history word of the tile.
+// sample's axon words are wave-uniform, so the bucket tests run on scalar
+// registers; per non-empty word each lane reads its neurons' column words
+// from LDS, per non-empty bucket it adds popcounts. The neurons' spike bits
+// of the wave's samples are collected per lane and ORed across the eight
+// waves in LDS, giving each neuron's 64-sample history word of the tile.
 #include <type_traits>
 
 #include "kern_bits.h"
@@ -38,8 +39,11 @@ namespace ranc {
 static constexpr int SP_TS = 64;        // samples per tile
 static constexpr int SP_SPW_MAX = 512;  // samples per workgroup (LDS counters)
 
+// Four waves per SIMD (two workgroups per CU) where the per-lane weights,
+// type counts and prefetched potentials fit in 128 VGPRs without spilling.
 template <int A_, int N_, int G_>
-__global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(N_ <= 128 || (N_ == 256 && A_ == 256 && G_ <= 4) ? 4 : 2)))
+void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
 {
     constexpr int W_ = A_ / 32;          // axon words
     constexpr int NW_ = N_ / 32;         // neuron words per crossbar row
@@ -48,12 +52,11 @@ __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta,
     constexpr int GPW = APW == 8 ? 2 : 1;  // 32-sample groups gathered per wave
     typedef typename std::conditional<GPW == 2, uint64_t, uint32_t>::type RawT;
 
-    // crossbar rows, lane-friendly: xr[a][h][j] = row word h + 2j (neurons
-    // 32h + 64j .. +31), so lane l reads its NPL words at (a, l / 32)
-    __shared__ __attribute__((aligned(16))) uint32_t xr[A_ * NW_];
+    // crossbar columns: bit b of col[w][n] = crossbar(32w + b, n)
+    __shared__ uint32_t col[W_][N_];
     __shared__ uint32_t tm[G_ * W_];                   // axon-type masks
-    __shared__ uint16_t dg[A_];                        // connected neurons per axon
     __shared__ uint32_t x_lds[2][SP_TS][W_ + 1];        // delivered axon words per sample
+    __shared__ uint32_t xe_lds[2][SP_TS][W_ + 1];       // external input words per sample
     __shared__ unsigned long long hacc[N_];            // the tile's spike words per neuron
     // per sample of the chunk: [0] emitted | routed << 10 | out << 20,
     // [1] events | delivered << 18
@@ -68,18 +71,10 @@ __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta,
     const int s_begin = chunk * spw;
     const int s_end = min(n.S, s_begin + spw);
 
-    for (int i = threadIdx.x; i < A_ * NW_; i += blockDim.x) {
-        const int a = i / NW_, w = i % NW_;
-        xr[a * NW_ + (w & 1) * NPL + (w >> 1)] = n.xrow[((size_t)c * A_ + a) * NW_ + w];
-    }
+    for (int i = threadIdx.x; i < W_ * N_; i += blockDim.x)
+        (&col[0][0])[i] = n.colbits[(size_t)c * W_ * N_ + i];
     for (int i = threadIdx.x; i < G_ * W_; i += blockDim.x)
         tm[i] = n.typemask[(size_t)c * G_ * W_ + i];
-    for (int a = threadIdx.x; a < A_; a += blockDim.x) {
-        unsigned d = 0;
-        for (int w = 0; w < NW_; ++w)
-            d += __popc(n.xrow[((size_t)c * A_ + a) * NW_ + w]);
-        dg[a] = (uint16_t)d;
-    }
     for (int i = threadIdx.x; i < N_; i += blockDim.x)
         hacc[i] = 0ull;
     for (int i = threadIdx.x; i < 2 * SP_SPW_MAX; i += blockDim.x)
@@ -171,12 +166,22 @@ __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta,
         }
     };
 
+    // external input words of a tile into LDS (all threads, coalesced per sample)
+    auto stage_ext = [&](int s0, int buf) {
+        for (int i = threadIdx.x; i < SP_TS * W_; i += blockDim.x) {
+            const int t = i / W_, w = i % W_;
+            const int s = s0 + t;
+            xe_lds[buf][t][w] = (ext_c && s < s_end) ? ext_c[(size_t)s * ta.ext_sstride + w] : 0u;
+        }
+    };
+
     RawT mraw[FMAX] = {};
     if (gatherer) {
         load_mask(s_begin, mraw);
         transpose_store(mask_of(mraw), 0);
         load_mask(s_begin + SP_TS, mraw);
     }
+    stage_ext(s_begin, 0);
     __syncthreads();
 
     int it = 0;
@@ -187,27 +192,24 @@ __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta,
 #pragma unroll
         for (int j = 0; j < NPL; ++j)
             hw[j] = 0ull;
-        // potentials of the wave's first sample of the tile
-        int32_t vnext[NPL];
-        {
-            const int s = min(s0 + wave, s_end - 1);
+        // the potentials of PF of the wave's eight samples of the tile are
+        // loaded together, ahead of their use
+        constexpr int PF = NPL >= 4 ? 4 : 8;
+        for (int i0 = 0; i0 < 8; i0 += PF) {
+        int32_t vbuf[PF][NPL];
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int s = min(s0 + wave + 8 * (i0 + i), s_end - 1);
 #pragma unroll
             for (int j = 0; j < NPL; ++j)
-                vnext[j] = vc[(size_t)s * N_ + 64 * j];
+                vbuf[i][j] = vc[(size_t)s * N_ + 64 * j];
         }
-        for (int t = wave; t < SP_TS; t += 8) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int t = wave + 8 * (i0 + i);
             const int s = s0 + t;
             if (s >= s_end)
                 break;   // wave-uniform
-            int32_t vcur[NPL];
-#pragma unroll
-            for (int j = 0; j < NPL; ++j)
-                vcur[j] = vnext[j];
-            if (t + 8 < SP_TS && s + 8 < s_end) {
-#pragma unroll
-                for (int j = 0; j < NPL; ++j)
-                    vnext[j] = vc[(size_t)(s + 8) * N_ + 64 * j];
-            }
             // the sample's axon words: delivered | external input
             uint32_t xw[W_];
             unsigned delivered = 0;
@@ -215,57 +217,52 @@ __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta,
             for (int w = 0; w < W_; ++w) {
                 const uint32_t xd = __builtin_amdgcn_readfirstlane(x_lds[buf][t][w]);
                 delivered += __popc(xd);
-                xw[w] = xd | (ext_c ? ext_c[(size_t)s * ta.ext_sstride + w] : 0u);
+                xw[w] = xd | __builtin_amdgcn_readfirstlane(xe_lds[buf][t][w]);
             }
-            int32_t acc[NPL];
+            // per type, spiking connected axons of each of this lane's neurons
+            unsigned cnt[G_][NPL];
 #pragma unroll
-            for (int j = 0; j < NPL; ++j)
-                acc[j] = lk[j];
-            unsigned events = 0;
-            const int lj = lane & 31;
+            for (int g = 0; g < G_; ++g)
 #pragma unroll
-            for (int g = 0; g < G_; ++g) {
+                for (int j = 0; j < NPL; ++j)
+                    cnt[g][j] = 0u;
 #pragma unroll
-                for (int w = 0; w < W_; ++w) {
-                    uint32_t bits = xw[w] & tm[g * W_ + w];   // wave-uniform
-                    // up to four spiking axons per round, their row reads in flight together
-                    while (bits) {
-                        int a[4];
-                        bool v[4];
+            for (int w = 0; w < W_; ++w) {
+                if (!xw[w])
+                    continue;   // wave-uniform
+                uint32_t cw[NPL];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            v[u] = bits != 0u;
-                            a[u] = v[u] ? 32 * w + __builtin_ctz(bits) : 0;
-                            bits &= bits - 1u;
-                        }
-                        uint32_t row[4][NPL];
-                        unsigned d[4];
+                for (int j = 0; j < NPL; ++j)
+                    cw[j] = col[w][lane + 64 * j];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            d[u] = dg[a[u]];
+                for (int g = 0; g < G_; ++g) {
+                    const uint32_t m = xw[w] & tm[g * W_ + w];   // wave-uniform
+                    if (!m)
+                        continue;
 #pragma unroll
-                            for (int j = 0; j < NPL; ++j)
-                                row[u][j] = xr[a[u] * NW_ + h * NPL + j];
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            if (v[u]) {   // wave-uniform
-                                events += d[u];
-#pragma unroll
-                                for (int j = 0; j < NPL; ++j)
-                                    acc[j] += (int32_t)((row[u][j] >> lj) & 1u) * wt[g][j];
-                            }
-                        }
-                    }
+                    for (int j = 0; j < NPL; ++j)
+                        cnt[g][j] += (unsigned)__popc(cw[j] & m);
                 }
             }
+            int32_t acc[NPL];
+            unsigned ev = 0;
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+                acc[j] = lk[j];
+#pragma unroll
+                for (int g = 0; g < G_; ++g) {
+                    acc[j] += __mul24((int)cnt[g][j], wt[g][j]);
+                    ev += cnt[g][j];
+                }
+            }
+            const unsigned events = wave_sum(ev);
             // leak was the accumulator's start; threshold, reset
             unsigned emitted = 0, routed = 0, out = 0;
             const int pos = 32 * (t >> 5) + sigma32_inv(t & 31);
 #pragma unroll
             for (int j = 0; j < NPL; ++j) {
                 int32_t vn;
-                const bool fire = lif_update(vcur[j], acc[j], 0, th[j], rs[j], vmin, vmax, vn);
+                const bool fire = lif_update(vbuf[i][j], acc[j], 0, th[j], rs[j], vmin, vmax, vn);
                 vc[(size_t)s * N_ + 64 * j] = vn;
                 hw[j] |= fire ? (1ull << pos) : 0ull;
                 const unsigned long long m = __ballot(fire);
@@ -279,6 +276,7 @@ __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta,
                 s_cnt[0][s - s_begin] = emitted | (routed << 10) | (out << 20);
                 s_cnt[1][s - s_begin] = events | (delivered << 18);
             }
+        }
         }
         // the tile's spike words of every neuron: OR of the eight waves' bits
 #pragma unroll
@@ -295,9 +293,12 @@ __global__ __launch_bounds__(512) void k_integrate_sparse(DevNet n, TickArgs ta,
             if (oi >= 0)
                 reinterpret_cast<uint64_t *>(n.raster)[((size_t)r_row * n.Nout + oi) * HG + tile] = w;
         }
-        if (s0 + SP_TS < s_end && gatherer) {
-            transpose_store(mask_of(mraw), (it + 1) & 1);
-            load_mask(s0 + 2 * SP_TS, mraw);
+        if (s0 + SP_TS < s_end) {
+            if (gatherer) {
+                transpose_store(mask_of(mraw), (it + 1) & 1);
+                load_mask(s0 + 2 * SP_TS, mraw);
+            }
+            stage_ext(s0 + SP_TS, (it + 1) & 1);
         }
         __syncthreads();
     }

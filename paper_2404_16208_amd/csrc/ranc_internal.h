@@ -6,7 +6,7 @@
 // RT retained raster ticks, Wout output words, Nout output neurons.
 //
 // Parameters (written once at load):
-//   colbits  u32 [C][W][N]     bit b of colbits[c][w][n] = crossbar(c, 32w+b, n)   (plain path)
+//   colbits  u32 [C][W][N]     bit b of colbits[c][w][n] = crossbar(c, 32w+b, n)   (plain, sparse)
 //   typemask u32 [C][G][W]     bit b of typemask[c][g][w] = (type(c, 32w+b) == g)
 //   wts      i32 [C][G][N]     weight of neuron n for axon type g
 //   leak, thr, rst, vinit i32 [C][N]
@@ -23,7 +23,6 @@
 //   degb     u32 [C][2][A/4]   (MFMA path) connected neurons per axon, low byte
 //                              plane then high byte plane, 4 axons per word
 //   planes   int8 MFMA B operand tiles (MFMA path), see kern_mfma.hip
-//   xrow     u32 [C][A][NW]    (sparse path) crossbar rows as given: bit n%32 of word n/32
 //   rtx_ptr  u32 [C*A + 1], rtx_ent u32 [E]  (MFMA path) the same routing table keyed by
 //                              destination axon: entries (source neuron c*N + n) << 4 | (delay - 1)
 // State:
@@ -76,7 +75,6 @@ struct DevNet {
     const uint16_t *rt_dcnt;
     const uint32_t *rt_goff, *rt_ent;
     const int32_t *outidx;
-    const uint32_t *xrow;        // crossbar rows [C][A][NW] (sparse path)
     const uint32_t *degb;
     const uint4 *planes;
     const uint32_t *rtx_ptr, *rtx_ent;

@@ -42,7 +42,7 @@ ranc_status hip_fail(hipError_t e, const char *what)
 
 enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
-    R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_XROW, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
+    R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
     R_PARAMS_END,  // everything before this is uploaded once at load
     R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_TICK, R_BATCH, R_EXT, R_NREG
 };
@@ -226,8 +226,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     const bool mf = p.path == RANC_PATH_MFMA;
     const bool sp = p.path == RANC_PATH_SPARSE;
     const bool tiled = mf || sp;   // sample-tiled paths: spike history, neuron-major raster
-    p.size[R_COLBITS] = tiled ? 0 : C * W * N * 4;
-    p.size[R_XROW] = sp ? C * A * NW * 4 : 0;
+    p.size[R_COLBITS] = mf ? 0 : C * W * N * 4;
     p.size[R_TYPEMASK] = C * G * W * 4;
     p.size[R_WTS] = C * G * N * 4;
     p.size[R_LEAK] = p.size[R_THR] = p.size[R_RST] = p.size[R_VINIT] = C * N * 4;
@@ -389,8 +388,6 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
         for (size_t i = 0; i < (size_t)C * N; ++i)
             oi[i] = d->dest_kind[i] == RANC_DEST_OUT ? next++ : -1;
     }
-    if (p.size[R_XROW])
-        memcpy(at(R_XROW), d->crossbar, (size_t)C * A * NW * 4);
     if (p.size[R_PLANES]) {
         // B tiles: [C][N/32][A/32][planes][64 lanes][16 bytes]; lane l, byte b of
         // k-step k covers axon 32k + 16(l/32) + b and neuron 32nb + l%32.
@@ -908,7 +905,6 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.rt_ent = (const uint32_t *)reg(R_RTENT);
     n.degb = (const uint32_t *)reg(R_DEGB);
     n.outidx = (const int32_t *)reg(R_OUTIDX);
-    n.xrow = (const uint32_t *)reg(R_XROW);
     n.planes = (const uint4 *)reg(R_PLANES);
     n.V = (int32_t *)reg(R_V);
     n.ring = (uint32_t *)reg(R_RING);
