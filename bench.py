@@ -208,6 +208,59 @@ def bench_sparse_mesh(args, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args, torch, np):
+    """Uneven design-space sweep: 64 seeded network variants (cores 16..4096,
+    axons and neurons 64..512, 2-8 axon types, 4-9 bit weights) with 64
+    samples each, advanced together (one launch per tick and path, graph
+    replay), against the same networks advanced one after another."""
+    from paper_2404_16208_amd import workloads as W
+    from paper_2404_16208_amd.ranc import RancNet, run_batch
+
+    S, T = 64, 8
+    nets, xs = [], []
+    print("[bench] generating 64 sweep variants and their inputs", file=sys.stderr, flush=True)
+    for v in range(64):
+        net, _ = W.sweep_variant(0, v)
+        nets.append(net)
+        xs.append(torch.from_numpy(W.bernoulli_inputs(v, net, S, T, 0.1, config_id=4).view(np.int32)).cuda())
+    print("[bench] loading", file=sys.stderr, flush=True)
+    gs = [RancNet(n, S, T) for n in nets]
+    paths = [g.path for g in gs]
+    core_ticks = sum(n.num_cores for n in nets) * S * T
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def counters():
+        tot = 0
+        for g in gs:
+            tot += sum(g.counters(s)["events"] for s in range(S))
+        return tot
+
+    ev0 = counters()
+    ms_batch = timed(lambda: run_batch(gs, xs, T, graph=True), args.steps)
+    ev1 = counters()
+    ms_each = timed(lambda: [g.run(x, T, graph=True) for g, x in zip(gs, xs)], max(2, args.steps // 2))
+    out = {"metric": "core-ticks/s and synaptic events/s, 64-variant uneven design-space sweep in one batch",
+           "unit": "core-ticks/s", "value": core_ticks / (ms_batch / 1e3), "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "64 seeded sweep variants (cores 16..4096, axons/neurons 64..512, 2-8 types, "
+                                  "4-9 bit weights, density 0.05-0.3), 64 samples each, 8 ticks per step",
+                      "networks": 64, "mfma_networks": paths.count("mfma"), "plain_networks": paths.count("plain"),
+                      "cores_total": sum(n.num_cores for n in nets), "samples": S, "ticks_per_step": T},
+           "steps": args.steps, "ms_per_step": ms_batch, "ms_per_tick": ms_batch / T,
+           "synaptic_events_per_s": (ev1 - ev0) / ((args.steps + 1) * ms_batch / 1e3),
+           "one_by_one_ms_per_step": ms_each, "batch_speedup_vs_one_by_one": ms_each / ms_batch}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,7 +272,7 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time per-launch calls instead of graph replays")
-    ap.add_argument("--workload", default="mnist512", choices=["mnist512", "sparse-mesh"],
+    ap.add_argument("--workload", default="mnist512", choices=["mnist512", "sparse-mesh", "sweep"],
                     help="mnist512: the headline line (default); sparse-mesh: the event-driven vs dense "
                          "comparison on the 16384-core mesh")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -242,6 +295,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "sparse-mesh":
         bench_sparse_mesh(args, torch, np)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args, torch, np)
         return
     S, T = args.samples, args.ticks
     print(f"[bench] generating 512-core net and {S}x{T} inputs", file=sys.stderr, flush=True)

@@ -17,8 +17,7 @@ namespace ranc {
 // One (core, sample) on a workgroup of at least N threads (threads past N
 // take part in the ballots and the barrier only).
 template <int W_, int G_>
-__device__ __forceinline__ void integrate_plain_unit(const DevNet &n, const TickArgs &ta, int c, int s,
-                                                     unsigned (*red)[4])
+__device__ __forceinline__ void integrate_plain_unit(const DevNet &n, const TickArgs &ta, int c, int s)
 {
     const int N = n.N;
     const int jt = threadIdx.x;
@@ -76,7 +75,9 @@ __device__ __forceinline__ void integrate_plain_unit(const DevNet &n, const Tick
     if (!live)
         ev = 0;
 
-    // Spike words (ballot), counters, output raster.
+    // Spike words (ballot), counters, output raster. Each wavefront adds its
+    // 64 neurons' counts to its own counter row (no reduction across waves);
+    // wave 0 also counts the core's delivered spikes.
     const unsigned long long b = __ballot(fire);
     ev = wave_sum(ev);
     if (lane == 0 && wave < (N >> 6)) {
@@ -95,34 +96,92 @@ __device__ __forceinline__ void integrate_plain_unit(const DevNet &n, const Tick
             if (ow >= 0)
                 n.raster[((size_t)tick_row(n, ta.k) * n.S + s) * n.Wout + ow] = om;
         }
-        red[wave][0] = em;
-        red[wave][1] = ro;
-        red[wave][2] = ou;
-        red[wave][3] = ev;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long em = 0, ro = 0, ou = 0, e = 0;
-        for (int w = 0; w < (N >> 6); ++w) {
-            em += red[w][0];
-            ro += red[w][1];
-            ou += red[w][2];
-            e += red[w][3];
-        }
-        unsigned long long *cp = n.cnt + ((size_t)c * n.S + s) * CNT_N;
+        unsigned long long *cp = n.cnt + (((size_t)c * (N >> 6) + wave) * n.S + s) * CNT_N;
         cp[CNT_EMITTED] += em;
         cp[CNT_ROUTED] += ro;
-        cp[CNT_DELIVERED] += delivered;
+        if (wave == 0)
+            cp[CNT_DELIVERED] += delivered;
         cp[CNT_OUT] += ou;
-        cp[CNT_EVENTS] += e;
+        cp[CNT_EVENTS] += ev;
     }
 }
 
 template <int W_, int G_>
 __global__ __launch_bounds__(512) void k_integrate_plain(DevNet n, TickArgs ta)
 {
-    __shared__ unsigned red[8][4];
-    integrate_plain_unit<W_, G_>(n, ta, blockIdx.x, blockIdx.y, red);
+    integrate_plain_unit<W_, G_>(n, ta, blockIdx.x, blockIdx.y);
+}
+
+// The same tick for one 64-neuron block of one (core, sample) on a single
+// wavefront (the batched launch, where networks of every N share one launch
+// shape); the block's counts go to its own counter row.
+template <int W_, int G_>
+__device__ __forceinline__ void integrate_plain_wave(const DevNet &n, const TickArgs &ta, int c, int s, int nb)
+{
+    const int N = n.N;
+    const int lane = threadIdx.x & 63;
+    const uint32_t *slot = n.ring + (((size_t)tick_slot(n, ta.k) * n.S + s) * n.C + c) * W_;
+    const int ci = n.in_index[c];
+    const uint32_t *ext = (ta.ext_t != nullptr && ci >= 0)
+                              ? ta.ext_t + (size_t)s * ta.ext_sstride + (size_t)ci * W_
+                              : nullptr;
+    const uint32_t *tmask = n.typemask + (size_t)c * G_ * W_;
+    const int j = nb * 64 + lane;
+    unsigned cnt[G_];
+#pragma unroll
+    for (int g = 0; g < G_; ++g)
+        cnt[g] = 0;
+    unsigned delivered = 0;
+    const uint32_t *col = n.colbits + (size_t)c * W_ * N + j;
+    // axon words and type masks are wave-uniform (scalar loads)
+#pragma unroll 2
+    for (int w = 0; w < W_; ++w) {
+        const uint32_t r = slot[w];
+        delivered += __popc(r);
+        const uint32_t cw = col[(size_t)w * N] & (r | (ext ? ext[w] : 0u));
+#pragma unroll
+        for (int g = 0; g < G_; ++g)
+            cnt[g] += __popc(cw & tmask[g * W_ + w]);
+    }
+    const int32_t *wt = n.wts + (size_t)c * G_ * N + j;
+    int in = 0;
+    unsigned e = 0;
+#pragma unroll
+    for (int g = 0; g < G_; ++g) {
+        in += __mul24((int)cnt[g], wt[(size_t)g * N]);
+        e += cnt[g];
+    }
+    const size_t cj = (size_t)c * N + j;
+    const size_t vi = ((size_t)c * n.S + s) * N + j;
+    int32_t vnew;
+    const bool fire = lif_update(n.V[vi], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, vnew);
+    n.V[vi] = vnew;
+    const unsigned long long b = __ballot(fire);
+    const unsigned ev = wave_sum(e);
+    if (lane == 0) {
+        unsigned em = 0, ro = 0, ou = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int nw = nb * 2 + h;
+            const uint32_t wd = (uint32_t)(b >> (32 * h));
+            const size_t m = (size_t)c * n.NW + nw;
+            const uint32_t om = wd & n.outmask[m];
+            em += __popc(wd);
+            ro += __popc(wd & n.coremask[m]);
+            ou += __popc(om);
+            n.spk[((size_t)s * n.C + c) * n.NW + nw] = wd;
+            const int ow = n.outword[m];
+            if (ow >= 0)
+                n.raster[((size_t)tick_row(n, ta.k) * n.S + s) * n.Wout + ow] = om;
+        }
+        unsigned long long *cp = n.cnt + (((size_t)c * (N >> 6) + nb) * n.S + s) * CNT_N;
+        cp[CNT_EMITTED] += em;
+        cp[CNT_ROUTED] += ro;
+        if (nb == 0)
+            cp[CNT_DELIVERED] += delivered;
+        cp[CNT_OUT] += ou;
+        cp[CNT_EVENTS] += ev;
+    }
 }
 
 int plain_shape_code(int W, int G)
@@ -133,10 +192,10 @@ int plain_shape_code(int W, int G)
 }
 
 // Several networks on the plain path, one tick, one launch: unit u is
-// (core, sample) of the network whose unit range holds u.
-__global__ __launch_bounds__(512) void k_integrate_plain_batch(const BatchEntry *tab, int num, int k)
+// (64-neuron block, core, sample) of the network whose unit range holds u,
+// on one wavefront.
+__global__ __launch_bounds__(64) void k_integrate_plain_batch(const BatchEntry *tab, int num, int k)
 {
-    __shared__ unsigned red[8][4];
     const int u = blockIdx.x;
     int lo = 0, hi = num - 1;
     while (lo < hi) {
@@ -148,14 +207,15 @@ __global__ __launch_bounds__(512) void k_integrate_plain_batch(const BatchEntry 
     }
     const BatchEntry &e = tab[lo];
     const int local = u - e.unit_begin;
-    const int c = local % e.n.C, s = local / e.n.C;
+    const int nbs = e.n.N >> 6;
+    const int nb = local % nbs, c = (local / nbs) % e.n.C, s = local / nbs / e.n.C;
     TickArgs ta;
     ta.k = k;
     ta.ext_t = e.ext_base ? e.ext_base + (size_t)k * e.tick_words : nullptr;
     ta.ext_sstride = e.ext_sstride;
     switch (e.code) {
 #define RANC_PLAIN_CASE(WI, W, GI, G) \
-    case WI * 4 + GI: integrate_plain_unit<W, G>(e.n, ta, c, s, red); break;
+    case WI * 4 + GI: integrate_plain_wave<W, G>(e.n, ta, c, s, nb); break;
         RANC_PLAIN_CASE(0, 2, 0, 1) RANC_PLAIN_CASE(0, 2, 1, 2) RANC_PLAIN_CASE(0, 2, 2, 4) RANC_PLAIN_CASE(0, 2, 3, 8)
         RANC_PLAIN_CASE(1, 4, 0, 1) RANC_PLAIN_CASE(1, 4, 1, 2) RANC_PLAIN_CASE(1, 4, 2, 4) RANC_PLAIN_CASE(1, 4, 3, 8)
         RANC_PLAIN_CASE(2, 8, 0, 1) RANC_PLAIN_CASE(2, 8, 1, 2) RANC_PLAIN_CASE(2, 8, 2, 4) RANC_PLAIN_CASE(2, 8, 3, 8)
@@ -170,7 +230,7 @@ hipError_t launch_integrate_plain_batch(const BatchEntry *tab, int num, int tota
 {
     if (num < 1 || total < 1)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_integrate_plain_batch, dim3(total), dim3(512), 0, st, tab, num, k);
+    hipLaunchKernelGGL(k_integrate_plain_batch, dim3(total), dim3(64), 0, st, tab, num, k);
     return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ static constexpr long long RT_MAX_NEURONS = 1LL << 23;
 
 struct DevNet {
     int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, vlayout;
-    int cnt_rows;   // counter rows per core, summed when read
+    int cnt_rows;   // counter rows per core, summed when read (plain: one per 64 neurons)
     int32_t vmin, vmax;
     // parameters
     const uint32_t *colbits, *typemask;

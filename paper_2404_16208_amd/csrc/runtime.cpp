@@ -180,10 +180,11 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
         int chunks = (1024 + p.C - 1) / p.C;
         chunks = std::max(1, std::min(chunks, tiles));
         const int tiles_per = (tiles + chunks - 1) / chunks;
-        p.spw = std::min(64 * tiles_per, std::min(mfma_max_samples_per_wg(), sparse_max_samples_per_wg()));
+        const int cap = path == RANC_PATH_SPARSE ? sparse_max_samples_per_wg() : mfma_max_samples_per_wg();
+        p.spw = std::min(64 * tiles_per, std::min(cap, 512));
         if (const char *e = getenv("RANC_MFMA_SPW")) {
             const int v = atoi(e);
-            if (v > 0 && v % 64 == 0 && v <= mfma_max_samples_per_wg())
+            if (v > 0 && v % 64 == 0 && v <= cap)
                 p.spw = v;
         }
     }
@@ -247,7 +248,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_SPK] = tiled ? 0 : (size_t)S * C * NW * 4;
     p.size[R_HIST] = tiled ? (size_t)p.Q * C * N * HG * 8 : 0;
     p.size[R_RASTER] = tiled ? (size_t)RT * p.Nout * HG * 8 : (size_t)RT * S * p.Wout * 4;
-    p.size[R_CNT] = C * S * CNT_N * 8;
+    p.size[R_CNT] = C * (tiled ? 1 : N / 64) * S * CNT_N * 8;   // plain: one row per 64 neurons
     p.size[R_TICK] = 16;
     p.size[R_BATCH] = BATCH_TABLE_BYTES;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
@@ -662,15 +663,17 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
             b.mf.push_back(e);
         } else {
             e.code = plain_shape_code(p.W, p.G);
-            e.units = p.C * p.S;
-            e.route_code = route_shape_code(net->rcfg, p.D);
+            e.units = p.C * p.S * (p.N / 64);
+            // batched routing reads the spike bitmaps from L2 (no LDS staging,
+            // so the one launch keeps its occupancy for every network)
+            RouteCfg rc = net->rcfg;
+            rc.stage = 0;
+            e.route_code = route_shape_code(rc, p.D);
             if (e.route_code < 0)
                 return fail(RANC_EUNSUPPORTED, "nets[%d]: router shape (%d samples per block, max delay %d) "
                             "cannot run in a batch", i, net->rcfg.samples_per_block, p.D);
             e.route_split = net->rcfg.blocks_per_group;
             e.route_units = e.route_split * ((p.S + net->rcfg.samples_per_block - 1) / net->rcfg.samples_per_block);
-            if (net->rcfg.stage)
-                b.rt_lds = std::max(b.rt_lds, (size_t)p.C * p.NW * 4 * net->rcfg.samples_per_block);
             b.pl.push_back(e);
         }
     }
@@ -885,7 +888,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     DevNet &n = net->dn;
     n.C = p.C; n.A = p.A; n.N = p.N; n.G = p.G; n.W = p.W; n.NW = p.NW; n.D = p.D; n.Q = p.Q;
     n.S = p.S; n.S64 = p.S64; n.RT = p.RT; n.Wout = p.Wout; n.Nout = p.Nout; n.Cin = p.Cin;
-    n.cnt_rows = 1;
+    n.cnt_rows = p.path == RANC_PATH_PLAIN ? p.N / 64 : 1;
     n.vlayout = p.path == RANC_PATH_MFMA ? VLAYOUT_BRICK : p.path == RANC_PATH_SPARSE ? VLAYOUT_SPARSE : VLAYOUT_CSN;
     n.vmin = (int32_t)(-(1LL << (desc->potential_bits - 1)));
     n.vmax = (int32_t)((1LL << (desc->potential_bits - 1)) - 1);
@@ -1252,7 +1255,8 @@ ranc_status ranc_autotune(ranc_net *net, const uint32_t *inputs, uint32_t flags,
     if (p.path != RANC_PATH_PLAIN) {
         const int tiles = (p.S + 63) / 64;
         int last_chunks = -1;
-        for (int spw = 64; spw <= mfma_max_samples_per_wg(); spw *= 2) {
+        const int cap = p.path == RANC_PATH_SPARSE ? sparse_max_samples_per_wg() : mfma_max_samples_per_wg();
+        for (int spw = 64; spw <= cap; spw *= 2) {
             const int chunks = (tiles * 64 + spw - 1) / spw;
             if (chunks == last_chunks)
                 break;
@@ -1368,9 +1372,9 @@ ranc_status ranc_set_launch_shape(ranc_net *net, const ranc_tune *shape)
     const Plan &p = net->p;
     if (p.path != RANC_PATH_PLAIN) {
         const int v = shape->samples_per_wg;
-        if (v <= 0 || v % 64 || v > mfma_max_samples_per_wg())
-            return fail(RANC_EINVAL, "samples_per_wg %d must be a multiple of 64 in [64, %d]", v,
-                        mfma_max_samples_per_wg());
+        const int cap = p.path == RANC_PATH_SPARSE ? sparse_max_samples_per_wg() : mfma_max_samples_per_wg();
+        if (v <= 0 || v % 64 || v > cap)
+            return fail(RANC_EINVAL, "samples_per_wg %d must be a multiple of 64 in [64, %d]", v, cap);
         drop_graphs(net);
         net->p.spw = v;
         return RANC_OK;
