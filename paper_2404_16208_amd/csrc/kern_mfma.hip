@@ -87,6 +87,12 @@ template <int A_, int N_> struct MfmaLds {
     typedef int8_t ATile[MFMA_TS * ROWB];  // int8 axon spikes of a tile (x2, double buffer)
     typedef v4i VTile[STW][4][64];         // next tile's potentials (one per wave)
     typedef uint32_t XTile[MFMA_TS][XW];   // delivered axon words of a tile (x2)
+    // this tick's history words of the workgroup's neurons, collected over HB
+    // tiles and written to memory in 64-byte runs per neuron (two batches in
+    // flight when two wavefronts share a neuron's words)
+    static constexpr int HB = A_ == 512 ? 4 : 8;
+    static constexpr int HBS = STW == 1 ? 2 * HB : HB;
+    typedef uint64_t HBuf[N_][HBS];
 };
 
 // One unit of work: workgroup `bid` of the tick's grid (core bid % C, sample
@@ -94,13 +100,17 @@ template <int A_, int N_> struct MfmaLds {
 // kernel, so several shapes can share one kernel's LDS.
 // CLAMP: potentials narrower than 32 bits are clamped to [vmin, vmax] after
 // the saturating 32-bit add (with 32-bit potentials the add alone is exact).
-template <int A_, int N_, bool TWO, bool CLAMP>
+// HBUF: history words are collected in `hbuf` and written in runs of HB
+// words per neuron; otherwise each tile's word is stored at once.
+template <int A_, int N_, bool TWO, bool CLAMP, bool HBUF>
 __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickArgs &ta, int spw, int bid,
                                                     typename MfmaLds<A_, N_>::ATile *a_lds,
                                                     typename MfmaLds<A_, N_>::VTile *v_lds,
                                                     typename MfmaLds<A_, N_>::XTile *x_lds,
+                                                    typename MfmaLds<A_, N_>::HBuf *hbuf,
                                                     unsigned (*s_cnt)[MFMA_SPW_MAX])
 {
+    typedef MfmaLds<A_, N_> L;
     constexpr int NB = N_ / 32;          // 32-neuron blocks (4 or 8)
     constexpr int KS = A_ / 32;          // 32-axon k-steps
     constexpr int PL = TWO ? 2 : 1;      // B planes
@@ -296,17 +306,25 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
             for (int q = 0; q < 4; ++q)
                 __builtin_nontemporal_store(vnew[t][q], vb_out + ((size_t)sg * 4 + q) * 64);
         }
-        const int tile = ps0 / MFMA_TS;
         if (h == 0) {
-            if constexpr (STW == 2) {
-                const uint64_t w64 = (uint64_t)hword[0] | ((uint64_t)hword[STW - 1] << 32);
-                hist_out[tile] = w64;
-                if (rast_out)
-                    rast_out[tile] = w64;
+            if constexpr (HBUF) {
+                const int hslot = ((ps0 - s_begin) / MFMA_TS) % L::HBS;
+                if constexpr (STW == 2)
+                    (*hbuf)[neuron][hslot] = (uint64_t)hword[0] | ((uint64_t)hword[STW - 1] << 32);
+                else
+                    reinterpret_cast<uint32_t *>(&(*hbuf)[neuron][hslot])[stg] = hword[0];
             } else {
-                reinterpret_cast<uint32_t *>(hist_out + tile)[stg] = hword[0];
-                if (rast_out)
-                    reinterpret_cast<uint32_t *>(rast_out + tile)[stg] = hword[0];
+                const int tile = ps0 / MFMA_TS;
+                if constexpr (STW == 2) {
+                    const uint64_t w64 = (uint64_t)hword[0] | ((uint64_t)hword[STW - 1] << 32);
+                    hist_out[tile] = w64;
+                    if (rast_out)
+                        rast_out[tile] = w64;
+                } else {
+                    reinterpret_cast<uint32_t *>(hist_out + tile)[stg] = hword[0];
+                    if (rast_out)
+                        reinterpret_cast<uint32_t *>(rast_out + tile)[stg] = hword[0];
+                }
             }
 #pragma unroll
             for (int t = 0; t < STW; ++t) {
@@ -318,6 +336,24 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
         const int s = ps0 + lane;
         if (s < s_end && pdlev)
             atomicAdd(&s_cnt[1][s - s_begin], pdlev);
+    };
+
+    // history (and raster) words of chunk tiles [t0, t0 + nt) from LDS to
+    // memory: lanes jj and jj + 32 write the first and second half of the
+    // run of neuron 32nb + jj
+    auto write_hist = [&](int t0, int nt) {
+        if (!HBUF || (STW == 1 && stg != 0))
+            return;   // wave-uniform: wave stg 0 writes the neuron's words
+        const int tile0 = s_begin / MFMA_TS + t0;
+#pragma unroll
+        for (int k = h * (L::HB / 2); k < (h + 1) * (L::HB / 2); ++k) {
+            if (k < nt) {
+                const uint64_t w = (*hbuf)[neuron][(t0 + k) % L::HBS];
+                hist_out[tile0 + k] = w;
+                if (rast_out)
+                    rast_out[tile0 + k] = w;
+            }
+        }
     };
 
     prefetch_v(s_begin);
@@ -388,6 +424,9 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
             load_ext(s0 + MFMA_TS);
         }
         lds_barrier();
+        // the history words of the last HB tiles are complete in LDS
+        if (it > 0 && it % L::HB == 0)
+            write_hist(it - L::HB, L::HB);
 
         // 3. products and potential update
 #pragma unroll
@@ -443,6 +482,7 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
     flush();
     lds_barrier();
+    write_hist(it - 1 - (it - 1) % L::HB, (it - 1) % L::HB + 1);
     for (int i = threadIdx.x; i < s_end - s_begin; i += blockDim.x) {
         unsigned long long *cp = n.cnt + ((size_t)c * n.S + s_begin + i) * CNT_N;
         const unsigned sp = s_cnt[0][i], ev = s_cnt[1][i];
@@ -461,8 +501,9 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
     __shared__ __attribute__((aligned(16))) typename L::ATile a_lds[2];
     __shared__ __attribute__((aligned(16))) typename L::VTile v_lds[8];
     __shared__ typename L::XTile x_lds[2];
+    __shared__ typename L::HBuf hbuf[1];
     __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
-    integrate_mfma_unit<A_, N_, TWO, CLAMP>(n, ta, spw, blockIdx.x, a_lds, v_lds, x_lds, s_cnt);
+    integrate_mfma_unit<A_, N_, TWO, CLAMP, true>(n, ta, spw, blockIdx.x, a_lds, v_lds, x_lds, hbuf, s_cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,9 +526,9 @@ __device__ __forceinline__ void batch_unit(const BatchEntry &e, const TickArgs &
                                            v4i *v_raw, uint32_t *x_raw, unsigned (*s_cnt)[MFMA_SPW_MAX])
 {
     typedef MfmaLds<A_, N_> L;
-    integrate_mfma_unit<A_, N_, TWO, true>(e.n, ta, e.spw, bid, reinterpret_cast<typename L::ATile *>(a_raw),
-                                           reinterpret_cast<typename L::VTile *>(v_raw),
-                                           reinterpret_cast<typename L::XTile *>(x_raw), s_cnt);
+    integrate_mfma_unit<A_, N_, TWO, true, false>(e.n, ta, e.spw, bid, reinterpret_cast<typename L::ATile *>(a_raw),
+                                                  reinterpret_cast<typename L::VTile *>(v_raw),
+                                                  reinterpret_cast<typename L::XTile *>(x_raw), nullptr, s_cnt);
 }
 
 __global__ __launch_bounds__(512) void k_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k,
