@@ -95,8 +95,10 @@ template <int A_, int N_> struct MfmaLds {
     typedef uint64_t HBuf[N_][HBS];
 };
 
-// One unit of work: workgroup `bid` of the tick's grid (core bid % C, sample
-// chunk bid / C), on 512 threads. The LDS arrays come from the calling
+// One unit of work: workgroup `bid` of the tick's grid (core bid % C, then
+// neuron slice and sample chunk), on 512 threads. N_ is the slice width: a
+// core of 512 neurons runs as two slices of 256, each with its own B tiles,
+// degree counts and counter row, sharing the axon inputs of the core. The LDS arrays come from the calling
 // kernel, so several shapes can share one kernel's LDS.
 // CLAMP: potentials narrower than 32 bits are clamped to [vmin, vmax] after
 // the saturating 32-bit add (with 32-bit potentials the add alone is exact).
@@ -129,14 +131,16 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int c = bid % n.C;
-    const int chunk = bid / n.C;
+    const int slice = (bid / n.C) % n.slices;
+    const int chunk = bid / n.C / n.slices;
     const int s_begin = chunk * spw;
     const int s_end = min(n.S, s_begin + spw);
     const int h = lane >> 5, jj = lane & 31;
     const int sig = sigma32(jj);
     const int nb = wave % NB;
     const int stg = wave / NB;
-    const int neuron = nb * 32 + jj;
+    const int neuron = nb * 32 + jj;       // within the slice
+    const int nbc = slice * NB + nb;       // 32-neuron block within the core
 
     for (int i = threadIdx.x; i < 2 * MFMA_SPW_MAX; i += blockDim.x)
         (&s_cnt[0][0])[i] = 0u;
@@ -148,16 +152,17 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     for (int k = 0; k < KS; ++k)
 #pragma unroll
         for (int p = 0; p < PL; ++p)
-            breg[k][p] = planes[((((size_t)c * NB + nb) * KS + k) * PL + p) * 64 + lane];
-    const size_t cj = (size_t)c * N_ + neuron;
+            breg[k][p] = planes[((((size_t)c * n.NW + nbc) * KS + k) * PL + p) * 64 + lane];
+    const size_t cj = (size_t)c * n.N + slice * N_ + neuron;
     const int32_t lk = n.leak[cj], th = n.thr[cj], rs = n.rst[cj];
     const int32_t vmin = n.vmin, vmax = n.vmax;
     const int oi = n.outidx[cj];
-    const uint32_t cm32 = n.coremask[(size_t)c * NB + nb];
-    const uint32_t om32 = n.outmask[(size_t)c * NB + nb];
+    const uint32_t cm32 = n.coremask[(size_t)c * n.NW + nbc];
+    const uint32_t om32 = n.outmask[(size_t)c * n.NW + nbc];
 
-    // Connected-neuron counts of this wave's expansion words, low and high
-    // bytes, 4 axons per word, for the dot4 event count.
+    // Connected-neuron counts (neurons of the slice) of this wave's expansion
+    // words, low and high bytes, 4 axons per word, for the dot4 event count.
+    const size_t dg = (size_t)c * n.slices + slice;
     uint32_t degl[WPW][8], degh[WPW][8];
     bool any_hi = false;
 #pragma unroll
@@ -165,8 +170,8 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
         const int wi = wave + 8 * k;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            degl[k][q] = wi < W_ ? n.degb[((size_t)c * 2 + 0) * (A_ / 4) + wi * 8 + q] : 0u;
-            degh[k][q] = wi < W_ ? n.degb[((size_t)c * 2 + 1) * (A_ / 4) + wi * 8 + q] : 0u;
+            degl[k][q] = wi < W_ ? n.degb[(dg * 2 + 0) * (A_ / 4) + wi * 8 + q] : 0u;
+            degh[k][q] = wi < W_ ? n.degb[(dg * 2 + 1) * (A_ / 4) + wi * 8 + q] : 0u;
             any_hi |= degh[k][q] != 0u;
         }
     }
@@ -176,10 +181,10 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     const int q_now = tick_slot(n, ta.k), r_row = tick_row(n, ta.k);
     const size_t G32 = (size_t)n.S64 / 32;   // 32-sample groups
     const size_t HG = (size_t)n.S64 / 64;    // 64-sample history words per neuron
-    const size_t vbase = ((size_t)c * NB + nb) * G32 * 256 + lane;
+    const size_t vbase = ((size_t)c * n.NW + nbc) * G32 * 256 + lane;
     const v4i *vb_in = reinterpret_cast<const v4i *>(n.V) + vbase;
     v4i *vb_out = reinterpret_cast<v4i *>(n.V) + vbase;
-    const size_t CN = (size_t)n.C * N_;
+    const size_t CN = (size_t)n.C * n.N;
     uint64_t *hist_out = n.hist + ((size_t)q_now * CN + cj) * HG;
     uint64_t *rast_out =
         oi >= 0 ? reinterpret_cast<uint64_t *>(n.raster) + ((size_t)r_row * n.Nout + oi) * HG : nullptr;
@@ -484,12 +489,13 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     lds_barrier();
     write_hist(it - 1 - (it - 1) % L::HB, (it - 1) % L::HB + 1);
     for (int i = threadIdx.x; i < s_end - s_begin; i += blockDim.x) {
-        unsigned long long *cp = n.cnt + ((size_t)c * n.S + s_begin + i) * CNT_N;
+        unsigned long long *cp = n.cnt + (((size_t)c * n.cnt_rows + slice) * n.S + s_begin + i) * CNT_N;
         const unsigned sp = s_cnt[0][i], ev = s_cnt[1][i];
         cp[CNT_EMITTED] += sp & 1023u;
         cp[CNT_ROUTED] += (sp >> 10) & 1023u;
         cp[CNT_OUT] += sp >> 20;
-        cp[CNT_DELIVERED] += ev >> 18;
+        if (slice == 0)   // the core's delivered spikes, counted once
+            cp[CNT_DELIVERED] += ev >> 18;
         cp[CNT_EVENTS] += ev & ((1u << 18) - 1u);
     }
 }
@@ -598,16 +604,19 @@ hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total
 bool mfma_shape_supported(int A, int N, int two_planes)
 {
     const bool ok_a = A == 64 || A == 128 || A == 256 || A == 512;
-    // 32-neuron blocks over 8 wavefronts (4 or 8 blocks); the B tiles take
-    // A * planes / 8 VGPRs per lane, at most 64.
-    return ok_a && (N == 128 || N == 256) && A * (two_planes ? 2 : 1) <= 512;
+    // 32-neuron blocks over 8 wavefronts (4 or 8 blocks per slice, 512
+    // neurons as two slices); the B tiles take A * planes / 8 VGPRs per lane,
+    // at most 64.
+    return ok_a && (N == 128 || N == 256 || N == 512) && A * (two_planes ? 2 : 1) <= 512;
 }
+
+int mfma_slices(int N) { return N > 256 ? N / 256 : 1; }
 
 template <int A_, int N_, bool TWO>
 static void launch_mfma_k(const DevNet &n, const TickArgs &a, int spw, hipStream_t st)
 {
     const int chunks = (n.S + spw - 1) / spw;
-    const dim3 grid(n.C * chunks), block(512);
+    const dim3 grid(n.C * n.slices * chunks), block(512);
     if (n.vmin == INT32_MIN && n.vmax == INT32_MAX)
         hipLaunchKernelGGL((k_integrate_mfma<A_, N_, TWO, false>), grid, block, 0, st, n, a, spw);
     else
@@ -633,7 +642,7 @@ static hipError_t launch_mfma_an(const DevNet &n, const TickArgs &a, int two, in
 template <int A_>
 static hipError_t launch_mfma_a(const DevNet &n, const TickArgs &a, int two, int spw, hipStream_t st)
 {
-    switch (n.N) {
+    switch (n.N / n.slices) {
     case 128: return launch_mfma_an<A_, 128>(n, a, two, spw, st);
     case 256: return launch_mfma_an<A_, 256>(n, a, two, spw, st);
     default: return hipErrorInvalidValue;
@@ -643,7 +652,8 @@ static hipError_t launch_mfma_a(const DevNet &n, const TickArgs &a, int two, int
 hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes, int samples_per_wg,
                                  hipStream_t st)
 {
-    if (!mfma_shape_supported(n.A, n.N, two_planes) || samples_per_wg <= 0 || samples_per_wg % MFMA_TS ||
+    if (!mfma_shape_supported(n.A, n.N, two_planes) || n.slices != mfma_slices(n.N) || n.cnt_rows != n.slices ||
+        samples_per_wg <= 0 || samples_per_wg % MFMA_TS ||
         samples_per_wg > MFMA_SPW_MAX || n.vlayout != VLAYOUT_BRICK || n.S64 % MFMA_TS || n.S > n.S64)
         return hipErrorInvalidValue;
     switch (n.A) {

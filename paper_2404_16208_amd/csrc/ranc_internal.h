@@ -65,7 +65,8 @@ static constexpr long long RT_MAX_NEURONS = 1LL << 23;
 
 struct DevNet {
     int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, vlayout;
-    int cnt_rows;   // counter rows per core, summed when read (plain: one per 64 neurons)
+    int cnt_rows;   // counter rows per core, summed when read (plain: one per 64 neurons, MFMA: one per slice)
+    int slices;     // MFMA: neuron slices per core, one workgroup each (N / slices <= 256)
     int32_t vmin, vmax;
     // parameters
     const uint32_t *colbits, *typemask;
@@ -131,6 +132,7 @@ hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t
 hipError_t launch_reset_state(const DevNet &n, hipStream_t st);
 hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st);
 bool mfma_shape_supported(int A, int N, int two_planes);
+int mfma_slices(int N);
 int mfma_shape_code(int A, int N, int two_planes);
 int plain_shape_code(int W, int G);
 int route_shape_code(const RouteCfg &cfg, int max_delay);

@@ -49,6 +49,8 @@ enum Region {
 
 struct Plan {
     int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, path, two, spw;
+    int slices;          // MFMA: neuron slices per core (one workgroup each)
+    int cnt_rows;        // counter rows per core
     long long E;         // routed (CORE) neurons
     long long ell_words; // u32 words of the wave-interleaved routing table
     size_t off[R_NREG], size[R_NREG], params_bytes, total;
@@ -174,10 +176,13 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     if (path == RANC_PATH_SPARSE && !sparse_shape_supported(p.A, p.N, p.G))
         return fail(RANC_EUNSUPPORTED, "sparse path does not support N=%d with G=%d", p.N, p.G);
     p.path = path;
+    p.slices = path == RANC_PATH_MFMA ? mfma_slices(p.N) : 1;
+    p.cnt_rows = path == RANC_PATH_PLAIN ? p.N / 64 : p.slices;
     // Samples per workgroup (sample-tiled paths): aim for >= 1024 workgroups, in 64-sample tiles.
     {
         const int tiles = (S + 63) / 64;
-        int chunks = (1024 + p.C - 1) / p.C;
+        const int per_chunk = p.C * p.slices;   // workgroups per sample chunk
+        int chunks = (1024 + per_chunk - 1) / per_chunk;
         chunks = std::max(1, std::min(chunks, tiles));
         const int tiles_per = (tiles + chunks - 1) / chunks;
         const int cap = path == RANC_PATH_SPARSE ? sparse_max_samples_per_wg() : mfma_max_samples_per_wg();
@@ -240,7 +245,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_RTXENT] = tiled ? std::max<size_t>((size_t)E, 1) * 4 : 0;
     const size_t HG = (size_t)p.S64 / 64;
     p.size[R_HZERO] = tiled ? HG * 8 : 0;
-    p.size[R_DEGB] = mf ? C * 2 * A : 0;
+    p.size[R_DEGB] = mf ? C * p.slices * 2 * A : 0;
     p.size[R_OUTIDX] = tiled ? C * N * 4 : 0;
     p.size[R_PLANES] = mf ? C * A * N * (p.two ? 2 : 1) : 0;
     p.size[R_V] = C * (tiled ? (size_t)p.S64 : (size_t)S) * N * 4;
@@ -248,7 +253,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_SPK] = tiled ? 0 : (size_t)S * C * NW * 4;
     p.size[R_HIST] = tiled ? (size_t)p.Q * C * N * HG * 8 : 0;
     p.size[R_RASTER] = tiled ? (size_t)RT * p.Nout * HG * 8 : (size_t)RT * S * p.Wout * 4;
-    p.size[R_CNT] = C * (tiled ? 1 : N / 64) * S * CNT_N * 8;   // plain: one row per 64 neurons
+    p.size[R_CNT] = C * p.cnt_rows * S * CNT_N * 8;   // plain: one row per 64 neurons, MFMA: per slice
     p.size[R_TICK] = 16;
     p.size[R_BATCH] = BATCH_TABLE_BYTES;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
@@ -372,16 +377,20 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
                 ent[fill[dest_of(i)]++] = ((uint32_t)i << 4) | (uint32_t)(d->dest_delay[i] - 1);
     }
     if (p.size[R_DEGB]) {
-        // connected neurons per axon, as a low-byte and a high-byte plane
+        // connected neurons per axon within each neuron slice, as a low-byte
+        // and a high-byte plane: [C][slices][2][A]
         uint8_t *db = at(R_DEGB);
+        const int SL = p.slices, WS = NW / SL;
         for (int c = 0; c < C; ++c)
-            for (int a = 0; a < A; ++a) {
-                int k = 0;
-                for (int w = 0; w < NW; ++w)
-                    k += __builtin_popcount(d->crossbar[((size_t)c * A + a) * NW + w]);
-                db[((size_t)c * 2 + 0) * A + a] = (uint8_t)(k & 255);
-                db[((size_t)c * 2 + 1) * A + a] = (uint8_t)(k >> 8);
-            }
+            for (int sl = 0; sl < SL; ++sl)
+                for (int a = 0; a < A; ++a) {
+                    int k = 0;
+                    for (int w = sl * WS; w < (sl + 1) * WS; ++w)
+                        k += __builtin_popcount(d->crossbar[((size_t)c * A + a) * NW + w]);
+                    const size_t r = (size_t)c * SL + sl;
+                    db[(r * 2 + 0) * A + a] = (uint8_t)(k & 255);
+                    db[(r * 2 + 1) * A + a] = (uint8_t)(k >> 8);
+                }
     }
     if (p.size[R_OUTIDX]) {
         int32_t *oi = (int32_t *)at(R_OUTIDX);
@@ -658,8 +667,8 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         if (p.path == RANC_PATH_SPARSE)
             return fail(RANC_EUNSUPPORTED, "nets[%d]: the sparse path runs one network per call", i);
         if (p.path == RANC_PATH_MFMA) {
-            e.code = mfma_shape_code(p.A, p.N, p.two);
-            e.units = p.C * ((p.S + p.spw - 1) / p.spw);
+            e.code = mfma_shape_code(p.A, p.N / p.slices, p.two);
+            e.units = p.C * p.slices * ((p.S + p.spw - 1) / p.spw);
             b.mf.push_back(e);
         } else {
             e.code = plain_shape_code(p.W, p.G);
@@ -680,7 +689,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
     if ((int)b.mf.size() > BATCH_MAX || (int)b.pl.size() > BATCH_MAX)
         return fail(RANC_EUNSUPPORTED, "a batch holds at most %d networks per path", BATCH_MAX);
     auto work = [](const BatchEntry &e) {
-        return (double)e.spw * e.n.N * (e.n.A + 64) * ((e.code & 1) ? 2 : 1);
+        return (double)e.spw * (e.n.N / e.n.slices) * (e.n.A + 64) * ((e.code & 1) ? 2 : 1);
     };
     std::stable_sort(b.mf.begin(), b.mf.end(),
                      [&](const BatchEntry &x, const BatchEntry &y) { return work(x) > work(y); });
@@ -888,7 +897,8 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     DevNet &n = net->dn;
     n.C = p.C; n.A = p.A; n.N = p.N; n.G = p.G; n.W = p.W; n.NW = p.NW; n.D = p.D; n.Q = p.Q;
     n.S = p.S; n.S64 = p.S64; n.RT = p.RT; n.Wout = p.Wout; n.Nout = p.Nout; n.Cin = p.Cin;
-    n.cnt_rows = p.path == RANC_PATH_PLAIN ? p.N / 64 : 1;
+    n.cnt_rows = p.cnt_rows;
+    n.slices = p.slices;
     n.vlayout = p.path == RANC_PATH_MFMA ? VLAYOUT_BRICK : p.path == RANC_PATH_SPARSE ? VLAYOUT_SPARSE : VLAYOUT_CSN;
     n.vmin = (int32_t)(-(1LL << (desc->potential_bits - 1)));
     n.vmax = (int32_t)((1LL << (desc->potential_bits - 1)) - 1);
@@ -1135,7 +1145,7 @@ ranc_status ranc_read_counters(ranc_net *net, int32_t sample, ranc_counters *out
     const Plan &p = net->p;
     if (sample < 0 || sample >= p.S)
         return fail(RANC_EINVAL, "sample %d out of range", sample);
-    const int rows = p.C * net->dn.cnt_rows;   // counter rows: one per core, or per 128-neuron group
+    const int rows = p.C * net->dn.cnt_rows;   // counter rows: per core, 64-neuron block (plain) or slice (MFMA)
     net->cnt_host.resize((size_t)rows * p.S * CNT_N);
     ranc_status st = refresh_mirror(net, net->dn.cnt, net->cnt_host.size() * 8, net->cnt_host.data(),
                                     net->cnt_version, "reading counters");

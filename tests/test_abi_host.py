@@ -194,6 +194,11 @@ def test_mfma_path_unsupported_shape_reported(R):
     assert R.STATUS_NAMES[st] == "RANC_EUNSUPPORTED" and "MFMA" in msg
     st, msg, _ = ws_status(R, net, path=R.RANC_PATH_AUTO)
     assert st == R.RANC_OK, msg
+    # 512 neurons with one weight plane, or 256 axons with two, fit (two slices)
+    for A, b in ((512, 8), (256, 9)):
+        net = W.random_net(8, 4, A, 512, 2, weight_bits=b, grid_w=2, config_id=601)
+        st, msg, _ = ws_status(R, net, path=R.RANC_PATH_MFMA)
+        assert st == R.RANC_OK, (A, b, msg)
 
 
 def test_tiny_validation_net_from_pins_rejected_shape(R):

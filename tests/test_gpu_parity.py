@@ -46,6 +46,10 @@ SHAPES = [
     (4, 256, 128, 4, 9, 10, 1, 2, 129, 7),
     (4, 128, 128, 2, 9, 16, 4, 2, 130, 8),
     (2, 512, 256, 4, 8, 32, 3, 2, 100, 6),
+    # 512 neurons: two 256-neuron slices per core on the MFMA path
+    (3, 256, 512, 4, 9, 32, 4, 3, 130, 8),
+    (2, 512, 512, 2, 8, 16, 3, 2, 100, 6),
+    (4, 128, 512, 4, 6, 32, 2, 2, 70, 8),
 ]
 
 
@@ -95,6 +99,16 @@ def test_mfma_many_tiles_per_workgroup(spw, monkeypatch):
     x = W.bernoulli_inputs(15, net, 300, 9, 0.3, config_id=705)
     assert_parity(net, x, 9, "mfma", samples=[0, 1, 63, 64, 127, 128, 200, 255, 256, 298, 299],
                   what=f"spw{spw}")
+
+
+def test_mfma_neuron_slices_many_tiles(monkeypatch):
+    # 512-neuron cores as two slices, several tiles per workgroup, ragged
+    # last tile; fan-in up to 6 per axon, outputs from both slices
+    monkeypatch.setenv("RANC_MFMA_SPW", "128")
+    net = W.random_net(82, 4, 256, 512, 4, weight_bits=9, max_delay=4, grid_w=2, density=0.2, p_core=0.8,
+                       p_out=0.15, input_cores=[0, 3], config_id=706)
+    x = W.bernoulli_inputs(16, net, 200, 9, 0.3, config_id=706)
+    assert_parity(net, x, 9, "mfma", samples=[0, 1, 63, 64, 127, 128, 150, 198, 199], what="slices")
 
 
 # ----------------------------------------------------------- resume / state
