@@ -211,8 +211,10 @@ def bench_sparse_mesh(args, torch, np):
 def bench_sweep(args, torch, np):
     """Uneven design-space sweep: 64 seeded network variants (cores 16..4096,
     axons and neurons 64..512, 2-8 axon types, 4-9 bit weights) with 64
-    samples each, advanced together (one launch per tick and path, graph
-    replay), against the same networks advanced one after another."""
+    samples each, advanced together (graph replay; per tick one launch per
+    MFMA shape class and one integration and one routing launch for the
+    plain-path networks), against the same networks advanced one after
+    another, and against the batch with one persistent MFMA launch per tick."""
     from paper_2404_16208_amd import workloads as W
     from paper_2404_16208_amd.ranc import RancNet, run_batch
 
@@ -248,6 +250,7 @@ def bench_sweep(args, torch, np):
     ev0 = counters()
     ms_batch = timed(lambda: run_batch(gs, xs, T, graph=True), args.steps)
     ev1 = counters()
+    ms_pers = timed(lambda: run_batch(gs, xs, T, graph=True, persistent=True), max(2, args.steps // 2))
     ms_each = timed(lambda: [g.run(x, T, graph=True) for g, x in zip(gs, xs)], max(2, args.steps // 2))
     out = {"metric": "core-ticks/s and synaptic events/s, 64-variant uneven design-space sweep in one batch",
            "unit": "core-ticks/s", "value": core_ticks / (ms_batch / 1e3), "n_gpus": 1, "data": "synthetic",
@@ -257,7 +260,8 @@ def bench_sweep(args, torch, np):
                       "cores_total": sum(n.num_cores for n in nets), "samples": S, "ticks_per_step": T},
            "steps": args.steps, "ms_per_step": ms_batch, "ms_per_tick": ms_batch / T,
            "synaptic_events_per_s": (ev1 - ev0) / ((args.steps + 1) * ms_batch / 1e3),
-           "one_by_one_ms_per_step": ms_each, "batch_speedup_vs_one_by_one": ms_each / ms_batch}
+           "one_by_one_ms_per_step": ms_each, "batch_speedup_vs_one_by_one": ms_each / ms_batch,
+           "persistent_queue_ms_per_step": ms_pers}
     print(json.dumps(out), flush=True)
 
 

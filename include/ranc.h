@@ -69,6 +69,11 @@ enum {
  * read from a tick counter kept in the workspace, so a replay is exact from
  * any starting tick. Results are identical to the per-launch form. */
 #define RANC_RUN_GRAPH 2u
+/* With several networks per call: run the MFMA-path networks of each tick in
+ * one persistent launch (one workgroup per compute unit pulls units from a
+ * work queue, largest first; LDS sized for the largest shape) instead of one
+ * launch per shape class. Results are identical. */
+#define RANC_BATCH_PERSISTENT 4u
 
 /*
  * Network description (host memory; the library copies it during
@@ -158,15 +163,16 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples,
  * RANC_INPUTS_ON_DEVICE, else in host memory (copied to the workspace's
  * staging area first). Consecutive calls continue the same simulation:
  * spikes whose delivery tick lies beyond the call stay scheduled.
- * flags: RANC_INPUTS_ON_DEVICE, RANC_RUN_GRAPH (see above); other bits are
- * rejected with RANC_EINVAL. With RANC_RUN_GRAPH and device inputs, the
+ * flags: RANC_INPUTS_ON_DEVICE, RANC_RUN_GRAPH, RANC_BATCH_PERSISTENT (see
+ * above); other bits are rejected with RANC_EINVAL. With RANC_RUN_GRAPH and device inputs, the
  * input buffer must stay at the same address to reuse a captured loop.
  *
  * With num_nets > 1 the networks (any shapes, paths and sample counts; each
- * at most once) advance together: per tick, one persistent launch runs the
- * units of every MFMA-path network from a shared work queue (largest units
- * first), and one launch each integrates and routes every plain-path
- * network. The batch tables are kept in the workspace of nets[0] (at most
+ * at most once) advance together: per tick, one launch per MFMA shape class
+ * (axons, neurons per workgroup, weight planes, potential clamp) runs every
+ * MFMA-path network of that class (or, with RANC_BATCH_PERSISTENT, one
+ * persistent launch runs all of them from a work queue), and one launch each
+ * integrates and routes every plain-path network. The batch tables are kept in the workspace of nets[0] (at most
  * 128 networks per path); they are rebuilt, with a synchronization of
  * `stream`, whenever the list of networks, the input addresses or num_ticks
  * change. Results are identical to running each network alone.

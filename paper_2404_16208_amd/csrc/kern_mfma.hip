@@ -601,6 +601,72 @@ hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Several networks of one shape class (A, slice width, planes, clamp) in one
+// launch: workgroup u runs unit u - e.unit_begin of the table entry e whose
+// unit range holds u (entries numbered from 0 within the class). The LDS is
+// exactly the shape's, as in the single-network kernel.
+template <int A_, int N_, bool TWO, bool CLAMP>
+__global__ __launch_bounds__(512) void k_integrate_mfma_group(const BatchEntry *tab, int num, int k)
+{
+    typedef MfmaLds<A_, N_> L;
+    __shared__ __attribute__((aligned(16))) typename L::ATile a_lds[2];
+    __shared__ __attribute__((aligned(16))) typename L::VTile v_lds[8];
+    __shared__ typename L::XTile x_lds[2];
+    __shared__ typename L::HBuf hbuf[1];
+    __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
+    const int u = blockIdx.x;
+    int lo = 0, hi = num - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].unit_begin <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchEntry &e = tab[lo];
+    TickArgs ta;
+    ta.k = k;
+    ta.ext_t = e.ext_base ? e.ext_base + (size_t)k * e.tick_words : nullptr;
+    ta.ext_sstride = e.ext_sstride;
+    integrate_mfma_unit<A_, N_, TWO, CLAMP, true>(e.n, ta, e.spw, u - e.unit_begin, a_lds, v_lds, x_lds, hbuf,
+                                                  s_cnt);
+}
+
+template <int A_, int N_, bool TWO>
+static void launch_group_k(const BatchEntry *tab, int num, int total, int k, int clamp, hipStream_t st)
+{
+    if (clamp)
+        hipLaunchKernelGGL((k_integrate_mfma_group<A_, N_, TWO, true>), dim3(total), dim3(512), 0, st, tab, num, k);
+    else
+        hipLaunchKernelGGL((k_integrate_mfma_group<A_, N_, TWO, false>), dim3(total), dim3(512), 0, st, tab, num, k);
+}
+
+hipError_t launch_integrate_mfma_group(const BatchEntry *tab, int num, int total, int k, int code, int clamp,
+                                       hipStream_t st)
+{
+    if (num < 1 || total < 1)
+        return hipErrorInvalidValue;
+    switch (code) {
+    case 0: launch_group_k<64, 128, false>(tab, num, total, k, clamp, st); break;
+    case 1: launch_group_k<64, 128, true>(tab, num, total, k, clamp, st); break;
+    case 2: launch_group_k<64, 256, false>(tab, num, total, k, clamp, st); break;
+    case 3: launch_group_k<64, 256, true>(tab, num, total, k, clamp, st); break;
+    case 4: launch_group_k<128, 128, false>(tab, num, total, k, clamp, st); break;
+    case 5: launch_group_k<128, 128, true>(tab, num, total, k, clamp, st); break;
+    case 6: launch_group_k<128, 256, false>(tab, num, total, k, clamp, st); break;
+    case 7: launch_group_k<128, 256, true>(tab, num, total, k, clamp, st); break;
+    case 8: launch_group_k<256, 128, false>(tab, num, total, k, clamp, st); break;
+    case 9: launch_group_k<256, 128, true>(tab, num, total, k, clamp, st); break;
+    case 10: launch_group_k<256, 256, false>(tab, num, total, k, clamp, st); break;
+    case 11: launch_group_k<256, 256, true>(tab, num, total, k, clamp, st); break;
+    case 12: launch_group_k<512, 128, false>(tab, num, total, k, clamp, st); break;
+    case 14: launch_group_k<512, 256, false>(tab, num, total, k, clamp, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 bool mfma_shape_supported(int A, int N, int two_planes)
 {
     const bool ok_a = A == 64 || A == 128 || A == 256 || A == 512;

@@ -20,14 +20,19 @@
 // as neuron-major history words. Bits within a 32-sample group follow the
 // order sigma32 of kern_bits.h, so both paths read and write the same words.
 //
-// Mapping: one workgroup of 8 wavefronts per (core, chunk of samples), 64
-// samples per tile; wave w handles samples w, w + 8, ..., w + 56 of the tile,
-// one at a time, with lane l owning neurons l, l + 64, ... (N/64 per lane). A
-// sample's axon words are wave-uniform, so the bucket tests run on scalar
+// Mapping: one workgroup per (core, chunk of samples), 64 samples per tile,
+// of 4 wavefronts (8 when A = 512, whose history gather needs 8); wave w of
+// the workgroup's nw waves handles samples w, w + nw, ... of the tile, one at
+// a time, with lane l owning neurons l, l + 64, ... (N/64 per lane). Small
+// workgroups keep several independent workgroups per compute unit: with few
+// samples per core a workgroup is a short chain of dependent memory
+// accesses, and the chains of different workgroups overlap. A sample's axon
+// words are wave-uniform, so the bucket tests run on scalar
 // registers; per non-empty word each lane reads its neurons' column words
 // from LDS, per non-empty bucket it adds popcounts. The neurons' spike bits
-// of the wave's samples are collected per lane and ORed across the eight
-// waves in LDS, giving each neuron's 64-sample history word of the tile.
+// of the wave's samples are collected per lane and ORed across the
+// workgroup's waves in LDS, giving each neuron's 64-sample history word of
+// the tile.
 #include <type_traits>
 
 #include "kern_bits.h"
@@ -39,17 +44,23 @@ namespace ranc {
 static constexpr int SP_TS = 64;        // samples per tile
 static constexpr int SP_SPW_MAX = 512;  // samples per workgroup (LDS counters)
 
-// Four waves per SIMD (two workgroups per CU) where the per-lane weights,
-// type counts and prefetched potentials fit in 128 VGPRs without spilling.
+template <int A_> constexpr int sp_waves() { return A_ == 512 ? 8 : 4; }
+
+// Four waves per SIMD where the per-lane weights, type counts and prefetched
+// potentials fit in 128 VGPRs without spilling.
 template <int A_, int N_, int G_>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(N_ <= 128 || (N_ == 256 && A_ == 256 && G_ <= 4) ? 4 : 2)))
+__global__ __launch_bounds__(64 * sp_waves<A_>()) __attribute__((amdgpu_waves_per_eu(N_ <= 128 || (N_ == 256 && A_ == 256 && G_ <= 4) ? 4 : 2)))
 void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
 {
+    constexpr int NWV = sp_waves<A_>();  // wavefronts per workgroup
     constexpr int W_ = A_ / 32;          // axon words
     constexpr int NW_ = N_ / 32;         // neuron words per crossbar row
     constexpr int NPL = N_ / 64;         // neurons per lane: lane + 64 j
     constexpr int APW = A_ / 64;         // 64-axon blocks of the gather
-    constexpr int GPW = APW == 8 ? 2 : 1;  // 32-sample groups gathered per wave
+    // 32-sample groups gathered per wave: both when the (block, group) pairs
+    // outnumber the waves
+    constexpr int GPW = 2 * APW > NWV ? 2 : 1;
+    static_assert(APW * 2 / GPW <= NWV, "gather roles exceed the workgroup's waves");
     typedef typename std::conditional<GPW == 2, uint64_t, uint32_t>::type RawT;
 
     // crossbar columns: bit b of col[w][n] = crossbar(32w + b, n)
@@ -102,8 +113,9 @@ void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
     int32_t *vc = n.V + (size_t)c * n.S64 * N_ + lane;
 
     // ---- history gather (as on the MFMA path): wave w collects, for axon
-    // block w % APW, group w / APW of each tile's history bits.
-    const bool gatherer = wave < 2 * APW;
+    // block w % APW, group w / APW of each tile's history bits (both groups
+    // with GPW = 2).
+    const bool gatherer = wave < 2 * APW / GPW;
     const int axb = wave % APW;
     const int grp = GPW == 2 ? 0 : wave / APW;
     const int ga = axb * 64 + lane;
@@ -192,21 +204,22 @@ void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
 #pragma unroll
         for (int j = 0; j < NPL; ++j)
             hw[j] = 0ull;
-        // the potentials of PF of the wave's eight samples of the tile are
-        // loaded together, ahead of their use
+        // the potentials of PF of the wave's samples of the tile are loaded
+        // together, ahead of their use
         constexpr int PF = NPL >= 4 ? 4 : 8;
-        for (int i0 = 0; i0 < 8; i0 += PF) {
+        constexpr int SPW = SP_TS / NWV;   // samples per wave per tile
+        for (int i0 = 0; i0 < SPW; i0 += PF) {
         int32_t vbuf[PF][NPL];
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
-            const int s = min(s0 + wave + 8 * (i0 + i), s_end - 1);
+            const int s = min(s0 + wave + NWV * (i0 + i), s_end - 1);
 #pragma unroll
             for (int j = 0; j < NPL; ++j)
                 vbuf[i][j] = vc[(size_t)s * N_ + 64 * j];
         }
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
-            const int t = wave + 8 * (i0 + i);
+            const int t = wave + NWV * (i0 + i);
             const int s = s0 + t;
             if (s >= s_end)
                 break;   // wave-uniform
@@ -278,7 +291,7 @@ void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
             }
         }
         }
-        // the tile's spike words of every neuron: OR of the eight waves' bits
+        // the tile's spike words of every neuron: OR of the waves' bits
 #pragma unroll
         for (int j = 0; j < NPL; ++j)
             if (hw[j])
@@ -328,7 +341,7 @@ template <int A_, int N_>
 static hipError_t launch_sparse_an(const DevNet &n, const TickArgs &a, int spw, hipStream_t st)
 {
     const int chunks = (n.S + spw - 1) / spw;
-    const dim3 grid(n.C * chunks), block(512);
+    const dim3 grid(n.C * chunks), block(64 * sp_waves<A_>());
     switch (n.G) {
     case 1: hipLaunchKernelGGL((k_integrate_sparse<A_, N_, 1>), grid, block, 0, st, n, a, spw); break;
     case 2: hipLaunchKernelGGL((k_integrate_sparse<A_, N_, 2>), grid, block, 0, st, n, a, spw); break;

@@ -141,6 +141,8 @@ hipError_t launch_route_batch(const BatchEntry *tab, int num, int total, int k, 
 hipError_t launch_advance_batch(const BatchEntry *tab, int num, int num_ticks, unsigned *queue, hipStream_t st);
 hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k, unsigned *queue,
                                        int workgroups, hipStream_t st);
+hipError_t launch_integrate_mfma_group(const BatchEntry *tab, int num, int total, int k, int code, int clamp,
+                                       hipStream_t st);
 RouteCfg route_default_cfg(const DevNet &n);
 int route_dmax(int max_delay);
 int mfma_max_samples_per_wg();

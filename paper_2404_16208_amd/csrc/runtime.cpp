@@ -454,6 +454,10 @@ struct Batch {
     std::vector<const uint32_t *> bases;
     int num_ticks = 0;
     std::vector<BatchEntry> mf, pl;
+    // MFMA shape classes (one launch each per tick), unless persistent
+    struct Group { int first, num, units, code, clamp; };
+    std::vector<Group> groups;
+    bool persistent = false;
     int mf_units = 0, pl_units = 0, rt_units = 0, mf_workgroups = 0;
     size_t rt_lds = 0;
     hipGraph_t graph = nullptr;
@@ -643,8 +647,10 @@ static int device_cu_count()
 // Build the host tables of a batch (entries sorted by decreasing work per
 // unit, so the persistent MFMA launch hands out the largest units first).
 static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *const *bases,
-                               int num_ticks, Batch &b)
+                               int num_ticks, bool persistent, Batch &b)
 {
+    b.persistent = persistent;
+    b.groups.clear();
     b.nets.assign(nets, nets + num);
     b.uids.clear();
     for (int i = 0; i < num; ++i)
@@ -691,12 +697,37 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
     auto work = [](const BatchEntry &e) {
         return (double)e.spw * (e.n.N / e.n.slices) * (e.n.A + 64) * ((e.code & 1) ? 2 : 1);
     };
-    std::stable_sort(b.mf.begin(), b.mf.end(),
-                     [&](const BatchEntry &x, const BatchEntry &y) { return work(x) > work(y); });
+    auto clamp = [](const BatchEntry &e) { return e.n.vmin == INT32_MIN && e.n.vmax == INT32_MAX ? 0 : 1; };
     long long mu = 0, pu = 0, ru = 0;
-    for (auto &e : b.mf) {
-        e.unit_begin = (int)mu;
-        mu += e.units;
+    if (persistent) {
+        // one unit numbering, largest units first
+        std::stable_sort(b.mf.begin(), b.mf.end(),
+                         [&](const BatchEntry &x, const BatchEntry &y) { return work(x) > work(y); });
+        for (auto &e : b.mf) {
+            e.unit_begin = (int)mu;
+            mu += e.units;
+        }
+    } else {
+        // shape classes, each numbered from 0, largest units first within a class
+        std::stable_sort(b.mf.begin(), b.mf.end(), [&](const BatchEntry &x, const BatchEntry &y) {
+            if (x.code != y.code)
+                return x.code < y.code;
+            if (clamp(x) != clamp(y))
+                return clamp(x) < clamp(y);
+            return work(x) > work(y);
+        });
+        for (size_t i = 0; i < b.mf.size(); ++i) {
+            BatchEntry &e = b.mf[i];
+            if (b.groups.empty() || b.groups.back().code != e.code || b.groups.back().clamp != clamp(e))
+                b.groups.push_back({(int)i, 0, 0, e.code, clamp(e)});
+            Batch::Group &g = b.groups.back();
+            if ((long long)g.units + e.units > INT32_MAX)
+                return fail(RANC_EUNSUPPORTED, "batch has too many work units");
+            e.unit_begin = g.units;
+            g.units += e.units;
+            g.num += 1;
+            mu += e.units;
+        }
     }
     for (auto &e : b.pl) {
         e.unit_begin = (int)pu;
@@ -733,8 +764,11 @@ static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t
         hipError_t e = hipSuccess;
         if (!b.mf.empty()) {
             e = timed ? prof_begin(lead, 0, s, &slot) : hipSuccess;
-            if (e == hipSuccess)
+            if (e == hipSuccess && b.persistent)
                 e = launch_integrate_mfma_batch(tmf, (int)b.mf.size(), b.mf_units, k, queue, b.mf_workgroups, s);
+            for (size_t g = 0; e == hipSuccess && !b.persistent && g < b.groups.size(); ++g)
+                e = launch_integrate_mfma_group(tmf + b.groups[g].first, b.groups[g].num, b.groups[g].units, k,
+                                                b.groups[g].code, b.groups[g].clamp, s);
             if (e == hipSuccess && timed)
                 e = prof_end(lead, slot, s);
             if (e != hipSuccess)
@@ -771,11 +805,11 @@ static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t
 // RANC_RUN_GRAPH) is reused while the same networks, input addresses and
 // tick count repeat.
 static ranc_status run_batch(ranc_net *const *nets, int num, const uint32_t *const *bases, int num_ticks,
-                             bool graph, hipStream_t s)
+                             bool graph, bool persistent, hipStream_t s)
 {
     ranc_net *lead = nets[0];
     Batch &b = lead->batch;
-    bool same = b.num_ticks == num_ticks && (int)b.nets.size() == num &&
+    bool same = b.num_ticks == num_ticks && b.persistent == persistent && (int)b.nets.size() == num &&
                 std::equal(b.nets.begin(), b.nets.end(), nets) && std::equal(b.bases.begin(), b.bases.end(), bases);
     for (int i = 0; same && i < num; ++i)
         same = b.uids[i] == nets[i]->uid;
@@ -788,7 +822,7 @@ static ranc_status run_batch(ranc_net *const *nets, int num, const uint32_t *con
         b.graph = nullptr;
         b.num_ticks = 0;
         Batch nb;
-        ranc_status st = build_batch(nets, num, bases, num_ticks, nb);
+        ranc_status st = build_batch(nets, num, bases, num_ticks, persistent, nb);
         if (st != RANC_OK)
             return st;
         // the previous tables may still be read by queued work
@@ -808,6 +842,8 @@ static ranc_status run_batch(ranc_net *const *nets, int num, const uint32_t *con
         b.bases = std::move(nb.bases);
         b.mf = std::move(nb.mf);
         b.pl = std::move(nb.pl);
+        b.groups = std::move(nb.groups);
+        b.persistent = nb.persistent;
         b.mf_units = nb.mf_units;
         b.pl_units = nb.pl_units;
         b.rt_units = nb.rt_units;
@@ -980,7 +1016,7 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
         if (num_ticks < 1 || num_ticks > nets[i]->p.RT)
             return fail(RANC_EINVAL, "num_ticks %d outside [1, max_ticks_per_call=%d]", num_ticks, nets[i]->p.RT);
     }
-    if (flags & ~(RANC_INPUTS_ON_DEVICE | RANC_RUN_GRAPH))
+    if (flags & ~(RANC_INPUTS_ON_DEVICE | RANC_RUN_GRAPH | RANC_BATCH_PERSISTENT))
         return fail(RANC_EINVAL, "unknown flags 0x%x", flags);
     for (int i = 0; i < num_nets; ++i)
         for (int j = 0; j < i; ++j)
@@ -1006,7 +1042,8 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
         bases[i] = base;
     }
     if (num_nets > 1) {
-        ranc_status st = run_batch(nets, num_nets, bases.data(), num_ticks, (flags & RANC_RUN_GRAPH) != 0, s);
+        ranc_status st = run_batch(nets, num_nets, bases.data(), num_ticks, (flags & RANC_RUN_GRAPH) != 0,
+                                   (flags & RANC_BATCH_PERSISTENT) != 0, s);
         if (st != RANC_OK)
             return st;
     } else {

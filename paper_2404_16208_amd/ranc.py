@@ -25,6 +25,7 @@ RANC_PATH_AUTO, RANC_PATH_PLAIN, RANC_PATH_MFMA, RANC_PATH_SPARSE = 0, 1, 2, 3
 PATHS = {"auto": RANC_PATH_AUTO, "plain": RANC_PATH_PLAIN, "mfma": RANC_PATH_MFMA, "sparse": RANC_PATH_SPARSE}
 RANC_INPUTS_ON_DEVICE = 1
 RANC_RUN_GRAPH = 2
+RANC_BATCH_PERSISTENT = 4
 
 EXPORTED = ("ranc_last_error", "ranc_workspace_bytes", "ranc_load_network", "ranc_run_ticks",
             "ranc_read_spikes", "ranc_read_potentials", "ranc_read_counters", "ranc_current_tick",
@@ -342,12 +343,14 @@ class RancNet:
         return tot
 
 
-def run_batch(nets, inputs, num_ticks: int, graph: bool = False):
-    """Advance several RancNets together: per tick one launch per path for all
-    of them (ranc_run_ticks with num_nets > 1). ``inputs``: one entry per net,
+def run_batch(nets, inputs, num_ticks: int, graph: bool = False, persistent: bool = False):
+    """Advance several RancNets together (ranc_run_ticks with num_nets > 1):
+    per tick one launch per MFMA shape class, or one persistent work-queue
+    launch for all MFMA-path nets with ``persistent``, and one integration and
+    one routing launch for all plain-path nets. ``inputs``: one entry per net,
     each None or an array as for :meth:`RancNet.run`; the non-None entries must
     be all numpy arrays (host) or all CUDA tensors (device)."""
-    flags = RANC_RUN_GRAPH if graph else 0
+    flags = (RANC_RUN_GRAPH if graph else 0) | (RANC_BATCH_PERSISTENT if persistent else 0)
     ptrs, keep = [], []
     kinds = set()
     for g, x in zip(nets, inputs):

@@ -196,11 +196,12 @@ def _small_sweep_variants(limit_neuron_axons=1 << 22):
     return out
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_of_uneven_variants(graph):
+@pytest.mark.parametrize("graph,persistent", [(False, False), (True, False), (False, True), (True, True)])
+def test_batch_of_uneven_variants(graph, persistent):
     """Design-space sweep variants of different core counts, core sizes, axon
-    types and weight precisions (both paths) advanced together, one launch per
-    tick and path, in two calls; plus a 6-core net on each path with its own
+    types and weight precisions (both paths) advanced together (per tick one
+    launch per MFMA shape class, or one persistent launch, and one per plain
+    step), in two calls; plus a 6-core net on each path with its own
     sample count. Every network equals the oracle on sampled instances and
     equals the same network run alone on every instance."""
     import torch
@@ -215,7 +216,7 @@ def test_batch_of_uneven_variants(graph):
     S = [64] * len(vs) + [70, 5]
     T, TC = 12, 6
     xs = [W.bernoulli_inputs(17, n, s, T, 0.1, config_id=709) for n, s in zip(nets, S)]
-    log(f"[batch] {len(nets)} networks, graph={graph}")
+    log(f"[batch] {len(nets)} networks, graph={graph}, persistent={persistent}")
     gs = [RancNet(n, s, TC) for n, s in zip(nets, S)]
     paths = [g.path for g in gs]
     assert "mfma" in paths and "plain" in paths
@@ -223,7 +224,7 @@ def test_batch_of_uneven_variants(graph):
     for call in range(T // TC):
         for b, x in zip(bufs, xs):
             b.copy_(torch.from_numpy(np.ascontiguousarray(x[:, call * TC:(call + 1) * TC]).view(np.int32)))
-        run_batch(gs, bufs, TC, graph=graph)
+        run_batch(gs, bufs, TC, graph=graph, persistent=persistent)
         torch.cuda.synchronize()
     alone = []
     for n, s, x in zip(nets, S, xs):
