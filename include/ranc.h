@@ -54,8 +54,9 @@ enum {
     RANC_PATH_AUTO = 0,   /* pick per shape */
     RANC_PATH_PLAIN = 1,  /* per (core, sample) workgroups, crossbar words and popcounts */
     RANC_PATH_MFMA = 2,   /* per-core workgroups over sample tiles, exact int8 MFMA;
-                             num_neurons in {128, 256, 512} (512 as two 256-neuron
-                             workgroups), num_axons * (weight_bits > 8 ? 2 : 1) <= 512 */
+                             num_axons * (weight_bits > 8 ? 2 : 1) <= 512 (512 neurons
+                             run as two 256-neuron workgroups, 64 as a 128-neuron
+                             workgroup with half its wavefronts idle) */
     RANC_PATH_SPARSE = 3  /* per-core workgroups over sample tiles, event-driven: only spiking
                              axons are visited (never chosen by RANC_PATH_AUTO) */
 };

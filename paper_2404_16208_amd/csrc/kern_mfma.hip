@@ -98,7 +98,10 @@ template <int A_, int N_> struct MfmaLds {
 // One unit of work: workgroup `bid` of the tick's grid (core bid % C, then
 // neuron slice and sample chunk), on 512 threads. N_ is the slice width: a
 // core of 512 neurons runs as two slices of 256, each with its own B tiles,
-// degree counts and counter row, sharing the axon inputs of the core. The LDS arrays come from the calling
+// degree counts and counter row, sharing the axon inputs of the core; a core
+// of 64 neurons runs as a slice of 128 whose upper two 32-neuron blocks are
+// dead (their wavefronts keep their gather and expansion roles and the
+// barriers, and skip all neuron work and memory traffic). The LDS arrays come from the calling
 // kernel, so several shapes can share one kernel's LDS.
 // CLAMP: potentials narrower than 32 bits are clamped to [vmin, vmax] after
 // the saturating 32-bit add (with 32-bit potentials the add alone is exact).
@@ -139,8 +142,11 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     const int sig = sigma32(jj);
     const int nb = wave % NB;
     const int stg = wave / NB;
-    const int neuron = nb * 32 + jj;       // within the slice
-    const int nbc = slice * NB + nb;       // 32-neuron block within the core
+    // wave-uniform; only 128-wide workgroups (64-neuron cores) have dead blocks
+    const bool live = N_ == 256 || slice * NB + nb < n.NW;
+    const int nbu = live ? nb : 0;         // block whose addresses a dead wave computes (never used)
+    const int neuron = nbu * 32 + jj;      // within the slice
+    const int nbc = slice * NB + nbu;      // 32-neuron block within the core
 
     for (int i = threadIdx.x; i < 2 * MFMA_SPW_MAX; i += blockDim.x)
         (&s_cnt[0][0])[i] = 0u;
@@ -284,6 +290,8 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     // used once per tick, and keeping them out of L2 leaves it to the weight
     // planes and the history words that later tiles read again.
     auto prefetch_v = [&](int s0) {
+        if (!live)
+            return;
 #pragma unroll
         for (int t = 0; t < STW; ++t) {
             const int g = (s0 >> 5) + stg * STW + t;
@@ -309,9 +317,10 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
             const int sg = (ps0 >> 5) + stg * STW + t;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                __builtin_nontemporal_store(vnew[t][q], vb_out + ((size_t)sg * 4 + q) * 64);
+                if (live)
+                    __builtin_nontemporal_store(vnew[t][q], vb_out + ((size_t)sg * 4 + q) * 64);
         }
-        if (h == 0) {
+        if (h == 0 && live) {
             if constexpr (HBUF) {
                 const int hslot = ((ps0 - s_begin) / MFMA_TS) % L::HBS;
                 if constexpr (STW == 2)
@@ -347,7 +356,7 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     // memory: lanes jj and jj + 32 write the first and second half of the
     // run of neuron 32nb + jj
     auto write_hist = [&](int t0, int nt) {
-        if (!HBUF || (STW == 1 && stg != 0))
+        if (!HBUF || !live || (STW == 1 && stg != 0))
             return;   // wave-uniform: wave stg 0 writes the neuron's words
         const int tile0 = s_begin / MFMA_TS + t0;
 #pragma unroll
@@ -433,55 +442,58 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
         if (it > 0 && it % L::HB == 0)
             write_hist(it - L::HB, L::HB);
 
-        // 3. products and potential update
+        // 3. products and potential update (dead blocks skip it: their
+        //    results are never stored)
+        if (live) {
 #pragma unroll
-        for (int t = 0; t < STW; ++t) {
-            const int st = stg * STW + t;
-            const int sg = (s0 >> 5) + st;   // 32-sample group
-            v16i acc_lo, acc_hi;
+            for (int t = 0; t < STW; ++t) {
+                const int st = stg * STW + t;
+                const int sg = (s0 >> 5) + st;   // 32-sample group
+                v16i acc_lo, acc_hi;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                acc_lo[r] = lk;
-                acc_hi[r] = 0;
-            }
-            const int8_t *arow = &A[(st * 32 + jj) * ROWB + 16 * h];
-#pragma unroll
-            for (int k = 0; k < KS; ++k) {
-                const v4i a = *reinterpret_cast<const v4i *>(arow + 32 * k);
-                if constexpr (TWO) {
-                    acc_hi = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][0], acc_hi, 0, 0, 0);
-                    acc_lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][1], acc_lo, 0, 0, 0);
-                } else {
-                    acc_lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][0], acc_lo, 0, 0, 0);
+                for (int r = 0; r < 16; ++r) {
+                    acc_lo[r] = lk;
+                    acc_hi[r] = 0;
                 }
-            }
-            // spike bits r of this lane, built from r = 15 down by doubling
-            uint32_t hb = 0;
+                const int8_t *arow = &A[(st * 32 + jj) * ROWB + 16 * h];
 #pragma unroll
-            for (int r = 15; r >= 0; --r) {
-                const int32_t in_leak = TWO ? acc_lo[r] + acc_hi[r] * 128 : acc_lo[r];
-                int32_t u = __builtin_elementwise_add_sat(vold[t][r >> 2][r & 3], in_leak);
-                if constexpr (CLAMP)
-                    u = min(max(u, vmin), vmax);
-                const bool fire = u >= th;
-                vnew[t][r >> 2][r & 3] = fire ? rs : u;
-                hb = hb + hb + (uint32_t)fire;
-            }
-            // samples past the end never fire (their potentials are never read)
-            if (sg * 32 + 32 > s_end) {   // wave-uniform
-                uint32_t vm = 0;
+                for (int k = 0; k < KS; ++k) {
+                    const v4i a = *reinterpret_cast<const v4i *>(arow + 32 * k);
+                    if constexpr (TWO) {
+                        acc_hi = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][0], acc_hi, 0, 0, 0);
+                        acc_lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][1], acc_lo, 0, 0, 0);
+                    } else {
+                        acc_lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, breg[k][0], acc_lo, 0, 0, 0);
+                    }
+                }
+                // spike bits r of this lane, built from r = 15 down by doubling
+                uint32_t hb = 0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    vm |= (uint32_t)(sg * 32 + 8 * (r >> 2) + 4 * h + (r & 3) < s_end) << r;
-                hb &= vm;
+                for (int r = 15; r >= 0; --r) {
+                    const int32_t in_leak = TWO ? acc_lo[r] + acc_hi[r] * 128 : acc_lo[r];
+                    int32_t u = __builtin_elementwise_add_sat(vold[t][r >> 2][r & 3], in_leak);
+                    if constexpr (CLAMP)
+                        u = min(max(u, vmin), vmax);
+                    const bool fire = u >= th;
+                    vnew[t][r >> 2][r & 3] = fire ? rs : u;
+                    hb = hb + hb + (uint32_t)fire;
+                }
+                // samples past the end never fire (their potentials are never read)
+                if (sg * 32 + 32 > s_end) {   // wave-uniform
+                    uint32_t vm = 0;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        vm |= (uint32_t)(sg * 32 + 8 * (r >> 2) + 4 * h + (r & 3) < s_end) << r;
+                    hb &= vm;
+                }
+                // the neuron's spike word: bits r from lane jj, bits 16 + r from lane jj + 32
+                const uint32_t hw = hb | ((uint32_t)__shfl_xor((int)hb, 32, 64) << 16);
+                hword[t] = hw;
+                // per-sample spike words of the wave's 32 neurons, and their counts
+                const uint32_t sw = transpose32(hw, lane);
+                pcnt[t] = (unsigned)__popc(sw) | ((unsigned)__popc(sw & cm32) << 10) |
+                          ((unsigned)__popc(sw & om32) << 20);
             }
-            // the neuron's spike word: bits r from lane jj, bits 16 + r from lane jj + 32
-            const uint32_t hw = hb | ((uint32_t)__shfl_xor((int)hb, 32, 64) << 16);
-            hword[t] = hw;
-            // per-sample spike words of the wave's 32 neurons, and their counts
-            const uint32_t sw = transpose32(hw, lane);
-            pcnt[t] = (unsigned)__popc(sw) | ((unsigned)__popc(sw & cm32) << 10) |
-                      ((unsigned)__popc(sw & om32) << 20);
         }
     }
     __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
@@ -671,12 +683,13 @@ bool mfma_shape_supported(int A, int N, int two_planes)
 {
     const bool ok_a = A == 64 || A == 128 || A == 256 || A == 512;
     // 32-neuron blocks over 8 wavefronts (4 or 8 blocks per slice, 512
-    // neurons as two slices); the B tiles take A * planes / 8 VGPRs per lane,
-    // at most 64.
-    return ok_a && (N == 128 || N == 256 || N == 512) && A * (two_planes ? 2 : 1) <= 512;
+    // neurons as two slices, 64 as a slice of 128 with two dead blocks); the
+    // B tiles take A * planes / 8 VGPRs per lane, at most 64.
+    return ok_a && (N == 64 || N == 128 || N == 256 || N == 512) && A * (two_planes ? 2 : 1) <= 512;
 }
 
 int mfma_slices(int N) { return N > 256 ? N / 256 : 1; }
+int mfma_width(int N) { return N <= 128 ? 128 : 256; }
 
 template <int A_, int N_, bool TWO>
 static void launch_mfma_k(const DevNet &n, const TickArgs &a, int spw, hipStream_t st)
@@ -708,7 +721,7 @@ static hipError_t launch_mfma_an(const DevNet &n, const TickArgs &a, int two, in
 template <int A_>
 static hipError_t launch_mfma_a(const DevNet &n, const TickArgs &a, int two, int spw, hipStream_t st)
 {
-    switch (n.N / n.slices) {
+    switch (mfma_width(n.N)) {
     case 128: return launch_mfma_an<A_, 128>(n, a, two, spw, st);
     case 256: return launch_mfma_an<A_, 256>(n, a, two, spw, st);
     default: return hipErrorInvalidValue;

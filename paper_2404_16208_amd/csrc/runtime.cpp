@@ -673,7 +673,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         if (p.path == RANC_PATH_SPARSE)
             return fail(RANC_EUNSUPPORTED, "nets[%d]: the sparse path runs one network per call", i);
         if (p.path == RANC_PATH_MFMA) {
-            e.code = mfma_shape_code(p.A, p.N / p.slices, p.two);
+            e.code = mfma_shape_code(p.A, mfma_width(p.N), p.two);
             e.units = p.C * p.slices * ((p.S + p.spw - 1) / p.spw);
             b.mf.push_back(e);
         } else {

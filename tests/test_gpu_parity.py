@@ -111,6 +111,17 @@ def test_mfma_neuron_slices_many_tiles(monkeypatch):
     assert_parity(net, x, 9, "mfma", samples=[0, 1, 63, 64, 127, 128, 150, 198, 199], what="slices")
 
 
+def test_mfma_64_neuron_cores_many_tiles(monkeypatch):
+    # 64-neuron cores as a 128-neuron workgroup with two dead blocks, several
+    # tiles per workgroup, ragged last tile, 8-bit potentials (clamped)
+    monkeypatch.setenv("RANC_MFMA_SPW", "128")
+    net = W.random_net(85, 6, 512, 64, 4, weight_bits=8, potential_bits=8, max_delay=3, grid_w=3,
+                       density=0.25, p_core=0.8, p_out=0.15, thr_range=(20, 120),
+                       input_cores=[0, 2, 5], config_id=710)
+    x = W.bernoulli_inputs(18, net, 200, 9, 0.3, config_id=710)
+    assert_parity(net, x, 9, "mfma", samples=[0, 1, 63, 64, 127, 128, 170, 199], what="n64")
+
+
 # ----------------------------------------------------------- resume / state
 
 @pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
