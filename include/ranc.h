@@ -54,9 +54,11 @@ enum {
     RANC_PATH_AUTO = 0,   /* pick per shape */
     RANC_PATH_PLAIN = 1,  /* per (core, sample) workgroups, crossbar words and popcounts */
     RANC_PATH_MFMA = 2,   /* per-core workgroups over sample tiles, exact int8 MFMA;
-                             num_axons * (weight_bits > 8 ? 2 : 1) <= 512 (512 neurons
-                             run as two 256-neuron workgroups, 64 as a 128-neuron
-                             workgroup with half its wavefronts idle) */
+                             every supported core shape (512 neurons run as 256-neuron
+                             workgroups, 64 as a 128-neuron workgroup with half its
+                             wavefronts idle, 512 axons with 9-bit weights as
+                             128-neuron workgroups with one weight plane per
+                             wavefront) */
     RANC_PATH_SPARSE = 3  /* per-core workgroups over sample tiles, event-driven: only spiking
                              axons are visited (never chosen by RANC_PATH_AUTO) */
 };

@@ -93,6 +93,9 @@ template <int A_, int N_> struct MfmaLds {
     static constexpr int HB = A_ == 512 ? 4 : 8;
     static constexpr int HBS = STW == 1 ? 2 * HB : HB;
     typedef uint64_t HBuf[N_][HBS];
+    // plane split (A = 512 with two weight planes): the partial sums one
+    // wavefront hands to its partner, [wave][accumulator element][lane]
+    typedef int32_t Xch[8][16][64];
 };
 
 // One unit of work: workgroup `bid` of the tick's grid (core bid % C, then
@@ -101,7 +104,13 @@ template <int A_, int N_> struct MfmaLds {
 // degree counts and counter row, sharing the axon inputs of the core; a core
 // of 64 neurons runs as a slice of 128 whose upper two 32-neuron blocks are
 // dead (their wavefronts keep their gather and expansion roles and the
-// barriers, and skip all neuron work and memory traffic). The LDS arrays come from the calling
+// barriers, and skip all neuron work and memory traffic).
+// Plane split (A = 512 with two weight planes, 128-neuron slices): the B
+// tiles of both planes would take 128 VGPRs per lane, so the two wavefronts
+// of a 32-neuron block hold one plane each (wave stg: plane stg, hi first),
+// each multiplies both 32-sample groups of the tile with its plane, and they
+// swap the partial sums of one group through LDS (`xch`): wave stg finishes
+// group stg with in = lo + 128 * hi. The LDS arrays come from the calling
 // kernel, so several shapes can share one kernel's LDS.
 // CLAMP: potentials narrower than 32 bits are clamped to [vmin, vmax] after
 // the saturating 32-bit add (with 32-bit potentials the add alone is exact).
@@ -113,12 +122,16 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
                                                     typename MfmaLds<A_, N_>::VTile *v_lds,
                                                     typename MfmaLds<A_, N_>::XTile *x_lds,
                                                     typename MfmaLds<A_, N_>::HBuf *hbuf,
+                                                    typename MfmaLds<A_, N_>::Xch *xch,
                                                     unsigned (*s_cnt)[MFMA_SPW_MAX])
 {
     typedef MfmaLds<A_, N_> L;
     constexpr int NB = N_ / 32;          // 32-neuron blocks (4 or 8)
     constexpr int KS = A_ / 32;          // 32-axon k-steps
-    constexpr int PL = TWO ? 2 : 1;      // B planes
+    constexpr bool PSPLIT = TWO && A_ == 512;   // one plane per wavefront
+    static_assert(!PSPLIT || N_ == 128, "the plane split pairs the two wavefronts of a block");
+    constexpr int PLY = TWO ? 2 : 1;     // B planes in the layout
+    constexpr int PL = PSPLIT ? 1 : PLY; // B planes held by a wavefront
     constexpr int STW = NB / 4;          // 32-sample sub-tiles per wave per tile
     constexpr int W_ = A_ / 32;          // axon words
     constexpr int ROWB = A_ + 16;        // padded LDS row of the int8 tile (bytes)
@@ -158,7 +171,7 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     for (int k = 0; k < KS; ++k)
 #pragma unroll
         for (int p = 0; p < PL; ++p)
-            breg[k][p] = planes[((((size_t)c * n.NW + nbc) * KS + k) * PL + p) * 64 + lane];
+            breg[k][p] = planes[((((size_t)c * n.NW + nbc) * KS + k) * PLY + (PSPLIT ? stg : p)) * 64 + lane];
     const size_t cj = (size_t)c * n.N + slice * N_ + neuron;
     const int32_t lk = n.leak[cj], th = n.thr[cj], rs = n.rst[cj];
     const int32_t vmin = n.vmin, vmax = n.vmax;
@@ -444,7 +457,72 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
 
         // 3. products and potential update (dead blocks skip it: their
         //    results are never stored)
-        if (live) {
+        if constexpr (PSPLIT) {
+            // epilogue of sub-tile t (32-sample group st of the tile at s0) from the
+            // input plus leak of each accumulator element: saturating add, clamp,
+            // threshold, reset; the neuron's spike word and the per-sample counts
+            auto finish = [&](int t, int st, int s0, const v16i &in) {
+                const int sg = (s0 >> 5) + st;   // 32-sample group
+                // spike bits r of this lane, built from r = 15 down by doubling
+                uint32_t hb = 0;
+#pragma unroll
+                for (int r = 15; r >= 0; --r) {
+                    int32_t u = __builtin_elementwise_add_sat(vold[t][r >> 2][r & 3], in[r]);
+                    if constexpr (CLAMP)
+                        u = min(max(u, vmin), vmax);
+                    const bool fire = u >= th;
+                    vnew[t][r >> 2][r & 3] = fire ? rs : u;
+                    hb = hb + hb + (uint32_t)fire;
+                }
+                // samples past the end never fire (their potentials are never read)
+                if (sg * 32 + 32 > s_end) {   // wave-uniform
+                    uint32_t vm = 0;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        vm |= (uint32_t)(sg * 32 + 8 * (r >> 2) + 4 * h + (r & 3) < s_end) << r;
+                    hb &= vm;
+                }
+                // the neuron's spike word: bits r from lane jj, bits 16 + r from lane jj + 32
+                const uint32_t hw = hb | ((uint32_t)__shfl_xor((int)hb, 32, 64) << 16);
+                hword[t] = hw;
+                // per-sample spike words of the wave's 32 neurons, and their counts
+                const uint32_t sw = transpose32(hw, lane);
+                pcnt[t] = (unsigned)__popc(sw) | ((unsigned)__popc(sw & cm32) << 10) |
+                          ((unsigned)__popc(sw & om32) << 20);
+            };
+
+            v16i accg[2];
+            if (live) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    accg[0][r] = stg == 1 ? lk : 0;   // the lo plane carries the leak
+                    accg[1][r] = stg == 1 ? lk : 0;
+                }
+                const int8_t *arow = &A[jj * ROWB + 16 * h];
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const v4i a0 = *reinterpret_cast<const v4i *>(arow + 32 * k);
+                    const v4i a1 = *reinterpret_cast<const v4i *>(arow + 32 * ROWB + 32 * k);
+                    accg[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, breg[k][0], accg[0], 0, 0, 0);
+                    accg[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, breg[k][0], accg[1], 0, 0, 0);
+                }
+                // hand over the group the partner finishes
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    (*xch)[wave][r][lane] = stg == 0 ? accg[1][r] : accg[0][r];
+            }
+            lds_barrier();
+            if (live) {
+                v16i in;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t own = stg == 0 ? accg[0][r] : accg[1][r];
+                    const int32_t other = (*xch)[wave ^ 4][r][lane];
+                    in[r] = stg == 0 ? other + own * 128 : own + other * 128;
+                }
+                finish(0, stg, s0, in);
+            }
+        } else if (live) {
 #pragma unroll
             for (int t = 0; t < STW; ++t) {
                 const int st = stg * STW + t;
@@ -520,8 +598,10 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
     __shared__ __attribute__((aligned(16))) typename L::VTile v_lds[8];
     __shared__ typename L::XTile x_lds[2];
     __shared__ typename L::HBuf hbuf[1];
+    __shared__ int32_t xch_raw[TWO && A_ == 512 ? sizeof(typename L::Xch) / 4 : 1];
     __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
-    integrate_mfma_unit<A_, N_, TWO, CLAMP, true>(n, ta, spw, blockIdx.x, a_lds, v_lds, x_lds, hbuf, s_cnt);
+    integrate_mfma_unit<A_, N_, TWO, CLAMP, true>(n, ta, spw, blockIdx.x, a_lds, v_lds, x_lds, hbuf,
+                                                  reinterpret_cast<typename L::Xch *>(xch_raw), s_cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,9 +624,17 @@ __device__ __forceinline__ void batch_unit(const BatchEntry &e, const TickArgs &
                                            v4i *v_raw, uint32_t *x_raw, unsigned (*s_cnt)[MFMA_SPW_MAX])
 {
     typedef MfmaLds<A_, N_> L;
+    // the plane-split exchange sits in the potential staging area past this
+    // shape's eight VTiles (it holds eight VTiles of the widest shape)
+    static_assert(!(TWO && A_ == 512) ||
+                  8 * sizeof(typename L::VTile) + sizeof(typename L::Xch) <= 8 * sizeof(MfmaLds<512, 256>::VTile),
+                  "exchange does not fit the staging area");
     integrate_mfma_unit<A_, N_, TWO, true, false>(e.n, ta, e.spw, bid, reinterpret_cast<typename L::ATile *>(a_raw),
                                                   reinterpret_cast<typename L::VTile *>(v_raw),
-                                                  reinterpret_cast<typename L::XTile *>(x_raw), nullptr, s_cnt);
+                                                  reinterpret_cast<typename L::XTile *>(x_raw), nullptr,
+                                                  reinterpret_cast<typename L::Xch *>(
+                                                      reinterpret_cast<int8_t *>(v_raw) + 8 * sizeof(typename L::VTile)),
+                                                  s_cnt);
 }
 
 __global__ __launch_bounds__(512) void k_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k,
@@ -597,6 +685,7 @@ __global__ __launch_bounds__(512) void k_integrate_mfma_batch(const BatchEntry *
         case 10: batch_unit<256, 256, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
         case 11: batch_unit<256, 256, true>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
         case 12: batch_unit<512, 128, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
+        case 13: batch_unit<512, 128, true>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
         case 14: batch_unit<512, 256, false>(e, ta, bid, a_raw, v_raw, x_raw, s_cnt); break;
         default: break;
         }
@@ -626,6 +715,7 @@ __global__ __launch_bounds__(512) void k_integrate_mfma_group(const BatchEntry *
     __shared__ __attribute__((aligned(16))) typename L::VTile v_lds[8];
     __shared__ typename L::XTile x_lds[2];
     __shared__ typename L::HBuf hbuf[1];
+    __shared__ int32_t xch_raw[TWO && A_ == 512 ? sizeof(typename L::Xch) / 4 : 1];
     __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
     const int u = blockIdx.x;
     int lo = 0, hi = num - 1;
@@ -642,7 +732,7 @@ __global__ __launch_bounds__(512) void k_integrate_mfma_group(const BatchEntry *
     ta.ext_t = e.ext_base ? e.ext_base + (size_t)k * e.tick_words : nullptr;
     ta.ext_sstride = e.ext_sstride;
     integrate_mfma_unit<A_, N_, TWO, CLAMP, true>(e.n, ta, e.spw, u - e.unit_begin, a_lds, v_lds, x_lds, hbuf,
-                                                  s_cnt);
+                                                  reinterpret_cast<typename L::Xch *>(xch_raw), s_cnt);
 }
 
 template <int A_, int N_, bool TWO>
@@ -673,6 +763,7 @@ hipError_t launch_integrate_mfma_group(const BatchEntry *tab, int num, int total
     case 10: launch_group_k<256, 256, false>(tab, num, total, k, clamp, st); break;
     case 11: launch_group_k<256, 256, true>(tab, num, total, k, clamp, st); break;
     case 12: launch_group_k<512, 128, false>(tab, num, total, k, clamp, st); break;
+    case 13: launch_group_k<512, 128, true>(tab, num, total, k, clamp, st); break;
     case 14: launch_group_k<512, 256, false>(tab, num, total, k, clamp, st); break;
     default: return hipErrorInvalidValue;
     }
@@ -684,12 +775,21 @@ bool mfma_shape_supported(int A, int N, int two_planes)
     const bool ok_a = A == 64 || A == 128 || A == 256 || A == 512;
     // 32-neuron blocks over 8 wavefronts (4 or 8 blocks per slice, 512
     // neurons as two slices, 64 as a slice of 128 with two dead blocks); the
-    // B tiles take A * planes / 8 VGPRs per lane, at most 64.
-    return ok_a && (N == 64 || N == 128 || N == 256 || N == 512) && A * (two_planes ? 2 : 1) <= 512;
+    // B tiles take A * planes / 8 VGPRs per lane, at most 64 (A = 512 with
+    // two planes: one plane per wavefront, in 128-neuron slices).
+    return ok_a && (N == 64 || N == 128 || N == 256 || N == 512) && A * (two_planes ? 2 : 1) <= 1024;
 }
 
-int mfma_slices(int N) { return N > 256 ? N / 256 : 1; }
-int mfma_width(int N) { return N <= 128 ? 128 : 256; }
+int mfma_width(int A, int N, int two_planes)
+{
+    // 128 neurons per workgroup for small cores and for the plane split
+    return N <= 128 || A * (two_planes ? 2 : 1) > 512 ? 128 : 256;
+}
+int mfma_slices(int A, int N, int two_planes)
+{
+    const int w = mfma_width(A, N, two_planes);
+    return N > w ? N / w : 1;
+}
 
 template <int A_, int N_, bool TWO>
 static void launch_mfma_k(const DevNet &n, const TickArgs &a, int spw, hipStream_t st)
@@ -711,9 +811,12 @@ static hipError_t launch_mfma_an(const DevNet &n, const TickArgs &a, int two, in
         else
             launch_mfma_k<A_, N_, false>(n, a, spw, st);
     } else {
-        if (two)
+        if (!two)
+            launch_mfma_k<A_, N_, false>(n, a, spw, st);
+        else if constexpr (N_ == 128)
+            launch_mfma_k<A_, 128, true>(n, a, spw, st);   // plane split
+        else
             return hipErrorInvalidValue;
-        launch_mfma_k<A_, N_, false>(n, a, spw, st);
     }
     return hipGetLastError();
 }
@@ -721,7 +824,7 @@ static hipError_t launch_mfma_an(const DevNet &n, const TickArgs &a, int two, in
 template <int A_>
 static hipError_t launch_mfma_a(const DevNet &n, const TickArgs &a, int two, int spw, hipStream_t st)
 {
-    switch (mfma_width(n.N)) {
+    switch (mfma_width(n.A, n.N, two)) {
     case 128: return launch_mfma_an<A_, 128>(n, a, two, spw, st);
     case 256: return launch_mfma_an<A_, 256>(n, a, two, spw, st);
     default: return hipErrorInvalidValue;
@@ -731,7 +834,8 @@ static hipError_t launch_mfma_a(const DevNet &n, const TickArgs &a, int two, int
 hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes, int samples_per_wg,
                                  hipStream_t st)
 {
-    if (!mfma_shape_supported(n.A, n.N, two_planes) || n.slices != mfma_slices(n.N) || n.cnt_rows != n.slices ||
+    if (!mfma_shape_supported(n.A, n.N, two_planes) || n.slices != mfma_slices(n.A, n.N, two_planes) ||
+        n.cnt_rows != n.slices ||
         samples_per_wg <= 0 || samples_per_wg % MFMA_TS ||
         samples_per_wg > MFMA_SPW_MAX || n.vlayout != VLAYOUT_BRICK || n.S64 % MFMA_TS || n.S > n.S64)
         return hipErrorInvalidValue;

@@ -132,8 +132,8 @@ hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t
 hipError_t launch_reset_state(const DevNet &n, hipStream_t st);
 hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st);
 bool mfma_shape_supported(int A, int N, int two_planes);
-int mfma_slices(int N);
-int mfma_width(int N);   // neurons per MFMA workgroup (128 or 256)
+int mfma_width(int A, int N, int two_planes);   // neurons per MFMA workgroup (128 or 256)
+int mfma_slices(int A, int N, int two_planes);  // MFMA workgroups per core and sample chunk
 int mfma_shape_code(int A, int N, int two_planes);
 int plain_shape_code(int W, int G);
 int route_shape_code(const RouteCfg &cfg, int max_delay);

@@ -176,7 +176,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     if (path == RANC_PATH_SPARSE && !sparse_shape_supported(p.A, p.N, p.G))
         return fail(RANC_EUNSUPPORTED, "sparse path does not support N=%d with G=%d", p.N, p.G);
     p.path = path;
-    p.slices = path == RANC_PATH_MFMA ? mfma_slices(p.N) : 1;
+    p.slices = path == RANC_PATH_MFMA ? mfma_slices(p.A, p.N, p.two) : 1;
     p.cnt_rows = path == RANC_PATH_PLAIN ? p.N / 64 : p.slices;
     // Samples per workgroup (sample-tiled paths): aim for >= 1024 workgroups, in 64-sample tiles.
     {
@@ -673,7 +673,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         if (p.path == RANC_PATH_SPARSE)
             return fail(RANC_EUNSUPPORTED, "nets[%d]: the sparse path runs one network per call", i);
         if (p.path == RANC_PATH_MFMA) {
-            e.code = mfma_shape_code(p.A, mfma_width(p.N), p.two);
+            e.code = mfma_shape_code(p.A, mfma_width(p.A, p.N, p.two), p.two);
             e.units = p.C * p.slices * ((p.S + p.spw - 1) / p.spw);
             b.mf.push_back(e);
         } else {

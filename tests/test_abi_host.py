@@ -188,17 +188,15 @@ def test_argument_rejections(R):
     R._lib.ranc_free(None)
 
 
-def test_mfma_path_unsupported_shape_reported(R):
-    net = W.random_net(8, 4, 512, 512, 2, grid_w=2, config_id=601)
-    st, msg, _ = ws_status(R, net, path=R.RANC_PATH_MFMA)
-    assert R.STATUS_NAMES[st] == "RANC_EUNSUPPORTED" and "MFMA" in msg
-    st, msg, _ = ws_status(R, net, path=R.RANC_PATH_AUTO)
-    assert st == R.RANC_OK, msg
-    # 512 neurons with one weight plane, or 256 axons with two, fit (two slices)
-    for A, b in ((512, 8), (256, 9)):
-        net = W.random_net(8, 4, A, 512, 2, weight_bits=b, grid_w=2, config_id=601)
+def test_mfma_path_accepts_every_core_shape(R):
+    # 512 neurons run as slices, 64 as a padded slice, 512 axons with 9-bit
+    # weights as a plane split: every valid core shape loads on the MFMA path
+    for A, N, b in ((512, 512, 9), (512, 64, 9), (512, 128, 9), (64, 64, 4), (256, 512, 9), (512, 512, 8)):
+        net = W.random_net(8, 4, A, N, 2, weight_bits=b, grid_w=2, config_id=601)
         st, msg, _ = ws_status(R, net, path=R.RANC_PATH_MFMA)
-        assert st == R.RANC_OK, (A, b, msg)
+        assert st == R.RANC_OK, (A, N, b, msg)
+        st, msg, _ = ws_status(R, net, path=R.RANC_PATH_AUTO)
+        assert st == R.RANC_OK, (A, N, b, msg)
 
 
 def test_tiny_validation_net_from_pins_rejected_shape(R):

@@ -50,6 +50,10 @@ SHAPES = [
     (3, 256, 512, 4, 9, 32, 4, 3, 130, 8),
     (2, 512, 512, 2, 8, 16, 3, 2, 100, 6),
     (4, 128, 512, 4, 6, 32, 2, 2, 70, 8),
+    # 512 axons with 9-bit weights: one weight plane per wavefront (plane split)
+    (2, 512, 512, 2, 9, 32, 3, 2, 100, 6),
+    (3, 512, 128, 4, 9, 16, 4, 3, 70, 8),
+    (4, 512, 64, 2, 9, 32, 2, 2, 66, 6),
 ]
 
 
