@@ -637,7 +637,7 @@ __device__ __forceinline__ void batch_unit(const BatchEntry &e, const TickArgs &
                                                   s_cnt);
 }
 
-__global__ __launch_bounds__(512) void k_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k,
+__global__ __launch_bounds__(512) void k_integrate_mfma_batch(const BatchEntry *__restrict__ tab, int num, int total, int k,
                                                               unsigned *queue)
 {
     typedef MfmaLds<512, 256> Lmax;
@@ -656,16 +656,7 @@ __global__ __launch_bounds__(512) void k_integrate_mfma_batch(const BatchEntry *
         __syncthreads();
         if (u >= total)
             break;
-        // network of unit u: the last entry whose first unit is <= u
-        int lo = 0, hi = num - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tab[mid].unit_begin <= u)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const BatchEntry &e = tab[lo];
+        const BatchEntry &e = tab[batch_entry_of(tab, num, u, false)];   // network of unit u
         TickArgs ta;
         ta.k = k;
         ta.ext_t = e.ext_base ? e.ext_base + (size_t)k * e.tick_words : nullptr;
@@ -704,11 +695,11 @@ hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total
 
 // ---------------------------------------------------------------------------
 // Several networks of one shape class (A, slice width, planes, clamp) in one
-// launch: workgroup u runs unit u - e.unit_begin of the table entry e whose
-// unit range holds u (entries numbered from 0 within the class). The LDS is
-// exactly the shape's, as in the single-network kernel.
+// launch: workgroup u runs unit u - e.unit_begin of the entry e whose unit
+// range holds u. The entries come as kernel arguments and the LDS is exactly
+// the shape's, as in the single-network kernel.
 template <int A_, int N_, bool TWO, bool CLAMP>
-__global__ __launch_bounds__(512) void k_integrate_mfma_group(const BatchEntry *tab, int num, int k)
+__global__ __launch_bounds__(512) void k_integrate_mfma_group(MfmaGroupArgs g, int k)
 {
     typedef MfmaLds<A_, N_> L;
     __shared__ __attribute__((aligned(16))) typename L::ATile a_lds[2];
@@ -718,15 +709,11 @@ __global__ __launch_bounds__(512) void k_integrate_mfma_group(const BatchEntry *
     __shared__ int32_t xch_raw[TWO && A_ == 512 ? sizeof(typename L::Xch) / 4 : 1];
     __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
     const int u = blockIdx.x;
-    int lo = 0, hi = num - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].unit_begin <= u)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const BatchEntry &e = tab[lo];
+    int idx = 0;   // the last entry whose first unit is <= u (independent scalar loads)
+    for (int i = 1; i < MFMA_GROUP_MAX; ++i)
+        if (i < g.num && g.e[i].unit_begin <= u)
+            idx = i;
+    const MfmaGroupEntry &e = g.e[idx];
     TickArgs ta;
     ta.k = k;
     ta.ext_t = e.ext_base ? e.ext_base + (size_t)k * e.tick_words : nullptr;
@@ -736,35 +723,36 @@ __global__ __launch_bounds__(512) void k_integrate_mfma_group(const BatchEntry *
 }
 
 template <int A_, int N_, bool TWO>
-static void launch_group_k(const BatchEntry *tab, int num, int total, int k, int clamp, hipStream_t st)
+static void launch_group_k(const MfmaGroupArgs &g, int total, int k, int clamp, hipStream_t st)
 {
     if (clamp)
-        hipLaunchKernelGGL((k_integrate_mfma_group<A_, N_, TWO, true>), dim3(total), dim3(512), 0, st, tab, num, k);
+        hipLaunchKernelGGL((k_integrate_mfma_group<A_, N_, TWO, true>), dim3(total), dim3(512), 0, st, g, k);
     else
-        hipLaunchKernelGGL((k_integrate_mfma_group<A_, N_, TWO, false>), dim3(total), dim3(512), 0, st, tab, num, k);
+        hipLaunchKernelGGL((k_integrate_mfma_group<A_, N_, TWO, false>), dim3(total), dim3(512), 0, st, g, k);
 }
 
-hipError_t launch_integrate_mfma_group(const BatchEntry *tab, int num, int total, int k, int code, int clamp,
+hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int clamp,
                                        hipStream_t st)
 {
-    if (num < 1 || total < 1)
+    static_assert(sizeof(MfmaGroupArgs) + sizeof(int) <= 4096, "kernel arguments exceed 4 KiB");
+    if (g.num < 1 || g.num > MFMA_GROUP_MAX || total < 1)
         return hipErrorInvalidValue;
     switch (code) {
-    case 0: launch_group_k<64, 128, false>(tab, num, total, k, clamp, st); break;
-    case 1: launch_group_k<64, 128, true>(tab, num, total, k, clamp, st); break;
-    case 2: launch_group_k<64, 256, false>(tab, num, total, k, clamp, st); break;
-    case 3: launch_group_k<64, 256, true>(tab, num, total, k, clamp, st); break;
-    case 4: launch_group_k<128, 128, false>(tab, num, total, k, clamp, st); break;
-    case 5: launch_group_k<128, 128, true>(tab, num, total, k, clamp, st); break;
-    case 6: launch_group_k<128, 256, false>(tab, num, total, k, clamp, st); break;
-    case 7: launch_group_k<128, 256, true>(tab, num, total, k, clamp, st); break;
-    case 8: launch_group_k<256, 128, false>(tab, num, total, k, clamp, st); break;
-    case 9: launch_group_k<256, 128, true>(tab, num, total, k, clamp, st); break;
-    case 10: launch_group_k<256, 256, false>(tab, num, total, k, clamp, st); break;
-    case 11: launch_group_k<256, 256, true>(tab, num, total, k, clamp, st); break;
-    case 12: launch_group_k<512, 128, false>(tab, num, total, k, clamp, st); break;
-    case 13: launch_group_k<512, 128, true>(tab, num, total, k, clamp, st); break;
-    case 14: launch_group_k<512, 256, false>(tab, num, total, k, clamp, st); break;
+    case 0: launch_group_k<64, 128, false>(g, total, k, clamp, st); break;
+    case 1: launch_group_k<64, 128, true>(g, total, k, clamp, st); break;
+    case 2: launch_group_k<64, 256, false>(g, total, k, clamp, st); break;
+    case 3: launch_group_k<64, 256, true>(g, total, k, clamp, st); break;
+    case 4: launch_group_k<128, 128, false>(g, total, k, clamp, st); break;
+    case 5: launch_group_k<128, 128, true>(g, total, k, clamp, st); break;
+    case 6: launch_group_k<128, 256, false>(g, total, k, clamp, st); break;
+    case 7: launch_group_k<128, 256, true>(g, total, k, clamp, st); break;
+    case 8: launch_group_k<256, 128, false>(g, total, k, clamp, st); break;
+    case 9: launch_group_k<256, 128, true>(g, total, k, clamp, st); break;
+    case 10: launch_group_k<256, 256, false>(g, total, k, clamp, st); break;
+    case 11: launch_group_k<256, 256, true>(g, total, k, clamp, st); break;
+    case 12: launch_group_k<512, 128, false>(g, total, k, clamp, st); break;
+    case 13: launch_group_k<512, 128, true>(g, total, k, clamp, st); break;
+    case 14: launch_group_k<512, 256, false>(g, total, k, clamp, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

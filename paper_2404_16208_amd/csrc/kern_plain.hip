@@ -194,18 +194,10 @@ int plain_shape_code(int W, int G)
 // Several networks on the plain path, one tick, one launch: unit u is
 // (64-neuron block, core, sample) of the network whose unit range holds u,
 // on one wavefront.
-__global__ __launch_bounds__(64) void k_integrate_plain_batch(const BatchEntry *tab, int num, int k)
+__global__ __launch_bounds__(64) void k_integrate_plain_batch(const BatchEntry *__restrict__ tab, int num, int k)
 {
     const int u = blockIdx.x;
-    int lo = 0, hi = num - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].unit_begin <= u)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const BatchEntry &e = tab[lo];
+    const BatchEntry &e = tab[batch_entry_of(tab, num, u, false)];
     const int local = u - e.unit_begin;
     const int nbs = e.n.N >> 6;
     const int nb = local % nbs, c = (local / nbs) % e.n.C, s = local / nbs / e.n.C;

@@ -121,19 +121,11 @@ int route_shape_code(const RouteCfg &cfg, int max_delay)
 
 // Several plain-path networks routed in one launch: unit u is block
 // (x, y) of the network whose router unit range holds u.
-__global__ __launch_bounds__(ROUTE_THREADS) void k_route_batch(const BatchEntry *tab, int num, int k)
+__global__ __launch_bounds__(ROUTE_THREADS) void k_route_batch(const BatchEntry *__restrict__ tab, int num, int k)
 {
     extern __shared__ uint32_t sp[];
     const int u = blockIdx.x;
-    int lo = 0, hi = num - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].route_begin <= u)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const BatchEntry &e = tab[lo];
+    const BatchEntry &e = tab[batch_entry_of(tab, num, u, true)];
     const int local = u - e.route_begin;
     const int bx = local % e.route_split, by = local / e.route_split;
     switch (e.route_code) {

@@ -112,7 +112,43 @@ struct BatchEntry {
     int code;
     int unit_begin, units;      // integration units
     int route_begin, route_units, route_code, route_split;   // plain path: router units and shape
+    int phase;                  // cache-sized phase of the batch (host bookkeeping)
 };
+
+// Networks of one MFMA shape class in one launch, passed by value as kernel
+// arguments (at most 4 KiB): pointers read from kernel arguments are known
+// to address global memory, so the kernel's accesses through them are
+// global (not flat) loads and stores, as in the single-network kernel.
+constexpr int MFMA_GROUP_MAX = 11;
+struct MfmaGroupEntry {
+    DevNet n;
+    const uint32_t *ext_base;   // inputs of the call ([S][T][Cin][W]), or nullptr
+    long long tick_words;       // Cin * W
+    long long ext_sstride;      // num_ticks * tick_words
+    int spw;                    // samples per workgroup
+    int unit_begin;             // first unit of the network in the launch
+};
+struct MfmaGroupArgs {
+    int num;
+    MfmaGroupEntry e[MFMA_GROUP_MAX];
+};
+
+// Index of the last entry of tab[0, num) whose first unit (unit_begin, or
+// route_begin with `route`) is <= u; the first units increase along the
+// table and entry 0 starts at 0. Each lane of the wavefront compares one
+// entry, so the lookup is one round of parallel loads instead of a chain of
+// dependent ones. The result is wave-uniform.
+__device__ inline int batch_entry_of(const BatchEntry *tab, int num, int u, bool route)
+{
+    const int lane = threadIdx.x & 63;
+    int count = 0;
+    for (int base = 0; base < num; base += 64) {
+        const int i = base + lane;
+        const int first = i < num ? (route ? tab[i].route_begin : tab[i].unit_begin) : INT32_MAX;
+        count += __popcll(__ballot(first <= u));
+    }
+    return __builtin_amdgcn_readfirstlane(count - 1);
+}
 
 // Route launch shape (chosen per network by the runtime).
 struct RouteCfg {
@@ -142,7 +178,7 @@ hipError_t launch_route_batch(const BatchEntry *tab, int num, int total, int k, 
 hipError_t launch_advance_batch(const BatchEntry *tab, int num, int num_ticks, unsigned *queue, hipStream_t st);
 hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k, unsigned *queue,
                                        int workgroups, hipStream_t st);
-hipError_t launch_integrate_mfma_group(const BatchEntry *tab, int num, int total, int k, int code, int clamp,
+hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int clamp,
                                        hipStream_t st);
 RouteCfg route_default_cfg(const DevNet &n);
 int route_dmax(int max_delay);

@@ -455,8 +455,14 @@ struct Batch {
     int num_ticks = 0;
     std::vector<BatchEntry> mf, pl;
     // MFMA shape classes (one launch each per tick), unless persistent
-    struct Group { int first, num, units, code, clamp; };
+    struct Group { int first, num, units, code, clamp; MfmaGroupArgs args; };
     std::vector<Group> groups;
+    // Phases: networks whose combined per-tick state fits the GPU's last-level
+    // cache; all ticks of a phase run before the next phase starts. Groups
+    // [g_first, g_first + g_num) and plain entries [pl_first, pl_first +
+    // pl_num), numbered from 0 within the phase. One phase when persistent.
+    struct Phase { int g_first, g_num, pl_first, pl_num, pl_units, rt_units; };
+    std::vector<Phase> phases;
     bool persistent = false;
     int mf_units = 0, pl_units = 0, rt_units = 0, mf_workgroups = 0;
     size_t rt_lds = 0;
@@ -651,6 +657,37 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
 {
     b.persistent = persistent;
     b.groups.clear();
+    b.phases.clear();
+    // Phase of each network: first fit, largest state first, into phases of
+    // at most `budget` bytes of state (a larger network forms its own phase).
+    // Networks are independent, so running them phase after phase is exact.
+    // Off unless RANC_BATCH_PHASE_MB is set: on the 64-variant sweep, phases
+    // of 64 or 160 MB were 0.5-1% slower than one phase.
+    size_t budget = 0;
+    if (const char *env = getenv("RANC_BATCH_PHASE_MB"))
+        budget = (size_t)std::max(0, atoi(env)) << 20;
+    std::vector<int> phase_of(num, 0);
+    if (!persistent && budget > 0) {
+        std::vector<std::pair<size_t, int>> foot;
+        for (int i = 0; i < num; ++i) {
+            const Plan &p = nets[i]->p;
+            foot.push_back({p.params_bytes + p.size[R_V] + p.size[R_HIST] + p.size[R_RING] + p.size[R_SPK] +
+                                p.size[R_CNT],
+                            i});
+        }
+        std::stable_sort(foot.begin(), foot.end(), [](const std::pair<size_t, int> &x,
+                                                       const std::pair<size_t, int> &y) { return x.first > y.first; });
+        std::vector<size_t> fill;
+        for (const auto &f : foot) {
+            size_t ph = 0;
+            while (ph < fill.size() && fill[ph] + f.first > budget)
+                ++ph;
+            if (ph == fill.size())
+                fill.push_back(0);
+            fill[ph] += f.first;
+            phase_of[f.second] = (int)ph;
+        }
+    }
     b.nets.assign(nets, nets + num);
     b.uids.clear();
     for (int i = 0; i < num; ++i)
@@ -670,6 +707,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         e.tick_words = (long long)p.Cin * p.W;
         e.ext_sstride = (long long)num_ticks * e.tick_words;
         e.spw = p.spw;
+        e.phase = phase_of[i];
         if (p.path == RANC_PATH_SPARSE)
             return fail(RANC_EUNSUPPORTED, "nets[%d]: the sparse path runs one network per call", i);
         if (p.path == RANC_PATH_MFMA) {
@@ -708,8 +746,10 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
             mu += e.units;
         }
     } else {
-        // shape classes, each numbered from 0, largest units first within a class
+        // by phase, then shape class (each numbered from 0), largest units first within a class
         std::stable_sort(b.mf.begin(), b.mf.end(), [&](const BatchEntry &x, const BatchEntry &y) {
+            if (x.phase != y.phase)
+                return x.phase < y.phase;
             if (x.code != y.code)
                 return x.code < y.code;
             if (clamp(x) != clamp(y))
@@ -718,21 +758,58 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         });
         for (size_t i = 0; i < b.mf.size(); ++i) {
             BatchEntry &e = b.mf[i];
-            if (b.groups.empty() || b.groups.back().code != e.code || b.groups.back().clamp != clamp(e))
-                b.groups.push_back({(int)i, 0, 0, e.code, clamp(e)});
+            if (b.groups.empty() || b.mf[b.groups.back().first].phase != e.phase ||
+                b.groups.back().code != e.code || b.groups.back().clamp != clamp(e) ||
+                b.groups.back().num == MFMA_GROUP_MAX) {
+                b.groups.push_back(Batch::Group());
+                Batch::Group &g = b.groups.back();
+                memset(&g.args, 0, sizeof g.args);
+                g.first = (int)i;
+                g.num = g.units = 0;
+                g.code = e.code;
+                g.clamp = clamp(e);
+            }
             Batch::Group &g = b.groups.back();
             if ((long long)g.units + e.units > INT32_MAX)
                 return fail(RANC_EUNSUPPORTED, "batch has too many work units");
             e.unit_begin = g.units;
+            MfmaGroupEntry &ge = g.args.e[g.num];
+            ge.n = e.n;
+            ge.ext_base = e.ext_base;
+            ge.tick_words = e.tick_words;
+            ge.ext_sstride = e.ext_sstride;
+            ge.spw = e.spw;
+            ge.unit_begin = e.unit_begin;
             g.units += e.units;
             g.num += 1;
+            g.args.num = g.num;
             mu += e.units;
         }
     }
+    // plain entries by phase, numbered from 0 within the phase
+    std::stable_sort(b.pl.begin(), b.pl.end(),
+                     [](const BatchEntry &x, const BatchEntry &y) { return x.phase < y.phase; });
+    int nphases = 0;
+    for (int i = 0; i < num; ++i)
+        nphases = std::max(nphases, phase_of[i] + 1);
+    b.phases.assign(nphases, Batch::Phase{0, 0, 0, 0, 0, 0});
+    for (size_t g = b.groups.size(); g-- > 0;) {
+        Batch::Phase &ph = b.phases[b.mf[b.groups[g].first].phase];
+        ph.g_first = (int)g;
+        ph.g_num += 1;
+    }
+    for (size_t i = b.pl.size(); i-- > 0;)
+        b.phases[b.pl[i].phase].pl_first = (int)i;
     for (auto &e : b.pl) {
-        e.unit_begin = (int)pu;
+        Batch::Phase &ph = b.phases[e.phase];
+        if ((long long)ph.pl_units + e.units > INT32_MAX || (long long)ph.rt_units + e.route_units > INT32_MAX)
+            return fail(RANC_EUNSUPPORTED, "batch has too many work units");
+        e.unit_begin = ph.pl_units;
+        ph.pl_units += e.units;
+        e.route_begin = ph.rt_units;
+        ph.rt_units += e.route_units;
+        ph.pl_num += 1;
         pu += e.units;
-        e.route_begin = (int)ru;
         ru += e.route_units;
     }
     if (mu > INT32_MAX || pu > INT32_MAX || ru > INT32_MAX)
@@ -759,31 +836,34 @@ static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t
     const BatchEntry *tmf = batch_table(lead, 0), *tpl = batch_table(lead, 1);
     unsigned *queue = batch_queue(lead);
     timed = timed && lead->prof.on;
+    for (const Batch::Phase &ph : b.phases)
     for (int k = 0; k < b.num_ticks; ++k) {
         int slot = -1;
         hipError_t e = hipSuccess;
-        if (!b.mf.empty()) {
+        const bool mf = b.persistent ? !b.mf.empty() : ph.g_num > 0;
+        if (mf) {
             e = timed ? prof_begin(lead, 0, s, &slot) : hipSuccess;
             if (e == hipSuccess && b.persistent)
                 e = launch_integrate_mfma_batch(tmf, (int)b.mf.size(), b.mf_units, k, queue, b.mf_workgroups, s);
-            for (size_t g = 0; e == hipSuccess && !b.persistent && g < b.groups.size(); ++g)
-                e = launch_integrate_mfma_group(tmf + b.groups[g].first, b.groups[g].num, b.groups[g].units, k,
-                                                b.groups[g].code, b.groups[g].clamp, s);
+            for (int g = ph.g_first; e == hipSuccess && !b.persistent && g < ph.g_first + ph.g_num; ++g)
+                e = launch_integrate_mfma_group(b.groups[g].args, b.groups[g].units, k, b.groups[g].code,
+                                                b.groups[g].clamp, s);
             if (e == hipSuccess && timed)
                 e = prof_end(lead, slot, s);
             if (e != hipSuccess)
                 return hip_fail(e, "launching batch integration (MFMA)");
         }
-        if (!b.pl.empty()) {
+        if (ph.pl_num > 0) {
+            const BatchEntry *tp = tpl + ph.pl_first;
             e = timed ? prof_begin(lead, 0, s, &slot) : hipSuccess;
             if (e == hipSuccess)
-                e = launch_integrate_plain_batch(tpl, (int)b.pl.size(), b.pl_units, k, s);
+                e = launch_integrate_plain_batch(tp, ph.pl_num, ph.pl_units, k, s);
             if (e == hipSuccess && timed)
                 e = prof_end(lead, slot, s);
             if (e == hipSuccess)
                 e = timed ? prof_begin(lead, 1, s, &slot) : hipSuccess;
             if (e == hipSuccess)
-                e = launch_route_batch(tpl, (int)b.pl.size(), b.rt_units, k, b.rt_lds, s);
+                e = launch_route_batch(tp, ph.pl_num, ph.rt_units, k, b.rt_lds, s);
             if (e == hipSuccess && timed)
                 e = prof_end(lead, slot, s);
             if (e != hipSuccess)
@@ -843,6 +923,7 @@ static ranc_status run_batch(ranc_net *const *nets, int num, const uint32_t *con
         b.mf = std::move(nb.mf);
         b.pl = std::move(nb.pl);
         b.groups = std::move(nb.groups);
+        b.phases = std::move(nb.phases);
         b.persistent = nb.persistent;
         b.mf_units = nb.mf_units;
         b.pl_units = nb.pl_units;

@@ -211,12 +211,15 @@ def _small_sweep_variants(limit_neuron_axons=1 << 22):
     return out
 
 
-@pytest.mark.parametrize("graph,persistent", [(False, False), (True, False), (False, True), (True, True)])
-def test_batch_of_uneven_variants(graph, persistent):
+@pytest.mark.parametrize("graph,persistent,phase_mb", [(False, False, None), (True, False, None),
+                                                      (False, True, None), (True, True, None),
+                                                      (False, False, "1"), (True, False, "1")])
+def test_batch_of_uneven_variants(graph, persistent, phase_mb, monkeypatch):
     """Design-space sweep variants of different core counts, core sizes, axon
     types and weight precisions (both paths) advanced together (per tick one
     launch per MFMA shape class, or one persistent launch, and one per plain
-    step), in two calls; plus a 6-core net on each path with its own
+    step; with a 1 MB phase budget every network runs all its ticks in a phase
+    of its own), in two calls; plus a 6-core net on each path with its own
     sample count. Every network equals the oracle on sampled instances and
     equals the same network run alone on every instance."""
     import torch
@@ -231,7 +234,9 @@ def test_batch_of_uneven_variants(graph, persistent):
     S = [64] * len(vs) + [70, 5]
     T, TC = 12, 6
     xs = [W.bernoulli_inputs(17, n, s, T, 0.1, config_id=709) for n, s in zip(nets, S)]
-    log(f"[batch] {len(nets)} networks, graph={graph}, persistent={persistent}")
+    if phase_mb is not None:
+        monkeypatch.setenv("RANC_BATCH_PHASE_MB", phase_mb)
+    log(f"[batch] {len(nets)} networks, graph={graph}, persistent={persistent}, phase_mb={phase_mb}")
     gs = [RancNet(n, s, TC) for n, s in zip(nets, S)]
     paths = [g.path for g in gs]
     assert "mfma" in paths and "plain" in paths
