@@ -131,6 +131,12 @@ def cpu_baseline(net, x, T, n_samples, gpu_net, torch):
     res = O.simulate(net, x, T, samples=range(n_samples), threads=threads)
     dt = time.perf_counter() - t0
     events = sum(r["counters"]["events"] for r in res)
+    # the same oracle on one thread (the paper's serial baseline), two samples
+    n1 = min(2, n_samples)
+    t0 = time.perf_counter()
+    res1 = O.simulate(net, x, T, samples=range(n1), threads=1)
+    dt1 = time.perf_counter() - t0
+    events1 = sum(r["counters"]["events"] for r in res1)
     gpu_net.reset()
     gpu_net.run(torch.from_numpy(x.view("int32")).cuda(), T)
     torch.cuda.synchronize()
@@ -146,6 +152,8 @@ def cpu_baseline(net, x, T, n_samples, gpu_net, torch):
             "sample": f"samples 0..{n_samples - 1} of the 1024-sample batch x {T} ticks "
                       f"(serial C oracle, one sample per thread), {dt:.2f} s wall",
             "core_ticks_per_s": n_samples * net.num_cores * T / dt,
+            "single_thread": {"value": events1 / dt1, "unit": "synaptic events/s", "cores": 1,
+                              "sample": f"samples 0..{n1 - 1} x {T} ticks, {dt1:.2f} s"},
             "gpu_bit_exact_on_sample": exact}
 
 
@@ -359,6 +367,7 @@ def main():
                    "cores": C, "axons": 256, "neurons": 256, "samples": S, "ticks_per_step": T, "path": "mfma",
                    "parallelism": "single GPU"},
         "core_ticks_per_s": core_ticks / secs,
+        "dense_synapse_evals_per_s": core_ticks * net.num_axons * net.num_neurons / secs,
         "synaptic_events_per_step": delta["events"] / args.steps,
         "spikes_emitted_per_step": delta["emitted"] / args.steps,
         "tick_loop": "hip graph replay" if graph else "per-tick launches",
@@ -378,6 +387,28 @@ def main():
     }
     g.close()
     del g
+    torch.cuda.empty_cache()
+
+    # End to end, as a user sees one step from a cold handle: load (parameter
+    # upload), one step with the inputs in host memory (staged over PCIe), and
+    # reading every sample's output spikes back; host clock, first call
+    # included (no graph capture).
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ge = RancNet(net, S, T, path="mfma")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ge.run(x, T)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    n_out = sum(len(ge.spikes(s)) for s in range(S))
+    t3 = time.perf_counter()
+    out["end_to_end"] = {"ms": (t3 - t0) * 1e3, "load_ms": (t1 - t0) * 1e3, "run_ms": (t2 - t1) * 1e3,
+                         "read_ms": (t3 - t2) * 1e3, "output_spikes": n_out,
+                         "includes": f"load + host-input staging + {T} ticks + reading all {S} samples' "
+                                     "output spikes (host clock)"}
+    ge.close()
+    del ge
     torch.cuda.empty_cache()
 
     if not args.skip_plain:
