@@ -126,6 +126,41 @@ def test_mfma_64_neuron_cores_many_tiles(monkeypatch):
     assert_parity(net, x, 9, "mfma", samples=[0, 1, 63, 64, 127, 128, 170, 199], what="n64")
 
 
+def test_batch_splits_large_shape_class():
+    """Fourteen networks of one MFMA shape class (more than one grouped launch
+    holds) and two of another, with their own core and sample counts, in one
+    batch under graph replay: each equals the same network run alone."""
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet, run_batch
+    nets, S = [], []
+    for i in range(14):
+        nets.append(W.random_net(90 + i, 2 + i % 5, 128, 128, 4, weight_bits=8, max_delay=3, grid_w=1,
+                                 input_cores=[0], config_id=711))
+        S.append(64 + 32 * (i % 3))
+    for i in range(2):
+        nets.append(W.random_net(110 + i, 3, 256, 256, 2, weight_bits=9, max_delay=2, grid_w=3,
+                                 input_cores=[1], config_id=712))
+        S.append(70)
+    T = 6
+    xs = [W.bernoulli_inputs(19, n, s, T, 0.2, config_id=713) for n, s in zip(nets, S)]
+    log(f"[batch-split] {len(nets)} networks")
+    gs = [RancNet(n, s, T) for n, s in zip(nets, S)]
+    assert all(g.path == "mfma" for g in gs)
+    bufs = [torch.from_numpy(np.ascontiguousarray(x).view(np.int32)).cuda() for x in xs]
+    run_batch(gs, bufs, T, graph=True)
+    torch.cuda.synchronize()
+    for i, (n, s, x) in enumerate(zip(nets, S, xs)):
+        a = RancNet(n, s, T)
+        a.run(np.ascontiguousarray(x), T)
+        for smp in (0, s // 2, s - 1):
+            assert np.array_equal(gs[i].potentials(smp), a.potentials(smp)), (i, smp)
+            assert np.array_equal(gs[i].spikes(smp), a.spikes(smp)), (i, smp)
+            assert gs[i].counters(smp) == a.counters(smp), (i, smp)
+        a.close()
+    ref = oracle_results(nets[13], xs[13], T, [0])
+    assert_sample_equal(gs[13], ref[0], 0, T, what="batch-split/oracle")
+
+
 # ----------------------------------------------------------- resume / state
 
 @pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
