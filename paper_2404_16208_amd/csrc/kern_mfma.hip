@@ -24,10 +24,13 @@
 // has exactly one writer (the firing neuron's wavefront, at tick t, slot
 // t % Q) and no atomics are used.
 //
-// Mapping: one workgroup of 8 wavefronts per (core, chunk of samples); wave w
-// owns the 32 neurons of block w % (N/32), whose B tiles stay in VGPRs for
-// the whole chunk (A*planes/8 VGPRs per lane). Samples go 64 at a time
-// (two 32-sample sub-tiles) through a software pipeline:
+// Mapping: one workgroup of 8 wavefronts per (core, neuron slice, chunk of
+// samples), a slice being 128 or 256 of the core's neurons; wave w owns the
+// 32 neurons of block w % (slice/32), whose B tiles stay in VGPRs for the
+// whole chunk (A*planes/8 VGPRs per lane; with 512 axons and two planes the
+// two wavefronts of a block hold one plane each, see integrate_mfma_unit).
+// Samples go 64 at a time (two 32-sample sub-tiles) through a software
+// pipeline:
 //   - the potentials of tile i+1 travel from HBM straight into LDS
 //     (global_load_lds) while tile i is processed; history bits of tile i+2
 //     are loaded and those of tile i+1 transposed into LDS meanwhile;
@@ -40,9 +43,11 @@
 //     (16 bits per lane, two lanes combined); a 32 x 32 bit transpose of the
 //     wave's spike words gives each sample's spike word, whose popcounts are
 //     the per-sample spike counters;
-//   - the results of tile i (potentials, spike history and raster words,
-//     counter updates in LDS) are written at the top of iteration i+1, so the
-//     stores have a whole iteration to drain before the next wait.
+//   - the results of tile i (potentials, counter updates in LDS, and the
+//     spike history and raster words, which collect in LDS and go out every
+//     few tiles as runs of consecutive words per neuron) are written at the
+//     top of iteration i+1, so the stores have a whole iteration to drain
+//     before the next wait.
 // Waves exchange data only through LDS, so barriers order LDS alone
 // (lds_barrier); the single wait for vector memory per iteration is explicit.
 //

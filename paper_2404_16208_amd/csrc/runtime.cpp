@@ -3,7 +3,9 @@
 // Validation of the network description, the workspace layout, host-side
 // packing of the description into the device layouts of ranc_internal.h
 // (crossbar columns, per-type masks, MFMA weight planes, the inverted routing
-// table), the tick loop that queues the per-tick kernels, and readback.
+// table), the tick loop that queues the per-tick kernels (per launch or as a
+// captured HIP graph), batches of several networks, the launch-shape
+// autotuner, and readback.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -650,8 +652,11 @@ static int device_cu_count()
     return cus;
 }
 
-// Build the host tables of a batch (entries sorted by decreasing work per
-// unit, so the persistent MFMA launch hands out the largest units first).
+// Build the host tables of a batch: for the persistent MFMA launch one unit
+// numbering sorted by decreasing work per unit (largest units handed out
+// first); otherwise the MFMA entries by phase and shape class, each class
+// split into launches of at most MFMA_GROUP_MAX networks whose descriptions
+// travel as kernel arguments; plain entries by phase.
 static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *const *bases,
                                int num_ticks, bool persistent, Batch &b)
 {
