@@ -598,14 +598,11 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     lds_barrier();
     write_hist(it - 1 - (it - 1) % L::HB, (it - 1) % L::HB + 1);
     for (int i = threadIdx.x; i < s_end - s_begin; i += blockDim.x) {
-        unsigned long long *cp = n.cnt + (((size_t)c * n.cnt_rows + slice) * n.S + s_begin + i) * CNT_N;
         const unsigned sp = s_cnt[0][i], ev = s_cnt[1][i];
-        cp[CNT_EMITTED] += sp & 1023u;
-        cp[CNT_ROUTED] += (sp >> 10) & 1023u;
-        cp[CNT_OUT] += sp >> 20;
-        if (slice == 0)   // the core's delivered spikes, counted once
-            cp[CNT_DELIVERED] += ev >> 18;
-        cp[CNT_EVENTS] += ev & ((1u << 18) - 1u);
+        // the core's delivered spikes are counted once, by slice 0
+        store_counts(n, ta.k, (size_t)c * n.cnt_rows + slice, s_begin + i,
+                     pack_counts(sp & 1023u, (sp >> 10) & 1023u, sp >> 20, slice == 0 ? ev >> 18 : 0u,
+                                 ev & ((1u << 18) - 1u)));
     }
 }
 

@@ -96,13 +96,8 @@ __device__ __forceinline__ void integrate_plain_unit(const DevNet &n, const Tick
             if (ow >= 0)
                 n.raster[((size_t)tick_row(n, ta.k) * n.S + s) * n.Wout + ow] = om;
         }
-        unsigned long long *cp = n.cnt + (((size_t)c * (N >> 6) + wave) * n.S + s) * CNT_N;
-        cp[CNT_EMITTED] += em;
-        cp[CNT_ROUTED] += ro;
-        if (wave == 0)
-            cp[CNT_DELIVERED] += delivered;
-        cp[CNT_OUT] += ou;
-        cp[CNT_EVENTS] += ev;
+        // the core's delivered spikes are counted once, in row 0
+        store_counts(n, ta.k, (size_t)c * (N >> 6) + wave, s, pack_counts(em, ro, ou, wave == 0 ? delivered : 0u, ev));
     }
 }
 
@@ -174,13 +169,7 @@ __device__ __forceinline__ void integrate_plain_wave(const DevNet &n, const Tick
             if (ow >= 0)
                 n.raster[((size_t)tick_row(n, ta.k) * n.S + s) * n.Wout + ow] = om;
         }
-        unsigned long long *cp = n.cnt + (((size_t)c * (N >> 6) + nb) * n.S + s) * CNT_N;
-        cp[CNT_EMITTED] += em;
-        cp[CNT_ROUTED] += ro;
-        if (nb == 0)
-            cp[CNT_DELIVERED] += delivered;
-        cp[CNT_OUT] += ou;
-        cp[CNT_EVENTS] += ev;
+        store_counts(n, ta.k, (size_t)c * (N >> 6) + nb, s, pack_counts(em, ro, ou, nb == 0 ? delivered : 0u, ev));
     }
 }
 

@@ -20,6 +20,8 @@
 // serves SB samples at a time with their spike bitmaps staged in LDS, so every
 // table entry fetched from L2 is used SB times. When the bitmaps do not fit in
 // LDS the gather reads them from memory.
+#include <algorithm>
+
 #include "kern_common.h"
 #include "ranc_internal.h"
 
@@ -326,6 +328,42 @@ __global__ void k_advance_tick(DevNet n, int num_ticks)
         n.tick[2] = (int)(unsigned)t;
         n.tick[3] = (int)(unsigned)(t >> 32);
     }
+}
+
+// Add the packed per-tick counts of the call's num_ticks ticks (ring rows
+// from the call's first raster row on) into the 64-bit totals. Runs before
+// the tick advance, which moves that row.
+__global__ void k_fold_counts(DevNet n, int num_ticks)
+{
+    const size_t R = (size_t)n.C * n.cnt_rows * n.S;   // counter rows x samples
+    const int r0 = n.tick[1];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < R; i += (size_t)gridDim.x * blockDim.x) {
+        unsigned long long em = 0, ro = 0, ou = 0, de = 0, ev = 0;
+        for (int k = 0; k < num_ticks; ++k) {
+            const unsigned long long w = n.cring[(size_t)((r0 + k) % n.RT) * R + i];
+            em += w & 1023u;
+            ro += (w >> 10) & 1023u;
+            ou += (w >> 20) & 1023u;
+            de += (w >> 30) & 1023u;
+            ev += w >> 40;
+        }
+        unsigned long long *cp = n.cnt + i * CNT_N;
+        cp[CNT_EMITTED] += em;
+        cp[CNT_ROUTED] += ro;
+        cp[CNT_OUT] += ou;
+        cp[CNT_DELIVERED] += de;
+        cp[CNT_EVENTS] += ev;
+    }
+}
+
+hipError_t launch_fold_counts(const DevNet &n, int num_ticks, hipStream_t st)
+{
+    if (num_ticks < 1 || num_ticks > n.RT)
+        return hipErrorInvalidValue;
+    const size_t R = (size_t)n.C * n.cnt_rows * n.S;
+    const unsigned blocks = (unsigned)std::min<size_t>((R + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fold_counts, dim3(blocks), dim3(256), 0, st, n, num_ticks);
+    return hipGetLastError();
 }
 
 hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st)

@@ -84,7 +84,8 @@ struct DevNet {
     int32_t *V;
     uint32_t *ring, *spk, *raster;
     uint64_t *hist;
-    unsigned long long *cnt;
+    unsigned long long *cnt;     // totals [C][cnt_rows][S][CNT_N]
+    unsigned long long *cring;   // per-tick packed counts [RT][C * cnt_rows][S], folded per call
     int *tick;
 };
 
@@ -99,6 +100,22 @@ struct TickArgs {
 // Scheduler slot and raster row of the tick at position k of the call.
 __device__ inline int tick_slot(const DevNet &n, int k) { return (n.tick[0] + k) % n.Q; }
 __device__ inline int tick_row(const DevNet &n, int k) { return (n.tick[1] + k) % n.RT; }
+
+// One tick's counts of one counter row and sample, packed into 64 bits:
+// emitted, routed, output-bus and delivered spikes in 10 bits each (at most
+// 512 per row and tick) and synaptic events in 24 bits (at most 512 * 512).
+// A tick writes its word at the tick's raster row of `cring`; the call's
+// words are added into the 64-bit totals once, after its last tick.
+__device__ inline unsigned long long pack_counts(unsigned emitted, unsigned routed, unsigned out,
+                                                 unsigned delivered, unsigned events)
+{
+    return (unsigned long long)emitted | (unsigned long long)routed << 10 | (unsigned long long)out << 20 |
+           (unsigned long long)delivered << 30 | (unsigned long long)events << 40;
+}
+__device__ inline void store_counts(const DevNet &n, int k, size_t row, int s, unsigned long long packed)
+{
+    n.cring[((size_t)tick_row(n, k) * n.C * n.cnt_rows + row) * n.S + s] = packed;
+}
 
 // One network of a batch advanced together (several networks per launch).
 // unit_begin: the network's first unit in the launch's numbering; code:
@@ -167,6 +184,7 @@ hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_pla
 hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st);
 hipError_t launch_reset_state(const DevNet &n, hipStream_t st);
 hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st);
+hipError_t launch_fold_counts(const DevNet &n, int num_ticks, hipStream_t st);
 bool mfma_shape_supported(int A, int N, int two_planes);
 int mfma_width(int A, int N, int two_planes);   // neurons per MFMA workgroup (128 or 256)
 int mfma_slices(int A, int N, int two_planes);  // MFMA workgroups per core and sample chunk

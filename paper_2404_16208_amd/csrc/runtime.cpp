@@ -46,7 +46,7 @@ enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
     R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
     R_PARAMS_END,  // everything before this is uploaded once at load
-    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_TICK, R_BATCH, R_EXT, R_NREG
+    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_NREG
 };
 
 struct Plan {
@@ -260,6 +260,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_HIST] = tiled ? (size_t)p.Q * C * N * HG * 8 : 0;
     p.size[R_RASTER] = tiled ? (size_t)RT * p.Nout * HG * 8 : (size_t)RT * S * p.Wout * 4;
     p.size[R_CNT] = C * p.cnt_rows * S * CNT_N * 8;   // plain: one row per 64 neurons, MFMA: per slice
+    p.size[R_CRING] = (size_t)RT * C * p.cnt_rows * S * 8;   // one packed word per row, sample and tick of a call
     p.size[R_TICK] = 16;
     p.size[R_BATCH] = BATCH_TABLE_BYTES;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
@@ -586,7 +587,9 @@ static ranc_status queue_ticks(ranc_net *net, const uint32_t *base, int num_tick
                 return hip_fail(e, "launching routing");
         }
     }
-    hipError_t e = launch_advance_tick(net->dn, num_ticks, s);
+    hipError_t e = launch_fold_counts(net->dn, num_ticks, s);
+    if (e == hipSuccess)
+        e = launch_advance_tick(net->dn, num_ticks, s);
     if (e != hipSuccess)
         return hip_fail(e, "advancing the tick");
     return RANC_OK;
@@ -880,7 +883,9 @@ static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t
         }
     }
     hipError_t e = hipSuccess;
-    if (!b.mf.empty())
+    for (size_t i = 0; e == hipSuccess && i < b.nets.size(); ++i)
+        e = launch_fold_counts(b.nets[i]->dn, b.num_ticks, s);
+    if (e == hipSuccess && !b.mf.empty())
         e = launch_advance_batch(tmf, (int)b.mf.size(), b.num_ticks, queue, s);
     if (e == hipSuccess && !b.pl.empty())
         e = launch_advance_batch(tpl, (int)b.pl.size(), b.num_ticks, queue, s);
@@ -1054,6 +1059,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.hist_zero = (const uint64_t *)reg(R_HZERO);
     n.raster = (uint32_t *)reg(R_RASTER);
     n.cnt = (unsigned long long *)reg(R_CNT);
+    n.cring = (unsigned long long *)reg(R_CRING);
     n.tick = (int *)reg(R_TICK);
     std::vector<uint8_t> host;
     pack_params(desc, p, host, net->out_words);
