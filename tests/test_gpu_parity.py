@@ -172,6 +172,18 @@ def test_batch_splits_large_shape_class():
     assert_sample_equal(gs[13], ref[0], 0, T, what="batch-split/oracle")
 
 
+@pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
+def test_fully_connected_core_all_axons_spiking(path):
+    # 512 x 512 crossbar fully connected and every axon spiking every tick:
+    # 2^18 synaptic events per sample and tick, the largest count a tick's
+    # packed counter word must hold
+    net = W.random_net(87, 1, 512, 512, 4, weight_bits=9, max_delay=2, density=1.0, p_core=0.5, p_out=0.5,
+                       input_cores=[0], config_id=715)
+    x = W.bernoulli_inputs(21, net, 64, 3, 1.0, config_id=715)
+    g = assert_parity(net, x, 3, path, samples=[0, 31, 63], what=f"full512/{path}")
+    assert g.counters(0)["events"] >= 3 * 512 * 512
+
+
 # ----------------------------------------------------------- resume / state
 
 @pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
