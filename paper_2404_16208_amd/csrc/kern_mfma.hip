@@ -597,12 +597,13 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     flush();
     lds_barrier();
     write_hist(it - 1 - (it - 1) % L::HB, (it - 1) % L::HB + 1);
+    unsigned long long *cw_out =
+        n.cring + ((size_t)r_row * n.C * n.cnt_rows + (size_t)c * n.cnt_rows + slice) * n.S + s_begin;
     for (int i = threadIdx.x; i < s_end - s_begin; i += blockDim.x) {
         const unsigned sp = s_cnt[0][i], ev = s_cnt[1][i];
         // the core's delivered spikes are counted once, by slice 0
-        store_counts(n, ta.k, (size_t)c * n.cnt_rows + slice, s_begin + i,
-                     pack_counts(sp & 1023u, (sp >> 10) & 1023u, sp >> 20, slice == 0 ? ev >> 18 : 0u,
-                                 ev & ((1u << 18) - 1u)));
+        cw_out[i] = pack_counts(sp & 1023u, (sp >> 10) & 1023u, sp >> 20, slice == 0 ? ev >> 18 : 0u,
+                                ev & ((1u << 18) - 1u));
     }
 }
 

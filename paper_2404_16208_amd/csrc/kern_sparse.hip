@@ -69,8 +69,9 @@ void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
     __shared__ uint32_t x_lds[2][SP_TS][W_ + 1];        // delivered axon words per sample
     __shared__ uint32_t xe_lds[2][SP_TS][W_ + 1];       // external input words per sample
     __shared__ unsigned long long hacc[N_];            // the tile's spike words per neuron
-    // per sample of the chunk: this tick's counts (pack_counts)
-    __shared__ unsigned long long s_cw[SP_SPW_MAX];
+    // per sample of the chunk: [0] emitted | routed << 10 | out << 20,
+    // [1] events | delivered << 19 (events <= 512 * 512 = 2^18)
+    __shared__ unsigned s_cnt[2][SP_SPW_MAX];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -87,8 +88,8 @@ void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
         tm[i] = n.typemask[(size_t)c * G_ * W_ + i];
     for (int i = threadIdx.x; i < N_; i += blockDim.x)
         hacc[i] = 0ull;
-    for (int i = threadIdx.x; i < SP_SPW_MAX; i += blockDim.x)
-        s_cw[i] = 0ull;
+    for (int i = threadIdx.x; i < 2 * SP_SPW_MAX; i += blockDim.x)
+        (&s_cnt[0][0])[i] = 0u;
 
     // neuron parameters of this lane
     int32_t wt[G_][NPL], lk[NPL], th[NPL], rs[NPL];
@@ -285,7 +286,8 @@ void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
                 out += __popc(lo & n.outmask[mw]) + __popc(hi & n.outmask[mw + 1]);
             }
             if (lane == 0) {
-                s_cw[s - s_begin] = pack_counts(emitted, routed, out, delivered, events);
+                s_cnt[0][s - s_begin] = emitted | (routed << 10) | (out << 20);
+                s_cnt[1][s - s_begin] = events | (delivered << 19);
             }
         }
         }
@@ -313,8 +315,11 @@ void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < s_end - s_begin; i += blockDim.x)
-        store_counts(n, ta.k, c, s_begin + i, s_cw[i]);
+    unsigned long long *cw_out = n.cring + ((size_t)r_row * n.C + c) * n.S + s_begin;   // one counter row per core
+    for (int i = threadIdx.x; i < s_end - s_begin; i += blockDim.x) {
+        const unsigned sp = s_cnt[0][i], ev = s_cnt[1][i];
+        cw_out[i] = pack_counts(sp & 1023u, (sp >> 10) & 1023u, sp >> 20, ev >> 19, ev & ((1u << 19) - 1u));
+    }
 }
 
 int sparse_max_samples_per_wg() { return SP_SPW_MAX; }
