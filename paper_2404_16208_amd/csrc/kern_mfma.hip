@@ -151,21 +151,9 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    // Unit v of core c (v = slice + slices * chunk). With a multiple of 8
-    // cores, the units of a core are numbered 8 apart inside a run of 8 cores,
-    // so they are dispatched together and all land on XCD c % 8 (workgroup
-    // index mod 8), where they share the core's weight planes in that XCD's
-    // L2; otherwise cores run fastest.
+    // unit v = slice + slices * chunk of core c, XCD-grouped (core_unit_of)
     int c, v;
-    if ((n.C & 7) == 0) {
-        const int U = n.slices * ((n.S + spw - 1) / spw);
-        const int t = bid >> 3;
-        c = ((t / U) << 3) | (bid & 7);
-        v = t % U;
-    } else {
-        c = bid % n.C;
-        v = bid / n.C;
-    }
+    core_unit_of(bid, n.C, n.slices * ((n.S + spw - 1) / spw), c, v);
     const int slice = v % n.slices;
     const int chunk = v / n.slices;
     const int s_begin = chunk * spw;

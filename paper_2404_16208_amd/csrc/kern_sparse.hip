@@ -77,8 +77,8 @@ void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5;
     const int sig = sigma32(lane & 31);
-    const int c = blockIdx.x % n.C;
-    const int chunk = blockIdx.x / n.C;
+    int c, chunk;   // XCD-grouped (core_unit_of)
+    core_unit_of(blockIdx.x, n.C, (n.S + spw - 1) / spw, c, chunk);
     const int s_begin = chunk * spw;
     const int s_end = min(n.S, s_begin + spw);
 

@@ -115,15 +115,16 @@ def test_mfma_neuron_slices_many_tiles(monkeypatch):
     assert_parity(net, x, 9, "mfma", samples=[0, 1, 63, 64, 127, 128, 150, 198, 199], what="slices")
 
 
-@pytest.mark.parametrize("C,N,spw", [(8, 512, 64), (16, 256, 128)])
-def test_mfma_xcd_grouped_units(C, N, spw, monkeypatch):
+@pytest.mark.parametrize("C,N,spw,path", [(8, 512, 64, "mfma"), (16, 256, 128, "mfma"), (32, 128, 64, "mfma"),
+                                          (32, 256, 128, "sparse")])
+def test_xcd_grouped_units(C, N, spw, path, monkeypatch):
     # a multiple of 8 cores: a core's slices and sample chunks are numbered
     # 8 apart inside runs of 8 cores; several chunks, ragged last tile
     monkeypatch.setenv("RANC_MFMA_SPW", str(spw))
     net = W.random_net(86 + C, C, 128, N, 4, weight_bits=8, max_delay=3, grid_w=4, density=0.2, p_core=0.85,
-                       p_out=0.1, input_cores=[0, 3, 5], config_id=714)
+                       p_out=0.1, input_cores=[0, 3, 5, C - 1], config_id=714)
     x = W.bernoulli_inputs(20, net, 300, 7, 0.3, config_id=714)
-    assert_parity(net, x, 7, "mfma", samples=[0, 63, 64, 130, 255, 256, 299], what=f"xcd C{C}N{N}")
+    assert_parity(net, x, 7, path, samples=[0, 63, 64, 130, 255, 256, 299], what=f"xcd C{C}N{N}/{path}")
 
 
 def test_mfma_64_neuron_cores_many_tiles(monkeypatch):
