@@ -31,7 +31,9 @@ if ROOT not in sys.path:
 METRIC = "synaptic events/sec & core-ticks/sec at 512 cores; batched-MFMA vs plain, bit-exact"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_integrate_mfma_mnist512_s1024.txt")
-KERNEL_SOURCES = ["paper_2404_16208_amd/csrc/kern_mfma.hip", "paper_2404_16208_amd/csrc/kern_common.h",
+TRAFFIC_FILE_MESH = os.path.join(ROOT, "profiles", "traffic_integrate_mesh16384_s64.txt")
+KERNEL_SOURCES = ["paper_2404_16208_amd/csrc/kern_mfma.hip", "paper_2404_16208_amd/csrc/kern_sparse.hip",
+                  "paper_2404_16208_amd/csrc/kern_common.h", "paper_2404_16208_amd/csrc/kern_bits.h",
                   "paper_2404_16208_amd/csrc/ranc_internal.h"]
 
 
@@ -66,13 +68,13 @@ def integrate_algorithmic_bytes(net, S: int, path: str) -> dict:
     return dict(per_unit=per_unit, units=S * C, total=state + params, state=state, params=params)
 
 
-def read_traffic(src_hash: str):
-    """HBM traffic per integration launch from the committed rocprofv3 PMC
+def read_traffic(src_hash: str, path: str = TRAFFIC_FILE, key: str = "hbm_bytes_per_launch"):
+    """HBM traffic per integration launch from a committed rocprofv3 PMC
     summary, or None if it is absent or was taken on other kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -80,7 +82,7 @@ def read_traffic(src_hash: str):
     if kv.get("kernel_source_sha256_16") != src_hash:
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
@@ -198,11 +200,13 @@ def bench_sparse_mesh(args, torch, np):
         ticks = args.steps * T
         per_tick = prof["graph_ms"] / max(1, prof["graph_launches"] * T)
         byts = sparse_mesh_algorithmic_bytes(net, S, delta["delivered"] / ticks, ext_bits)[path]
+        traffic = read_traffic(kernel_source_hash(), TRAFFIC_FILE_MESH, f"{path}_hbm_bytes_per_launch")
         out[path] = {"value": delta["events"] / (ms / 1e3), "ms_per_tick": ms / ticks,
                      "core_ticks_per_s": S * C * ticks / (ms / 1e3),
                      "integrate_avg_ms": per_tick,
                      "roofline": {"bound": "hbm", "achieved": byts / (per_tick / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                                   "unit": "GB/s", "frac": byts / (per_tick / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                  "traffic": (traffic / (per_tick / 1e3) / 1e9) if traffic else None,
                                   "algorithmic_bytes_per_launch": byts},
                      "delivered_axon_rate": delta["delivered"] / (S * C * A * ticks),
                      "input_axon_rate": ext_bits / (S * C * A * T),
@@ -305,6 +309,14 @@ def main():
     from paper_2404_16208_amd.ranc import RancNet
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20)
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {n} bytes done", file=sys.stderr, flush=True)
+        del a, b
     if args.workload == "sparse-mesh":
         bench_sparse_mesh(args, torch, np)
         return
@@ -317,15 +329,6 @@ def main():
     x = W.mnist_inputs(0, S, T)
     xd = torch.from_numpy(x.view(np.int32)).cuda()
     C = net.num_cores
-
-    if args.calib_copy_mib:
-        n = args.calib_copy_mib * (1 << 20)
-        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {n} bytes done", file=sys.stderr, flush=True)
-        del a, b
 
     print("[bench] mfma path: load + warmup + timed steps", file=sys.stderr, flush=True)
     g = RancNet(net, S, T, path="mfma")
