@@ -369,6 +369,40 @@ def test_read_window_errors():
     assert ei.value.status == R.RANC_EINVAL
 
 
+def test_call_errors_leave_state_untouched():
+    """Too many ticks for the handle, an unknown flag, the same handle twice
+    in one batch and a spike buffer that is too small are refused with their
+    status; the refused calls queue nothing, so the run continues exactly."""
+    import ctypes
+    import torch
+    from paper_2404_16208_amd import ranc as R
+    net = W.tiny_net(0)
+    x = W.tiny_inputs(0, S=64, T=16)
+    g = R.RancNet(net, 64, 8, path="mfma")
+    g.run(np.ascontiguousarray(x[:, :8]), 8)
+    stream = torch.cuda.current_stream().cuda_stream
+    for flags, ticks, handles, status in ((0, 9, [g.handle], R.RANC_EINVAL), (0, 0, [g.handle], R.RANC_EINVAL),
+                                          (8, 4, [g.handle], R.RANC_EINVAL),
+                                          (0, 4, [g.handle, g.handle], R.RANC_EINVAL)):
+        with pytest.raises(R.RancError) as ei:
+            R.ranc_run_ticks(handles, None, flags, ticks, stream)
+        assert ei.value.status in (status, R.RANC_ERANGE), (flags, ticks, ei.value.status)
+    assert g.tick == 8
+    g.run(np.ascontiguousarray(x[:, 8:]), 8)
+    ref = oracle_results(net, x, 16, [0, 63])
+    for s in (0, 63):
+        assert_sample_equal(g, ref[s], s, 16, what="after refused calls")
+    # a buffer of one spike for a sample with more: ETRUNC and the needed count
+    count = ctypes.c_int64(0)
+    buf = np.zeros(1, dtype=R.SPIKE_DTYPE)
+    st = R._lib.ranc_read_spikes(g.handle, 0, 8, 16, buf.ctypes.data, 1, ctypes.byref(count))
+    n_out = len(g.spikes(0, 8, 16))
+    if n_out > 1:
+        assert st == R.RANC_ETRUNC and count.value == n_out
+    else:
+        assert st == R.RANC_OK
+
+
 # ----------------------------------------------------------- 512-core MNIST-shaped net
 
 @pytest.fixture(scope="module")
