@@ -220,6 +220,78 @@ def bench_sparse_mesh(args, torch, np):
     print(json.dumps(out), flush=True)
 
 
+# The applications of the paper's Table I: name, ticks, cores, axons and
+# neurons per core, and the serial CPU simulator's time in seconds (context).
+TABLE1 = [("MNIST-12c", 10010, 12, 256, 256, 539), ("MNIST-128c", 10010, 128, 256, 256, 5230),
+          ("MNIST-512c", 10010, 512, 256, 256, 20344), ("VMM 32x32", 788, 21, 256, 256, 65),
+          ("VMM 50x50", 889, 45, 512, 256, 311), ("VMM 60x60", 1095, 51, 512, 256, 434),
+          ("CIFAR10", 10010, 36, 256, 256, 1693), ("TrueNorth Ref.", 500, 4096, 256, 256, 8295)]
+TABLE1_GRID_W = {12: 4, 128: 16, 512: 32, 21: 7, 45: 9, 51: 17, 36: 6, 4096: 64}
+# GPU-RANC (V100S) speedups over the serial simulator that the paper's text
+# states for single applications (Sec. IV-C); their implied GPU times are context.
+TABLE1_PAPER_SPEEDUP = {"MNIST-512c": 780, "TrueNorth Ref.": 521}
+
+
+def bench_table1(args, torch, np):
+    """The shapes of the paper's Table I applications as seeded synthetic
+    networks, one instance each, simulated for the table's number of ticks
+    (graph replays of 128-tick calls, inputs resident in HBM). The networks
+    are stand-ins of the same core counts and core sizes (random crossbars of
+    density 0.2, 4 axon types, 9-bit weights, random routing with delays
+    1..4, Bernoulli(0.1) input on a quarter of the cores); the TrueNorth
+    reference runs without any input or leak, so no neuron ever spikes (the
+    engine's fixed cost per tick)."""
+    from paper_2404_16208_amd import workloads as W
+    from paper_2404_16208_amd.ranc import RancNet
+
+    RT = 128
+    rows = []
+    for i, (name, T, C, A, N, cpu_s) in enumerate(TABLE1):
+        idle = name.startswith("TrueNorth")
+        print(f"[bench] {name}: {C} cores of {A}x{N}, {T} ticks", file=sys.stderr, flush=True)
+        net = W.random_net(900 + i, C, A, N, 4, weight_bits=9, max_delay=4, grid_w=TABLE1_GRID_W[C], density=0.2,
+                           p_core=0.8, p_out=0.1, leak_range=(0, 0) if idle else (-8, 8),
+                           input_cores=[] if idle else list(range(0, C, 4)), config_id=716)
+        x = None if idle else torch.from_numpy(
+            W.bernoulli_inputs(i, net, 1, RT, 0.1, config_id=716).view(np.int32)).cuda()
+        g = RancNet(net, 1, RT)
+        full, rem = divmod(T, RT)
+        xr = None if x is None or rem == 0 else x[:, :rem].contiguous()
+
+        def run_all():
+            for _ in range(full):
+                g.run(x, RT, graph=True)
+            if rem:
+                g.run(xr, rem, graph=True)
+
+        run_all()   # captures both graphs
+        g.reset()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run_all()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        c = g.counters(0)
+        rows.append({"application": name, "ticks": T, "cores": C, "axons": A, "neurons": N, "path": g.path,
+                     "ms": ms, "us_per_tick": 1e3 * ms / T, "core_ticks_per_s": C * T / (ms / 1e3),
+                     "spikes_emitted": c["emitted"], "synaptic_events": c["events"],
+                     "paper_cpu_s": cpu_s, "vs_paper_cpu": cpu_s / (ms / 1e3)})
+        if name in TABLE1_PAPER_SPEEDUP:
+            rows[-1]["paper_gpu_s"] = cpu_s / TABLE1_PAPER_SPEEDUP[name]
+            rows[-1]["vs_paper_gpu"] = rows[-1]["paper_gpu_s"] / (ms / 1e3)
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    out = {"metric": "simulated time per run of the paper's Table I application shapes (one instance each)",
+           "unit": "ms", "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
+           "config": {"workload": "Table I shapes as seeded random networks, 1 sample, the table's tick counts, "
+                                  f"graph replays of {RT}-tick calls", "calls_ticks": RT},
+           "value": sum(r["ms"] for r in rows), "applications": rows}
+    print(json.dumps(out), flush=True)
+
+
 def bench_sweep(args, torch, np):
     """Uneven design-space sweep: 64 seeded network variants (cores 16..4096,
     axons and neurons 64..512, 2-8 axon types, 4-9 bit weights) with 64
@@ -288,9 +360,10 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time per-launch calls instead of graph replays")
-    ap.add_argument("--workload", default="mnist512", choices=["mnist512", "sparse-mesh", "sweep"],
+    ap.add_argument("--workload", default="mnist512", choices=["mnist512", "sparse-mesh", "sweep", "table1"],
                     help="mnist512: the headline line (default); sparse-mesh: the event-driven vs dense "
-                         "comparison on the 16384-core mesh")
+                         "comparison on the 16384-core mesh; sweep: 64 uneven variants in one batch; table1: "
+                         "the paper's Table I application shapes, one instance each")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -322,6 +395,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args, torch, np)
+        return
+    if args.workload == "table1":
+        bench_table1(args, torch, np)
         return
     S, T = args.samples, args.ticks
     print(f"[bench] generating 512-core net and {S}x{T} inputs", file=sys.stderr, flush=True)
