@@ -240,7 +240,7 @@ def bench_table1(args, torch, np):
     density 0.2, 4 axon types, 9-bit weights, random routing with delays
     1..4, Bernoulli(0.1) input on a quarter of the cores); the TrueNorth
     reference runs without any input or leak, so no neuron ever spikes (the
-    engine's fixed cost per tick)."""
+    engine's fixed cost per tick). Path: --path (default: event-driven)."""
     from paper_2404_16208_amd import workloads as W
     from paper_2404_16208_amd.ranc import RancNet
 
@@ -254,7 +254,7 @@ def bench_table1(args, torch, np):
                            input_cores=[] if idle else list(range(0, C, 4)), config_id=716)
         x = None if idle else torch.from_numpy(
             W.bernoulli_inputs(i, net, 1, RT, 0.1, config_id=716).view(np.int32)).cuda()
-        g = RancNet(net, 1, RT)
+        g = RancNet(net, 1, RT, path=args.path)
         full, rem = divmod(T, RT)
         xr = None if x is None or rem == 0 else x[:, :rem].contiguous()
 
@@ -364,6 +364,9 @@ def main():
                     help="mnist512: the headline line (default); sparse-mesh: the event-driven vs dense "
                          "comparison on the 16384-core mesh; sweep: 64 uneven variants in one batch; table1: "
                          "the paper's Table I application shapes, one instance each")
+    ap.add_argument("--path", default="sparse", choices=["auto", "plain", "mfma", "sparse"],
+                    help="integration path of the table1 runs (default sparse: with one instance the "
+                         "event-driven path is the fastest, one launch per tick)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
