@@ -356,6 +356,37 @@ def test_autotune_keeps_results_exact(path, tmp_path):
         assert shape2[k] == shape[k], k
 
 
+@pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
+def test_single_instance_long_run(path):
+    """One instance for 300 ticks as graph replays of 128-tick calls plus a
+    44-tick call: scheduler slots and raster rows wrap many times and the
+    packed per-tick counts are folded once per call; the end state and the
+    output spikes the raster still holds (the last 128 ticks, across calls)
+    equal the oracle's."""
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.random_net(88, 12, 256, 256, 4, weight_bits=9, max_delay=4, grid_w=4, density=0.2, p_core=0.8,
+                       p_out=0.1, input_cores=[0, 4, 8], config_id=717)
+    T, RT = 300, 128
+    x = W.bernoulli_inputs(22, net, 1, T, 0.1, config_id=717)
+    g = RancNet(net, 1, RT, path=path)
+    assert g.path == path
+    t0 = 0
+    while t0 < T:
+        k = min(RT, T - t0)
+        xd = torch.from_numpy(np.ascontiguousarray(x[:, t0:t0 + k]).view(np.int32)).cuda()
+        g.run(xd, k, graph=True)
+        t0 += k
+    torch.cuda.synchronize()
+    ref = oracle_results(net, x, T, [0])[0]
+    assert np.array_equal(g.potentials(0), ref["v"]), "potentials"
+    cnt = g.counters(0)
+    assert all(cnt[k] == ref["counters"][k] for k in cnt), (cnt, ref["counters"])
+    ev = ref["events"]
+    assert np.array_equal(g.spikes(0), ev[ev[:, 0] >= T - RT]), "output spikes of the last 128 ticks"
+    assert np.array_equal(g.spikes(0, T - 44, T), ev[ev[:, 0] >= T - 44]), "output spikes of the last call"
+
+
 def test_read_window_errors():
     from paper_2404_16208_amd import ranc as R
     net = W.tiny_net(0)
