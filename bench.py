@@ -292,6 +292,78 @@ def bench_table1(args, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def bench_stream(args, torch, np):
+    """Streaming, as the paper runs its applications: one instance of the
+    512-core MNIST-shaped net for 10010 ticks with the inputs in pinned host
+    memory. Chunks of 128 ticks: the next chunk's inputs are copied to the
+    GPU on a second stream while the current chunk runs as a graph replay,
+    and each chunk's output-bus spikes are read back before the raster
+    wraps. Host clock over the whole run (upload, simulation, readback)."""
+    from paper_2404_16208_amd import workloads as W
+    from paper_2404_16208_amd.ranc import RancNet
+
+    T, RT = 10010, 128
+    print(f"[bench] generating the 512-core net and 1 x {T} inputs", file=sys.stderr, flush=True)
+    net = W.mnist_net(0)
+    x = W.mnist_inputs(0, 1, T)
+    host = torch.from_numpy(x.view(np.int32)).pin_memory()
+    g = RancNet(net, 1, RT, path=args.path)
+    cstream = torch.cuda.Stream()
+    bufs = [torch.empty((1, RT) + tuple(host.shape[2:]), dtype=torch.int32, device="cuda") for _ in range(2)]
+    chunks = [(t0, min(RT, T - t0)) for t0 in range(0, T, RT)]
+    # the last, shorter chunk has a buffer of its own (a fixed address, so its captured graph is reused)
+    tail = torch.empty((1, chunks[-1][1]) + tuple(host.shape[2:]), dtype=torch.int32, device="cuda")
+
+    def buf_of(i):
+        return tail if chunks[i][1] < RT else bufs[i % 2]
+
+    def run(read: bool):
+        g.reset()
+        done = [None, None]
+        copied = []
+        spikes = 0
+
+        def upload(i):
+            t0, k = chunks[i]
+            b = buf_of(i)
+            with torch.cuda.stream(cstream):
+                if done[i % 2] is not None:
+                    cstream.wait_event(done[i % 2])   # the chunk that last used this buffer has run
+                b.copy_(host[:, t0:t0 + k], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(cstream)
+            return ev
+
+        copied.append(upload(0))
+        for i, (t0, k) in enumerate(chunks):
+            if i + 1 < len(chunks):
+                copied.append(upload(i + 1))
+            torch.cuda.current_stream().wait_event(copied[i])
+            g.run(buf_of(i), k, graph=True)
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream())
+            done[i % 2] = ev
+            if read:
+                spikes += len(g.spikes(0, t0, t0 + k))
+        torch.cuda.synchronize()
+        return spikes
+
+    run(False)   # captures the graphs (both buffers, and the last partial chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_out = run(True)
+    dt = time.perf_counter() - t0
+    out = {"metric": "end-to-end time of a streamed 10010-tick single-instance run (512-core MNIST-shaped net)",
+           "unit": "s", "value": dt, "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"512-core MNIST-shaped net, 1 instance, {T} ticks in {RT}-tick chunks, inputs "
+                                  "in pinned host memory uploaded on a second stream, output spikes read back "
+                                  "per chunk", "path": g.path},
+           "ticks_per_s": T / dt, "us_per_tick": 1e6 * dt / T, "output_spikes": n_out,
+           "paper_gpu_end_to_end_s": 20344 / 780}
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_sweep(args, torch, np):
     """Uneven design-space sweep: 64 seeded network variants (cores 16..4096,
     axons and neurons 64..512, 2-8 axon types, 4-9 bit weights) with 64
@@ -360,13 +432,15 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time per-launch calls instead of graph replays")
-    ap.add_argument("--workload", default="mnist512", choices=["mnist512", "sparse-mesh", "sweep", "table1"],
+    ap.add_argument("--workload", default="mnist512",
+                    choices=["mnist512", "sparse-mesh", "sweep", "table1", "stream"],
                     help="mnist512: the headline line (default); sparse-mesh: the event-driven vs dense "
                          "comparison on the 16384-core mesh; sweep: 64 uneven variants in one batch; table1: "
-                         "the paper's Table I application shapes, one instance each")
+                         "the paper's Table I application shapes, one instance each; stream: one instance "
+                         "streamed for 10010 ticks from host memory, end to end")
     ap.add_argument("--path", default="sparse", choices=["auto", "plain", "mfma", "sparse"],
-                    help="integration path of the table1 runs (default sparse: with one instance the "
-                         "event-driven path is the fastest, one launch per tick)")
+                    help="integration path of the table1 and stream runs (default sparse: with one "
+                         "instance the event-driven path is the fastest, one launch per tick)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -401,6 +475,9 @@ def main():
         return
     if args.workload == "table1":
         bench_table1(args, torch, np)
+        return
+    if args.workload == "stream":
+        bench_stream(args, torch, np)
         return
     S, T = args.samples, args.ticks
     print(f"[bench] generating 512-core net and {S}x{T} inputs", file=sys.stderr, flush=True)

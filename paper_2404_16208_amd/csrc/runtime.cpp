@@ -1217,9 +1217,19 @@ ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, 
         const uint64_t *r64 = reinterpret_cast<const uint64_t *>(net->raster_host.data());
         for (int64_t t = tick_begin; t < tick_end; ++t) {
             const uint64_t *row = r64 + (size_t)(t % p.RT) * p.Nout * HG + sample / 64;
-            for (int o = 0; o < p.Nout; ++o)
-                if ((row[(size_t)o * HG] >> bit) & 1u)
+            // 64 output neurons at a time: gather their bits into one mask
+            // without branches, then emit the set bits in order
+            for (int o0 = 0; o0 < p.Nout; o0 += 64) {
+                const int n = std::min(64, p.Nout - o0);
+                uint64_t m = 0;
+                for (int j = 0; j < n; ++j)
+                    m |= ((row[(size_t)(o0 + j) * HG] >> bit) & 1u) << j;
+                while (m) {
+                    const int o = o0 + __builtin_ctzll(m);
+                    m &= m - 1;
                     emit(t, net->out_neurons[2 * o], net->out_neurons[2 * o + 1]);
+                }
+            }
         }
     } else {
         for (int64_t t = tick_begin; t < tick_end; ++t) {

@@ -159,16 +159,22 @@ def ranc_run_ticks(handles, inputs_ptrs, flags: int, num_ticks: int, stream: int
     _check(_lib.ranc_run_ticks(harr, n, iarr, flags, num_ticks, stream))
 
 
-def ranc_read_spikes(handle: int, sample: int, tick_begin: int, tick_end: int) -> np.ndarray:
+def ranc_read_spikes(handle: int, sample: int, tick_begin: int, tick_end: int, buf: np.ndarray | None = None):
+    """Output-bus spikes of one sample in [tick_begin, tick_end). ``buf``: an
+    optional SPIKE_DTYPE array to decode into (one call when it is large
+    enough; a larger array is made otherwise). Returns (spikes, buffer): the
+    spikes are a view of the buffer."""
     count = C.c_int64(0)
-    st = _lib.ranc_read_spikes(handle, sample, tick_begin, tick_end, None, 0, C.byref(count))
-    if st not in (RANC_OK, RANC_ETRUNC):
-        _check(st)
-    out = np.zeros(int(count.value), dtype=SPIKE_DTYPE)
-    if count.value:
-        _check(_lib.ranc_read_spikes(handle, sample, tick_begin, tick_end, out.ctypes.data, len(out),
-                                     C.byref(count)))
-    return out
+    if buf is None:
+        buf = np.zeros(0, dtype=SPIKE_DTYPE)
+    st = _lib.ranc_read_spikes(handle, sample, tick_begin, tick_end, buf.ctypes.data if len(buf) else None,
+                               len(buf), C.byref(count))
+    if st == RANC_ETRUNC:
+        buf = np.zeros(max(int(count.value), 2 * len(buf)), dtype=SPIKE_DTYPE)
+        st = _lib.ranc_read_spikes(handle, sample, tick_begin, tick_end, buf.ctypes.data, len(buf),
+                                   C.byref(count))
+    _check(st)
+    return buf[:int(count.value)], buf
 
 
 def ranc_read_potentials(handle: int, sample: int, C_: int, N: int) -> np.ndarray:
@@ -295,7 +301,8 @@ class RancNet:
             tick_end = t
         if tick_begin is None:
             tick_begin = max(0, t - self.RT)
-        sp = ranc_read_spikes(self.handle, sample, tick_begin, tick_end)
+        sp, self._spike_buf = ranc_read_spikes(self.handle, sample, tick_begin, tick_end,
+                                               getattr(self, "_spike_buf", None))
         return np.stack([sp["tick"], sp["core"].astype(np.int64), sp["neuron"].astype(np.int64)], axis=1) \
             if len(sp) else np.zeros((0, 3), np.int64)
 
