@@ -447,8 +447,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this engine runs on one GPU; multi-GPU runs are not part of this build "
-                                   "(samples shard across GPUs without communication, see DESIGN.md)",
+        print(json.dumps({"error": "this engine runs on one GPU; runs on several GPUs are not supported "
+                                   "(samples would shard across GPUs with no communication between them)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

@@ -43,7 +43,7 @@ typedef enum ranc_status {
     RANC_EDEVICE = -4,      /* a HIP call or a kernel failed */
     RANC_ESTATE = -5,       /* call not valid in the handle's state (e.g. ticks no longer retained) */
     RANC_ETRUNC = -6,       /* output buffer too small; the required size is reported */
-    RANC_EUNSUPPORTED = -7  /* shape or option this build does not implement */
+    RANC_EUNSUPPORTED = -7  /* shape or option the library does not implement */
 } ranc_status;
 
 /* Destination kinds of a neuron's spikes. */
