@@ -246,7 +246,10 @@ def bench_table1(args, torch, np):
 
     RT = 128
     rows = []
+    apps = [a.strip() for a in args.apps.split(",")] if args.apps else None
     for i, (name, T, C, A, N, cpu_s) in enumerate(TABLE1):
+        if apps is not None and name not in apps:
+            continue
         idle = name.startswith("TrueNorth")
         print(f"[bench] {name}: {C} cores of {A}x{N}, {T} ticks", file=sys.stderr, flush=True)
         net = W.random_net(900 + i, C, A, N, 4, weight_bits=9, max_delay=4, grid_w=TABLE1_GRID_W[C], density=0.2,
@@ -441,6 +444,8 @@ def main():
     ap.add_argument("--path", default="sparse", choices=["auto", "plain", "mfma", "sparse"],
                     help="integration path of the table1 and stream runs (default sparse: with one "
                          "instance the event-driven path is the fastest, one launch per tick)")
+    ap.add_argument("--apps", default="",
+                    help="table1 only: comma-separated application names to run (default: all)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -451,6 +456,11 @@ def main():
                                    "(samples would shard across GPUs with no communication between them)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+
+    if args.apps:
+        unknown = sorted({a.strip() for a in args.apps.split(",")} - {r[0] for r in TABLE1})
+        if args.workload != "table1" or unknown:
+            ap.error(f"--apps applies to --workload table1 and takes names from {[r[0] for r in TABLE1]}")
 
     import numpy as np
     import torch

@@ -19,3 +19,14 @@ def test_bench_refuses_more_than_one_gpu(argv, env):
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+@pytest.mark.parametrize("argv", [["--workload", "table1", "--apps", "no-such-app"],
+                                  ["--workload", "mnist512", "--apps", "MNIST-512c"]])
+def test_bench_rejects_bad_app_filter(argv):
+    # --apps names Table I applications and only applies to that workload;
+    # a bad value is an argument error, raised before any GPU work.
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--apps" in r.stderr
