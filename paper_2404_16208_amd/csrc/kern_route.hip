@@ -106,6 +106,91 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route(DevNet n, int k)
     route_unit<SB, DMAX, STAGE>(n, k, blockIdx.x, blockIdx.y, gridDim.x, sp);
 }
 
+// The same tick for one sample (blockIdx.y) with K lanes per destination
+// word: lane r of a word's group walks entries r, r + K, ... of each delay's
+// list, and the group ORs its partial words together with lane shuffles, so
+// the serial walk is K times shorter and K times more lanes are in flight
+// (used when the samples alone cannot fill the GPU). Lane 0 of the group is
+// still the only writer of the word's scheduler slots. The loop bound is
+// uniform across the block, so every lane reaches every shuffle.
+template <int DMAX, bool STAGE, int K>
+__global__ __launch_bounds__(ROUTE_THREADS) void k_route_split(DevNet n, int k)
+{
+    extern __shared__ uint32_t sp[];
+    static_assert(K >= 2 && K <= 64 && (K & (K - 1)) == 0, "K divides a wavefront");
+    const int q_now = tick_slot(n, k);
+    const int s = blockIdx.y;
+    const size_t words = (size_t)n.C * n.NW;
+    const uint32_t *spk = n.spk + (size_t)s * words;
+    if (STAGE) {
+        for (size_t i = threadIdx.x; i < words; i += blockDim.x)
+            sp[i] = spk[i];
+        __syncthreads();
+    }
+    const uint32_t *bits = STAGE ? sp : spk;
+    const int CW = n.C * n.W;
+    const size_t slot_stride = (size_t)n.S * CW;
+    uint32_t *ring_s = n.ring + (size_t)s * CW;
+    const int r = threadIdx.x & (K - 1);
+    constexpr int WPB = ROUTE_THREADS / K;   // destination words per block and pass
+    for (int dw0 = blockIdx.x * WPB; dw0 < CW; dw0 += gridDim.x * WPB) {
+        const int dw = dw0 + threadIdx.x / K;
+        const bool own = dw < CW;
+        uint32_t acc[DMAX];
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
+            acc[d] = 0u;
+        if (own) {
+            if (r == 0)
+                ring_s[(size_t)q_now * slot_stride + dw] = 0u;
+            const uint16_t *dcnt = n.rt_dcnt + (size_t)dw * DMAX;
+            const uint32_t *e = n.rt_ent + n.rt_goff[dw >> 6] + (dw & 63);
+            uint32_t k0 = 0;
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                const uint32_t kn = k0 + dcnt[d];
+#pragma unroll 2
+                for (uint32_t j = k0 + r; j < kn; j += K) {
+                    const uint32_t ent = e[(size_t)j * 64];
+                    const uint32_t g = ent >> RT_SRC_SHIFT;
+                    acc[d] |= ((bits[g >> 5] >> (g & 31u)) & 1u) << (ent & 31u);
+                }
+                k0 = kn;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) {
+#pragma unroll
+            for (int off = 1; off < K; off <<= 1)
+                acc[d] |= (uint32_t)__shfl_xor((int)acc[d], off, 64);
+        }
+        if (own && r == 0) {
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                if (d >= n.D)
+                    break;
+                int q = q_now + d + 1;
+                if (q >= n.Q)
+                    q -= n.Q;
+                if (acc[d])
+                    ring_s[(size_t)q * slot_stride + dw] |= acc[d];
+            }
+        }
+    }
+}
+
+// Lanes per destination word of the split router.
+static constexpr int ROUTE_SPLIT_K = 8;
+
+// Whether one tick's router runs as k_route_split: one sample per block and
+// too few (sample, word-range) blocks to give every compute unit one.
+static bool route_use_split(const DevNet &n, const RouteCfg &cfg)
+{
+    const int CW = n.C * n.W;
+    const long max_split = (CW + ROUTE_THREADS - 1) / ROUTE_THREADS;
+    return cfg.samples_per_block == 1 && (long)n.S * max_split < 256;
+}
+
 int route_dmax(int D) { return D <= 4 ? 4 : D <= 8 ? 8 : 16; }
 
 // Router variants usable in a batch launch: (samples per block, delay
@@ -210,8 +295,27 @@ RouteCfg route_default_cfg(const DevNet &n)
 template <int SB, int DMAX, bool STAGE>
 static hipError_t launch_route_v(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st)
 {
-    const dim3 grid(cfg.blocks_per_group, (n.S + SB - 1) / SB);
     const size_t lds = STAGE ? (size_t)n.C * n.NW * 4 * SB : 0;
+    if constexpr (SB == 1) {
+        if (route_use_split(n, cfg)) {
+            constexpr int WPB = ROUTE_THREADS / ROUTE_SPLIT_K;
+            const dim3 sgrid((n.C * n.W + WPB - 1) / WPB, n.S);
+            if (lds > 64 * 1024) {
+                static bool raised_split = false;
+                if (!raised_split) {
+                    hipError_t e = hipFuncSetAttribute((const void *)k_route_split<DMAX, STAGE, ROUTE_SPLIT_K>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)ROUTE_LDS_BYTES);
+                    if (e != hipSuccess)
+                        return e;
+                    raised_split = true;
+                }
+            }
+            hipLaunchKernelGGL((k_route_split<DMAX, STAGE, ROUTE_SPLIT_K>), sgrid, dim3(ROUTE_THREADS), lds, st, n, k);
+            return hipGetLastError();
+        }
+    }
+    const dim3 grid(cfg.blocks_per_group, (n.S + SB - 1) / SB);
     if (lds > 64 * 1024) {
         static bool raised = false;
         if (!raised) {
