@@ -442,8 +442,8 @@ def main():
                          "the paper's Table I application shapes, one instance each; stream: one instance "
                          "streamed for 10010 ticks from host memory, end to end")
     ap.add_argument("--path", default="sparse", choices=["auto", "plain", "mfma", "sparse"],
-                    help="integration path of the table1 and stream runs (default sparse: with one "
-                         "instance the event-driven path is the fastest, one launch per tick)")
+                    help="integration path of the table1 and stream runs (default sparse: the event-driven "
+                         "path, one launch per tick, fastest on the MNIST-512c shape)")
     ap.add_argument("--apps", default="",
                     help="table1 only: comma-separated application names to run (default: all)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
