@@ -460,11 +460,54 @@ __global__ void k_fold_counts(DevNet n, int num_ticks)
     }
 }
 
+// The same fold with one wavefront per counter row (few rows, e.g. a single
+// sample): lane l adds ticks l, l + 64, ..., and the wavefront sums the five
+// totals with shuffles before lane 0 adds them in.
+__global__ __launch_bounds__(256) void k_fold_counts_wave(DevNet n, int num_ticks)
+{
+    const size_t R = (size_t)n.C * n.cnt_rows * n.S;
+    const int r0 = n.tick[1];
+    const int lane = threadIdx.x & 63;
+    const size_t i = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i >= R)
+        return;   // whole wavefronts leave together
+    unsigned long long em = 0, ro = 0, ou = 0, de = 0, ev = 0;
+    for (int k = lane; k < num_ticks; k += 64) {
+        const unsigned long long w = n.cring[(size_t)((r0 + k) % n.RT) * R + i];
+        em += w & 1023u;
+        ro += (w >> 10) & 1023u;
+        ou += (w >> 20) & 1023u;
+        de += (w >> 30) & 1023u;
+        ev += w >> 40;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        em += __shfl_xor(em, off, 64);
+        ro += __shfl_xor(ro, off, 64);
+        ou += __shfl_xor(ou, off, 64);
+        de += __shfl_xor(de, off, 64);
+        ev += __shfl_xor(ev, off, 64);
+    }
+    if (lane == 0) {
+        unsigned long long *cp = n.cnt + i * CNT_N;
+        cp[CNT_EMITTED] += em;
+        cp[CNT_ROUTED] += ro;
+        cp[CNT_OUT] += ou;
+        cp[CNT_DELIVERED] += de;
+        cp[CNT_EVENTS] += ev;
+    }
+}
+
 hipError_t launch_fold_counts(const DevNet &n, int num_ticks, hipStream_t st)
 {
     if (num_ticks < 1 || num_ticks > n.RT)
         return hipErrorInvalidValue;
     const size_t R = (size_t)n.C * n.cnt_rows * n.S;
+    if (R <= 16384 && num_ticks >= 8) {
+        // fewer rows than a thread per row would spread over the GPU
+        hipLaunchKernelGGL(k_fold_counts_wave, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, st, n, num_ticks);
+        return hipGetLastError();
+    }
     const unsigned blocks = (unsigned)std::min<size_t>((R + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fold_counts, dim3(blocks), dim3(256), 0, st, n, num_ticks);
     return hipGetLastError();
