@@ -240,7 +240,8 @@ def bench_table1(args, torch, np):
     density 0.2, 4 axon types, 9-bit weights, random routing with delays
     1..4, Bernoulli(0.1) input on a quarter of the cores); the TrueNorth
     reference runs without any input or leak, so no neuron ever spikes (the
-    engine's fixed cost per tick). Path: --path (default: event-driven)."""
+    engine's fixed cost per tick). Path: --path (default: auto, the plain path
+    for one instance)."""
     from paper_2404_16208_amd import workloads as W
     from paper_2404_16208_amd.ranc import RancNet
 
@@ -441,9 +442,9 @@ def main():
                          "comparison on the 16384-core mesh; sweep: 64 uneven variants in one batch; table1: "
                          "the paper's Table I application shapes, one instance each; stream: one instance "
                          "streamed for 10010 ticks from host memory, end to end")
-    ap.add_argument("--path", default="sparse", choices=["auto", "plain", "mfma", "sparse"],
-                    help="integration path of the table1 and stream runs (default sparse: the event-driven "
-                         "path, one launch per tick, fastest on the MNIST-512c shape)")
+    ap.add_argument("--path", default="auto", choices=["auto", "plain", "mfma", "sparse"],
+                    help="integration path of the table1 and stream runs (default auto: the plain path for "
+                         "one instance, with the lane-split router the fastest on every Table I shape)")
     ap.add_argument("--apps", default="",
                     help="table1 only: comma-separated application names to run (default: all)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
