@@ -459,6 +459,19 @@ def test_mnist512_paths_agree_all_samples(mnist):
         assert gp.counters(s) == gm.counters(s), s
 
 
+@pytest.mark.parametrize("S,chunks", [(1, [5, 27]), (15, None), (16, None)])
+def test_mnist512_router_split_boundary(mnist, S, chunks):
+    """The 512-core net on the plain path at one instance and on both sides of
+    the router's switch to eight lanes per destination word (512 cores x 8
+    words = 16 router blocks per sample: eight lanes per word below 16
+    samples, one lane per word from 16 on), every sample against the oracle.
+    At one sample the 5-tick call folds its counts with a thread per counter
+    row and the 27-tick call with a wavefront per row."""
+    net, x = mnist
+    xs = np.ascontiguousarray(x[:S])
+    assert_parity(net, xs, 32, "plain", chunks=chunks, what=f"mnist512 router boundary S={S}")
+
+
 def test_mnist512_batched_1024_samples():
     """The 1024-sample batch on the MFMA path: sampled samples against the
     oracle, every sample against the plain GPU path, and the first 100 samples
