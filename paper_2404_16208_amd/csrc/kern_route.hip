@@ -178,13 +178,22 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_split(DevNet n, int k)
 // Lanes per destination word of the split router.
 static constexpr int ROUTE_SPLIT_K = 8;
 
-// Whether one tick's router runs as k_route_split: one sample per block and
-// too few (sample, word-range) blocks to give every compute unit one.
+// Whether one tick's router runs as k_route_split: the one-lane-per-word
+// launch of this configuration would have fewer blocks than the GPU has
+// compute units.
 static bool route_use_split(const DevNet &n, const RouteCfg &cfg)
 {
-    const int CW = n.C * n.W;
-    const long max_split = (CW + ROUTE_THREADS - 1) / ROUTE_THREADS;
-    return cfg.samples_per_block == 1 && (long)n.S * max_split < 256;
+    const long groups = (n.S + cfg.samples_per_block - 1) / cfg.samples_per_block;
+    return (long)cfg.blocks_per_group * groups < 256;
+}
+
+template <int DMAX>
+static hipError_t launch_route_split(const DevNet &n, int k, hipStream_t st)
+{
+    constexpr int WPB = ROUTE_THREADS / ROUTE_SPLIT_K;
+    const dim3 grid((n.C * n.W + WPB - 1) / WPB, n.S);
+    hipLaunchKernelGGL((k_route_split<DMAX, ROUTE_SPLIT_K>), grid, dim3(ROUTE_THREADS), 0, st, n, k);
+    return hipGetLastError();
 }
 
 int route_dmax(int D) { return D <= 4 ? 4 : D <= 8 ? 8 : 16; }
@@ -292,14 +301,6 @@ template <int SB, int DMAX, bool STAGE>
 static hipError_t launch_route_v(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st)
 {
     const size_t lds = STAGE ? (size_t)n.C * n.NW * 4 * SB : 0;
-    if constexpr (SB == 1) {
-        if (route_use_split(n, cfg)) {
-            constexpr int WPB = ROUTE_THREADS / ROUTE_SPLIT_K;
-            const dim3 sgrid((n.C * n.W + WPB - 1) / WPB, n.S);
-            hipLaunchKernelGGL((k_route_split<DMAX, ROUTE_SPLIT_K>), sgrid, dim3(ROUTE_THREADS), 0, st, n, k);
-            return hipGetLastError();
-        }
-    }
     const dim3 grid(cfg.blocks_per_group, (n.S + SB - 1) / SB);
     if (lds > 64 * 1024) {
         static bool raised = false;
@@ -344,6 +345,14 @@ hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t
         return hipErrorInvalidValue;
     if ((n.S + cfg.samples_per_block - 1) / cfg.samples_per_block > 65535)
         return hipErrorInvalidValue;
+    if (route_use_split(n, cfg)) {
+        // S < 256 x samples per block <= 2048 here: one sample per grid row fits
+        switch (route_dmax(n.D)) {
+        case 4: return launch_route_split<4>(n, k, st);
+        case 8: return launch_route_split<8>(n, k, st);
+        default: return launch_route_split<16>(n, k, st);
+        }
+    }
     switch (cfg.samples_per_block) {
     case 1: return launch_route_s<1>(n, k, cfg, st);
     case 2: return launch_route_s<2>(n, k, cfg, st);

@@ -459,14 +459,15 @@ def test_mnist512_paths_agree_all_samples(mnist):
         assert gp.counters(s) == gm.counters(s), s
 
 
-@pytest.mark.parametrize("S,chunks", [(1, [5, 27]), (15, None), (16, None)])
+@pytest.mark.parametrize("S,chunks", [(1, [5, 27]), (60, None), (61, None)])
 def test_mnist512_router_split_boundary(mnist, S, chunks):
     """The 512-core net on the plain path at one instance and on both sides of
-    the router's switch to eight lanes per destination word (512 cores x 8
-    words = 16 router blocks per sample: eight lanes per word below 16
-    samples, one lane per word from 16 on), every sample against the oracle.
-    At one sample the 5-tick call folds its counts with a thread per counter
-    row and the 27-tick call with a wavefront per row."""
+    the router's switch to eight lanes per destination word (its default
+    one-lane launch has 16 blocks per group of 4 samples, so eight lanes per
+    word run while that is under 256 blocks, up to 60 samples, and one lane
+    per word from 61 on), every sample against the oracle. At one sample the
+    5-tick call folds its counts with a thread per counter row and the
+    27-tick call with a wavefront per row."""
     net, x = mnist
     xs = np.ascontiguousarray(x[:S])
     assert_parity(net, xs, 32, "plain", chunks=chunks, what=f"mnist512 router boundary S={S}")
