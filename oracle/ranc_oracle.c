@@ -78,6 +78,7 @@ typedef struct orc_sim {
     uint8_t *sram;         /* scheduler SRAM [C][rows][A] of booleans */
     int32_t *curr;         /* [C] row of the current tick */
     uint8_t *spiked;       /* [C][N] spike flags of the current tick */
+    int32_t *active;       /* [A] axons of the core being integrated that hold a spike */
     int64_t counters[ORC_NCOUNTERS];
 } orc_sim;
 
@@ -168,8 +169,9 @@ orc_sim *orc_new(const orc_net *n)
     s->spiked = (uint8_t *)calloc(cn, 1);
     s->sram = (uint8_t *)calloc((size_t)n->num_cores * s->rows * n->num_axons, 1);
     s->curr = (int32_t *)malloc((size_t)n->num_cores * sizeof(int32_t));
-    if (!s->potential || !s->spiked || !s->sram || !s->curr) {
-        free(s->potential); free(s->spiked); free(s->sram); free(s->curr); free(s);
+    s->active = (int32_t *)malloc((size_t)n->num_axons * sizeof(int32_t));
+    if (!s->potential || !s->spiked || !s->sram || !s->curr || !s->active) {
+        free(s->potential); free(s->spiked); free(s->sram); free(s->curr); free(s->active); free(s);
         return NULL;
     }
     memcpy(s->potential, n->v_init, cn * sizeof(int32_t));
@@ -185,7 +187,7 @@ void orc_free(orc_sim *s)
 {
     if (!s)
         return;
-    free(s->potential); free(s->spiked); free(s->sram); free(s->curr); free(s);
+    free(s->potential); free(s->spiked); free(s->sram); free(s->curr); free(s->active); free(s);
 }
 
 /*
@@ -232,11 +234,18 @@ int orc_run(orc_sim *s, const uint32_t *ext, int32_t T, int64_t *out_events, int
         /* Neuron block. */
         for (int c = 0; c < C; ++c) {
             const uint8_t *row = sram_row(s, c, s->curr[c]);
+            /* An axon without a spike adds nothing to any neuron's sum, so the
+             * accumulation visits only the axons whose bit is set. */
+            int nact = 0;
+            for (int a = 0; a < A; ++a)
+                if (row[a])
+                    s->active[nact++] = a;
             for (int j = 0; j < N; ++j) {
                 size_t cj = (size_t)c * N + j;
                 int64_t acc = 0;
                 int64_t events = 0;
-                for (int a = 0; a < A; ++a) {
+                for (int k = 0; k < nact; ++k) {
+                    const int a = s->active[k];
                     /* a term counts iff the axon holds a spike and is connected */
                     int hit = row[a] & connected(n, c, a, j);
                     int type = n->axon_type[(size_t)c * A + a];
