@@ -38,7 +38,7 @@ DEST_CORE = 1
 DEST_OUT = 2
 
 # purposes of random streams
-_P_XBAR, _P_TYPE, _P_W, _P_PARAM, _P_DEST, _P_PIXMAP, _P_INTENS, _P_TICKU, _P_EXT = range(9)
+_P_XBAR, _P_TYPE, _P_W, _P_PARAM, _P_DEST, _P_PIXMAP, _P_INTENS, _P_TICKU, _P_EXT, _P_MODEL = range(10)
 
 
 def rng_for(seed: int, *key: int) -> np.random.Generator:
@@ -89,6 +89,10 @@ class Net:
     dest_delay: np.ndarray    # uint8  [C, N]
     input_cores: np.ndarray   # int32  [C_in]
     name: str = ""
+    leak_bits: int = 32       # leaks are signed values of this many bits
+    reset_bits: int = 32      # reset potentials are signed values of this many bits
+    floor: np.ndarray | None = None       # int32 [C, N]: lowest potential kept without firing (None: none)
+    reset_mode: np.ndarray | None = None  # uint8 [C, N]: 0 absolute reset, 1 linear reset (None: all absolute)
 
     @property
     def shape(self) -> Tuple[int, int, int, int]:
@@ -119,12 +123,17 @@ def random_net(seed: int, C: int, A: int, N: int, G: int, weight_bits: int = 9,
                density: float = 0.2, p_core: float = 0.8, p_out: float = 0.1,
                leak_range=(-8, 8), thr_range=(64, 512), reset_range=(0, 0),
                vinit_range=(0, 0), input_cores=None, config_id: int = 99,
-               weight_range=None) -> Net:
+               weight_range=None, floor_range=None, linear_frac: float = 0.0,
+               leak_bits: int = 32, reset_bits: int = 32) -> Net:
     """A generic seeded random network (any C, A, N, G), used by tests.
 
     Each neuron independently gets a CORE destination with probability
     ``p_core`` (uniform random core and axon, delay uniform in
-    1..max_delay), OUT with probability ``p_out``, else NONE.
+    1..max_delay), OUT with probability ``p_out``, else NONE. Neuron-model
+    options (drawn from a stream of their own, so they leave every other
+    draw unchanged): ``floor_range`` draws a floor per neuron (clipped to the
+    potential range), ``linear_frac`` puts that fraction of the neurons in
+    linear-reset mode.
     """
     if grid_w is None:
         grid_w = C
@@ -163,9 +172,18 @@ def random_net(seed: int, C: int, A: int, N: int, G: int, weight_bits: int = 9,
     ddel = np.where(core_mask, ddel, 0).astype(np.uint8)
     if input_cores is None:
         input_cores = np.arange(max(1, C // 2))
+    floor = mode = None
+    if floor_range is not None or linear_frac > 0:
+        r = rng_for(seed, config_id, _P_MODEL)
+        lo, hi = -(1 << (potential_bits - 1)), (1 << (potential_bits - 1)) - 1
+        if floor_range is not None:
+            floor = np.clip(r.integers(floor_range[0], floor_range[1] + 1, size=(C, N)), lo, hi).astype(np.int32)
+        if linear_frac > 0:
+            mode = (r.random((C, N)) < linear_frac).astype(np.uint8)
     return Net(C, A, N, G, weight_bits, potential_bits, max_delay, grid_w, grid_h,
                xbar, atype, w, leak, thr, rst, v0, kind, dx, dy, daxon, ddel,
-               np.asarray(input_cores, dtype=np.int32), name=f"random{C}x{A}x{N}g{G}").contiguous()
+               np.asarray(input_cores, dtype=np.int32), name=f"random{C}x{A}x{N}g{G}",
+               leak_bits=leak_bits, reset_bits=reset_bits, floor=floor, reset_mode=mode).contiguous()
 
 
 def bernoulli_inputs(seed: int, net: Net, S: int, T: int, rate, config_id: int = 99,
@@ -321,14 +339,43 @@ def sparse_mesh_net(seed: int = 0, side: int = 128) -> Net:
 SPARSE_MESH_THRESHOLD_SCALE = 4
 
 
-def sparse_mesh_inputs(seed: int, net: Net, S: int, T: int, t0: int = 0) -> np.ndarray:
-    """Bernoulli(r_s) input on every axon, r_s ~ U[0.01, 0.05] per sample."""
-    rates = rng_for(seed, 5, _P_INTENS).uniform(0.01, 0.05, size=max(S, 64))[:S]
+SPARSE_MESH_INPUT_BLOCK = 10   # ticks drawn from one random stream
+
+
+def bernoulli_bits(r: np.random.Generator, n: int, p: float) -> np.ndarray:
+    """n independent Bernoulli(p) draws as a bool array, from the gaps between
+    successes (geometric with parameter p), so the cost follows n * p."""
+    out = np.zeros(n, dtype=bool)
+    if p <= 0.0:
+        return out
+    pos = -1
+    while True:
+        k = max(1024, int(1.2 * (n - pos) * p) + 64)
+        hits = pos + np.cumsum(r.geometric(p, size=k))
+        inside = hits[hits < n]
+        out[inside] = True
+        if len(inside) < k:
+            return out
+        pos = int(hits[-1])
+
+
+def sparse_mesh_inputs(seed: int, net: Net, S: int, T: int, t0: int = 0, samples=None) -> np.ndarray:
+    """Bernoulli(r_s) input on every axon for ticks [t0, t0 + T), with
+    r_s ~ U[0.01, 0.05] per sample; [len(samples), T, C_in, A/32] (samples:
+    default 0..S-1). Ticks come in blocks of SPARSE_MESH_INPUT_BLOCK, each
+    from its own (sample, block) stream, so any tick range of any sample can be
+    drawn alone and agrees with a longer draw."""
+    samples = list(range(S)) if samples is None else [int(s) for s in samples]
+    rates = rng_for(seed, 5, _P_INTENS).uniform(0.01, 0.05, size=max(64, max(samples) + 1))
     Cin, A = len(net.input_cores), net.num_axons
-    out = np.empty((S, T, Cin, A // 32), dtype=np.uint32)
-    for i in range(S):
-        r = rng_for(seed, 5, _P_EXT, i, t0)
-        out[i] = pack_bits(r.random((T, Cin, A)) < rates[i])
+    B = SPARSE_MESH_INPUT_BLOCK
+    out = np.empty((len(samples), T, Cin, A // 32), dtype=np.uint32)
+    for i, s in enumerate(samples):
+        for b in range(t0 // B, (t0 + T + B - 1) // B):
+            bits = bernoulli_bits(rng_for(seed, 5, _P_EXT, s, b), B * Cin * A, float(rates[s]))
+            words = pack_bits(bits.reshape(B, Cin, A))
+            lo, hi = max(t0, b * B), min(t0 + T, (b + 1) * B)
+            out[i, lo - t0:hi - t0] = words[lo - b * B:hi - b * B]
     return out
 
 

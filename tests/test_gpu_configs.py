@@ -1,0 +1,234 @@
+"""GPU parity at the five workload configurations, at their configured sizes.
+
+Each test runs a workload in the launch configuration the benchmark times
+(graph replays of the tick loop, inputs resident in device memory) and
+compares the HIP library with the serial oracle, element by element: every
+output-bus spike (tick, core, neuron) of every tick, the final potentials of
+every neuron and the five counters, for every sample listed.
+
+  c1  tiny 5-core net, 10 samples x 16 ticks        (test_gpu_parity.py)
+  c2  512-core MNIST-shaped net, all 100 samples x 32 ticks, plain and MFMA
+      paths, plus the class read-out (argmax of class spike counts)
+  c3  the same net, all 1024 samples x 32 ticks in one batched MFMA launch
+  c4  all 64 design-space variants in one batch, 64 samples x 16 ticks (two
+      8-tick calls), per-shape-class launches and the persistent launch,
+      samples 0 and 63 of every variant
+  c5  the 16384-core mesh, all 64 samples x 100 ticks in 10-tick calls
+      (the 16-slot scheduler wraps six times), event-driven and dense MFMA
+"""
+import threading
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from oracle import ranc_oracle as O
+from paper_2404_16208_amd import workloads as W
+from tests.parity_utils import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_16208_amd import ranc  # noqa: F401  (fails loudly if the library is missing)
+
+
+def _run_collect(g, chunks, samples, graph=True):
+    """Advance the handle call by call; chunks yields (device input or None,
+    ticks). Output spikes of the listed samples are read after every call, so
+    every tick is compared, not only the ticks the raster still holds."""
+    import torch
+    got = {s: [] for s in samples}
+    t = g.tick
+    for xd, k in chunks:
+        g.run(xd, k, graph=graph)
+        torch.cuda.synchronize()
+        for s in samples:
+            got[s].append(g.spikes(s, t, t + k))
+        t += k
+    return {s: np.concatenate(v) if v else np.zeros((0, 3), np.int64) for s, v in got.items()}
+
+
+def _compare(g, ref, spikes, what):
+    """ref: sample -> oracle result; spikes: sample -> GPU output spikes."""
+    for s, r in ref.items():
+        ev = spikes[s]
+        assert ev.shape == r["events"].shape and np.array_equal(ev, r["events"]), \
+            f"{what} sample {s}: output spikes differ ({len(ev)} vs {len(r['events'])})"
+        v = g.potentials(s)
+        if not np.array_equal(v, r["v"]):
+            bad = np.argwhere(v != r["v"])
+            raise AssertionError(f"{what} sample {s}: {len(bad)} potentials differ, first {bad[0].tolist()}")
+        cnt = g.counters(s)
+        for k in ("emitted", "routed", "delivered", "out", "events"):
+            assert cnt[k] == r["counters"][k], f"{what} sample {s}: counter {k} {cnt[k]} vs {r['counters'][k]}"
+
+
+def _class_of(net, events):
+    """Class read-out of the MNIST-shaped net: spikes per class (class of an
+    output neuron = its global index mod 10), argmax with the lowest class
+    winning ties."""
+    cls = W.mnist_class_of_output(net)
+    votes = np.zeros(10, np.int64)
+    if len(events):
+        np.add.at(votes, cls[events[:, 1], events[:, 2]], 1)
+    return int(np.argmax(votes)), votes
+
+
+# ----------------------------------------------------------- c2 / c3: the 512-core net
+
+@pytest.fixture(scope="module")
+def mnist100():
+    net = W.mnist_net(0)
+    x = W.mnist_inputs(0, 100, 32)
+    log("[c2] oracle: 100 samples x 32 ticks")
+    ref = {r["sample"]: r for r in O.simulate(net, x, 32)}
+    return net, x, ref
+
+
+@pytest.mark.parametrize("path", ["plain", "mfma"])
+def test_c2_mnist512_all_100_samples(mnist100, path):
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet
+    net, x, ref = mnist100
+    log(f"[c2] {path}: 100 samples x 32 ticks, graph replay")
+    g = RancNet(net, 100, 32, path=path)
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    spikes = _run_collect(g, [(xd, 32)], range(100))
+    _compare(g, ref, spikes, f"c2/{path}")
+    classes = [_class_of(net, spikes[s]) for s in range(100)]
+    for s in range(100):
+        want = _class_of(net, ref[s]["events"])
+        assert classes[s][0] == want[0] and np.array_equal(classes[s][1], want[1]), s
+    g.close()
+
+
+def test_c3_mnist512_all_1024_samples():
+    """The benchmark's configuration: 1024 samples in one MFMA launch per
+    tick, the 32-tick loop as one graph replay, inputs in device memory; every
+    sample against the oracle (in batches of 64 samples, so that only one
+    batch's spike lists are held at a time). A second replay (ticks 32..63,
+    the same input buffer, as the benchmark's second step) is checked on 64
+    samples against 64-tick oracle runs."""
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.mnist_net(0)
+    log("[c3] generating 1024 x 32 inputs")
+    x = W.mnist_inputs(0, 1024, 32)
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    g = RancNet(net, 1024, 32, path="mfma")
+    log("[c3] GPU: one graph replay of 32 ticks")
+    g.run(xd, 32, graph=True)
+    torch.cuda.synchronize()
+    for b0 in range(0, 1024, 64):
+        batch = range(b0, b0 + 64)
+        ref = {r["sample"]: r for r in O.simulate(net, x, 32, samples=batch)}
+        _compare(g, ref, {s: g.spikes(s, 0, 32) for s in batch}, "c3/mfma")
+        log(f"[c3] samples {b0}..{b0 + 63} equal the oracle")
+    picks = list(range(0, 1024, 16))
+    spikes2 = _run_collect(g, [(xd, 32)], picks)
+    x2 = np.concatenate([x[picks], x[picks]], axis=1)
+    ref2 = {}
+    for r in O.simulate(net, x2, 64):
+        ev = r["events"]
+        ref2[picks[r["sample"]]] = dict(r, events=ev[ev[:, 0] >= 32])
+    _compare(g, ref2, spikes2, "c3/mfma replay 2")
+    log("[c3] second replay: 64 samples equal 64-tick oracle runs")
+    g.close()
+
+
+# ----------------------------------------------------------- c4: the design-space sweep
+
+@pytest.fixture(scope="module")
+def sweep64():
+    log("[c4] generating 64 variants and their inputs")
+    S, T = 64, 16
+    nets = [W.sweep_variant(0, v)[0] for v in range(64)]
+    xs = [W.bernoulli_inputs(v, n, S, T, 0.1, config_id=4) for v, n in enumerate(nets)]
+    log("[c4] oracle: samples 0 and 63 of every variant, 16 ticks")
+    jobs = [(v, s) for v in range(64) for s in (0, 63)]
+    jobs.sort(key=lambda j: -nets[j[0]].num_cores * nets[j[0]].num_neurons * nets[j[0]].num_axons)
+    lock, ref = threading.Lock(), {}
+
+    def one(job):
+        v, s = job
+        sim = O.OracleSim(nets[v])
+        ev, _, _ = sim.run(xs[v][s], T)
+        r = dict(sample=s, events=ev, v=sim.potentials(), counters=sim.counters())
+        with lock:
+            ref[job] = r
+
+    with ThreadPoolExecutor(max_workers=O.default_threads()) as ex:
+        list(ex.map(one, jobs))
+    return nets, xs, ref, S, T
+
+
+@pytest.mark.parametrize("persistent", [False, True], ids=["per_class", "persistent"])
+def test_c4_sweep_all_64_variants_one_batch(sweep64, persistent):
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet, run_batch
+    nets, xs, ref, S, T = sweep64
+    TC = 8
+    log(f"[c4] loading 64 variants ({sum(n.num_cores for n in nets)} cores), persistent={persistent}")
+    gs = [RancNet(n, S, TC) for n in nets]
+    paths = [g.path for g in gs]
+    log(f"[c4] paths: {paths.count('mfma')} mfma, {paths.count('plain')} plain")
+    bufs = [torch.empty((S, TC) + x.shape[2:], dtype=torch.int32, device="cuda") for x in xs]
+    got = {(v, s): [] for v in range(64) for s in (0, 63)}
+    for call in range(T // TC):
+        for b, x in zip(bufs, xs):
+            b.copy_(torch.from_numpy(np.ascontiguousarray(x[:, call * TC:(call + 1) * TC]).view(np.int32)))
+        run_batch(gs, bufs, TC, graph=True, persistent=persistent)
+        torch.cuda.synchronize()
+        log(f"[c4] call {call} done")
+        for v in range(64):
+            for s in (0, 63):
+                got[(v, s)].append(gs[v].spikes(s, call * TC, (call + 1) * TC))
+    for v, g in enumerate(gs):
+        assert g.tick == T
+        r = {s: ref[(v, s)] for s in (0, 63)}
+        _compare(g, r, {s: np.concatenate(got[(v, s)]) for s in (0, 63)}, f"c4/{nets[v].name}/{g.path}")
+    for g in gs:
+        g.close()
+
+
+# ----------------------------------------------------------- c5: the 16384-core mesh
+
+C5_T, C5_TC, C5_S = 100, 10, 64
+
+
+@pytest.fixture(scope="module")
+def mesh():
+    log("[c5] generating the 16384-core mesh")
+    net = W.sparse_mesh_net(0)
+    log(f"[c5] generating inputs, {C5_S} samples x {C5_T} ticks")
+    x = W.sparse_mesh_inputs(0, net, C5_S, C5_T)
+    log("[c5] oracle: 64 samples x 100 ticks")
+    ref = {r["sample"]: r for r in O.simulate(net, x, C5_T)}
+    return net, x, ref
+
+
+@pytest.mark.parametrize("path", ["sparse", "mfma"])
+def test_c5_mesh_16384_cores_all_samples(mesh, path):
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet
+    net, x, ref = mesh
+    log(f"[c5] {path}: {C5_S} samples x {C5_T} ticks in {C5_TC}-tick graph replays")
+    g = RancNet(net, C5_S, C5_TC, path=path)
+    buf = torch.empty((C5_S, C5_TC) + x.shape[2:], dtype=torch.int32, device="cuda")
+
+    def chunks():
+        for t0 in range(0, C5_T, C5_TC):
+            buf.copy_(torch.from_numpy(np.ascontiguousarray(x[:, t0:t0 + C5_TC]).view(np.int32)))
+            yield buf, C5_TC
+
+    spikes = _run_collect(g, chunks(), range(C5_S))
+    _compare(g, ref, spikes, f"c5/{path}")
+    tot = g.total_counters()
+    rate = (tot["delivered"] + int(np.unpackbits(x.view(np.uint8)).sum())) / (C5_S * C5_T * net.num_cores * 256)
+    log(f"[c5] {path}: total axon rate {rate:.4f}")
+    assert 0.005 <= rate <= 0.08
+    g.close()
