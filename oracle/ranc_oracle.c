@@ -31,7 +31,15 @@
  *   - leak is applied to every neuron on every tick;
  *   - the sum V + I + leak is formed exactly (int64) and clamped once per tick
  *     to a signed potential_bits-bit range;
- *   - on a spike the potential becomes the neuron's reset value;
+ *   - on a spike the potential becomes the neuron's reset value (absolute
+ *     reset) or, for a neuron in linear-reset mode, U - threshold clamped to
+ *     the potential range;
+ *   - a neuron that does not fire and whose U lies below its floor (a
+ *     negative threshold) keeps the floor instead; the floor does not apply
+ *     to the value a spike resets to;
+ *   - leaks, reset potentials and weights are signed values of leak_bits,
+ *     reset_bits and weight_bits bits (Sec. I and Sec. V name these widths as
+ *     configurable); a value outside its width is rejected;
  *   - several packets to the same (core, axon, tick) set one bit (the scheduler
  *     SRAM is an array of booleans), so they count once;
  *   - a packet with tick offset d written during tick t is read at tick t+d,
@@ -55,6 +63,8 @@ enum { ORC_EMITTED = 0, ORC_ROUTED, ORC_DELIVERED, ORC_OUT, ORC_EVENTS, ORC_HOPS
 
 enum { ORC_DEST_NONE = 0, ORC_DEST_CORE = 1, ORC_DEST_OUT = 2 };
 
+enum { ORC_RESET_ABSOLUTE = 0, ORC_RESET_LINEAR = 1 };
+
 typedef struct orc_net {
     int32_t num_cores, num_axons, num_neurons, num_types;
     int32_t weight_bits, potential_bits, max_delay, grid_w, grid_h;
@@ -68,6 +78,9 @@ typedef struct orc_net {
     const uint8_t *dest_delay;
     int32_t num_input_cores;
     const int32_t *input_cores; /* [C_in] */
+    int32_t leak_bits, reset_bits;
+    const int32_t *floor;       /* [C][N] lowest potential kept without firing, or NULL (none) */
+    const uint8_t *reset_mode;  /* [C][N] ORC_RESET_*, or NULL (all absolute) */
 } orc_net;
 
 typedef struct orc_sim {
@@ -137,6 +150,23 @@ int orc_check(const orc_net *n)
         for (int a = 0; a < n->num_axons; ++a)
             if (n->axon_type[(size_t)c * n->num_axons + a] >= n->num_types)
                 return ORC_EBADNET;
+    if (n->leak_bits < 2 || n->leak_bits > 32 || n->reset_bits < 2 || n->reset_bits > 32)
+        return ORC_EBADNET;
+    {
+        const int64_t lmax = ((int64_t)1 << (n->leak_bits - 1)) - 1, lmin = -((int64_t)1 << (n->leak_bits - 1));
+        const int64_t rmax = ((int64_t)1 << (n->reset_bits - 1)) - 1, rmin = -((int64_t)1 << (n->reset_bits - 1));
+        const int64_t vmax = ((int64_t)1 << (n->potential_bits - 1)) - 1, vmin = -((int64_t)1 << (n->potential_bits - 1));
+        for (size_t i = 0; i < (size_t)n->num_cores * n->num_neurons; ++i) {
+            if (n->leak[i] < lmin || n->leak[i] > lmax)
+                return ORC_EBADNET;
+            if (n->reset[i] < rmin || n->reset[i] > rmax)
+                return ORC_EBADNET;
+            if (n->floor && (n->floor[i] < vmin || n->floor[i] > vmax))
+                return ORC_EBADNET;
+            if (n->reset_mode && n->reset_mode[i] > ORC_RESET_LINEAR)
+                return ORC_EBADNET;
+        }
+    }
     for (size_t i = 0; i < (size_t)n->num_cores * n->num_neurons; ++i) {
         if (n->dest_kind[i] == ORC_DEST_CORE) {
             int64_t hops = 0;
@@ -258,9 +288,20 @@ int orc_run(orc_sim *s, const uint32_t *ext, int32_t T, int64_t *out_events, int
                 if (u < vmin) u = vmin;
                 if (u >= n->threshold[cj]) {
                     s->spiked[cj] = 1;
-                    s->potential[cj] = n->reset[cj];
+                    if (n->reset_mode && n->reset_mode[cj] == ORC_RESET_LINEAR) {
+                        /* linear reset: keep what exceeded the threshold */
+                        int64_t r = u - n->threshold[cj];
+                        if (r > vmax) r = vmax;
+                        if (r < vmin) r = vmin;
+                        s->potential[cj] = (int32_t)r;
+                    } else {
+                        s->potential[cj] = n->reset[cj];
+                    }
                     s->counters[ORC_EMITTED] += 1;
                 } else {
+                    /* below its floor a neuron that does not fire stops at the floor */
+                    if (n->floor && u < n->floor[cj])
+                        u = n->floor[cj];
                     s->spiked[cj] = 0;
                     s->potential[cj] = (int32_t)u;
                 }

@@ -43,7 +43,8 @@ class _Net(C.Structure):
         ("leak", C.c_void_p), ("threshold", C.c_void_p), ("reset", C.c_void_p),
         ("v_init", C.c_void_p), ("dest_kind", C.c_void_p), ("dest_dx", C.c_void_p),
         ("dest_dy", C.c_void_p), ("dest_axon", C.c_void_p), ("dest_delay", C.c_void_p),
-        ("num_input_cores", C.c_int32), ("input_cores", C.c_void_p)]
+        ("num_input_cores", C.c_int32), ("input_cores", C.c_void_p),
+        ("leak_bits", C.c_int32), ("reset_bits", C.c_int32), ("floor", C.c_void_p), ("reset_mode", C.c_void_p)]
 
 
 def _bind(path: str):
@@ -100,13 +101,22 @@ class _NetHolder:
             dest_delay=np.ascontiguousarray(net.dest_delay, dtype=np.uint8),
             input_cores=np.ascontiguousarray(net.input_cores, dtype=np.int32),
         )
+        floor = getattr(net, "floor", None)
+        mode = getattr(net, "reset_mode", None)
+        if floor is not None:
+            self.arrays["floor"] = np.ascontiguousarray(floor, dtype=np.int32)
+        if mode is not None:
+            self.arrays["reset_mode"] = np.ascontiguousarray(mode, dtype=np.uint8)
         self.c = _Net(net.num_cores, net.num_axons, net.num_neurons, net.num_types,
                       net.weight_bits, net.potential_bits, net.max_delay, net.grid_w, net.grid_h,
                       *[_ptr(self.arrays[k]) for k in ("crossbar", "axon_type", "weight", "leak",
                                                       "threshold", "reset", "v_init", "dest_kind",
                                                       "dest_dx", "dest_dy", "dest_axon",
                                                       "dest_delay")],
-                      len(self.arrays["input_cores"]), _ptr(self.arrays["input_cores"]))
+                      len(self.arrays["input_cores"]), _ptr(self.arrays["input_cores"]),
+                      int(getattr(net, "leak_bits", 32)), int(getattr(net, "reset_bits", 32)),
+                      _ptr(self.arrays["floor"]) if floor is not None else None,
+                      _ptr(self.arrays["reset_mode"]) if mode is not None else None)
         self.C, self.N = net.num_cores, net.num_neurons
 
 

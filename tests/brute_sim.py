@@ -12,7 +12,9 @@ uses): an axon holds a spike at tick t if any packet for (core, axon, t) was
 sent or the external input has it; a neuron's input is the sum, over spiking
 connected axons, of its weight for the axon's type; U = V + input + leak is
 clamped to a signed potential_bits range; the neuron fires iff U >= threshold
-and is then set to its reset value; a spike at t with delay d reaches its
+and is then set to its reset value (or, in linear-reset mode, to U minus the
+threshold, clamped to the range); a neuron that does not fire keeps
+max(U, floor) when it has a floor; a spike at t with delay d reaches its
 destination axon at t + d. Only for tiny cases: it is slow on purpose.
 """
 from __future__ import annotations
@@ -61,9 +63,13 @@ def brute_simulate(net, ext, T, pending=None, V=None, t0=0):
                         counters["events"] += 1
                 u = V[c][n] + total + int(net.leak[c][n])
                 u = min(hi, max(lo, u))
-                if u >= int(net.threshold[c][n]):
-                    V[c][n] = int(net.reset[c][n])
+                theta = int(net.threshold[c][n])
+                if u >= theta:
+                    linear = net.reset_mode is not None and int(net.reset_mode[c][n]) == 1
+                    V[c][n] = min(hi, max(lo, u - theta)) if linear else int(net.reset[c][n])
                     fired.append((c, n))
+                elif net.floor is not None:
+                    V[c][n] = max(u, int(net.floor[c][n]))
                 else:
                     V[c][n] = u
         counters["emitted"] += len(fired)

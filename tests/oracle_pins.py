@@ -58,7 +58,7 @@ def parse_golden(name):
 def make_net(C, A, N, G=1, grid_w=None, conn=None, axon_type=None, weight=None, leak=0,
              threshold=1 << 30, reset=0, v_init=0, dest_kind=0, dest_dx=0, dest_dy=0,
              dest_axon=0, dest_delay=0, potential_bits=32, max_delay=4, input_cores=(0,),
-             weight_bits=9):
+             weight_bits=9, floor=None, reset_mode=None, leak_bits=32, reset_bits=32):
     grid_w = grid_w or C
     full = lambda v, shape, dt: np.broadcast_to(np.asarray(v, dtype=dt), shape).copy()
     conn = np.ones((C, A, N), bool) if conn is None else np.asarray(conn, bool)
@@ -71,7 +71,9 @@ def make_net(C, A, N, G=1, grid_w=None, conn=None, axon_type=None, weight=None, 
                  full(dest_kind, (C, N), np.uint8), full(dest_dx, (C, N), np.int16),
                  full(dest_dy, (C, N), np.int16), full(dest_axon, (C, N), np.uint16),
                  full(dest_delay, (C, N), np.uint8),
-                 np.asarray(input_cores, np.int32)).contiguous()
+                 np.asarray(input_cores, np.int32), leak_bits=leak_bits, reset_bits=reset_bits,
+                 floor=None if floor is None else full(floor, (C, N), np.int32),
+                 reset_mode=None if reset_mode is None else full(reset_mode, (C, N), np.uint8)).contiguous()
 
 
 def ext_from_ticks(T, n_in, A, spikes):
@@ -88,9 +90,11 @@ def run1(net, ext, T, lib=None, trace=False):
     return ev, sim.potentials(), sim.counters(), st, vt, sim
 
 
-def single_neuron(weight, leak, threshold, reset, v_init, potential_bits, every, T):
+def single_neuron(weight, leak, threshold, reset, v_init, potential_bits, every, T, floor=None,
+                  reset_mode=None):
     net = make_net(1, 1, 1, G=1, weight=weight, leak=leak, threshold=threshold, reset=reset,
-                   v_init=v_init, potential_bits=potential_bits, dest_kind=W.DEST_OUT)
+                   v_init=v_init, potential_bits=potential_bits, dest_kind=W.DEST_OUT, floor=floor,
+                   reset_mode=reset_mode)
     ext = ext_from_ticks(T, 1, 1, [(t, 0, 0) for t in range(T)] if every else [])
     return net, ext
 
@@ -121,6 +125,89 @@ def pin_single_neuron_cases(lib=None):
         assert got == want, f"{name}: spikes {got} != {want}"
         assert int(v[0, 0]) == int(c["v_final"]), f"{name}: V {int(v[0, 0])} != {c['v_final']}"
         assert cnt["out"] == len(want) and cnt["emitted"] == len(want), name
+
+
+def pin_neuron_model_cases(lib=None):
+    """Linear reset and the potential floor (tests/golden/neuron_model_cases.txt)."""
+    for name, c in parse_golden("neuron_model_cases.txt").items():
+        T = int(c["ticks"])
+        mode = {"absolute": 0, "linear": 1}[c.get("reset_mode", "absolute")]
+        net, ext = single_neuron(int(c["weight"]), int(c["leak"]), int(c["threshold"]),
+                                 int(c["reset"]), int(c["v_init"]), int(c["potential_bits"]),
+                                 c["input"] == "every", T, floor=int(c["floor"]) if "floor" in c else None,
+                                 reset_mode=mode)
+        ev, v, cnt, *_ = run1(net, ext, T, lib)
+        want = [int(x) for x in c["spikes"].split()]
+        got = [int(t) for t in ev[:, 0]]
+        assert got == want, f"{name}: spikes {got} != {want}"
+        assert int(v[0, 0]) == int(c["v_final"]), f"{name}: V {int(v[0, 0])} != {c['v_final']}"
+
+
+def pin_linear_reset_sweep(lib=None, n=60, seed=8):
+    """Linear reset under constant drive u: with 0 < u < threshold the neuron
+    fires whenever v_init + (t+1) u passes a multiple of the threshold and
+    ends at (v_init + T u) mod threshold; with u >= threshold it fires every
+    tick and gains u - threshold per tick."""
+    r = np.random.default_rng(seed)
+    for i in range(n):
+        w = int(r.integers(1, 256))
+        leak = int(r.integers(-w + 1, 64))
+        u = w + leak
+        if i % 4 == 3:
+            thr = int(r.integers(1, u + 1))
+            v0 = int(r.integers(0, 50))
+        else:
+            thr = int(r.integers(u + 1, 3000))
+            v0 = int(r.integers(0, thr))
+        T = int(r.integers(1, 40))
+        net, ext = single_neuron(w, leak, thr, 0, v0, 32, True, T, reset_mode=1)
+        ev, v, *_ = run1(net, ext, T, lib)
+        if u < thr:
+            spikes = [t for t in range(T) if (v0 + (t + 1) * u) // thr > (v0 + t * u) // thr]
+            vf = (v0 + T * u) % thr
+        else:
+            spikes, vf = list(range(T)), v0 + T * (u - thr)
+        assert [int(t) for t in ev[:, 0]] == spikes, (w, leak, thr, v0, T)
+        assert int(v[0, 0]) == vf, (w, leak, thr, v0, T, int(v[0, 0]), vf)
+
+
+def pin_floor_sweep(lib=None, n=60, seed=9):
+    """Negative constant drive u with a floor F <= v_init < threshold: the
+    neuron never fires and ends at max(F, v_init + T u)."""
+    r = np.random.default_rng(seed)
+    for _ in range(n):
+        w = int(r.integers(0, 100))
+        leak = int(r.integers(-300, -w))
+        u = w + leak
+        F = int(r.integers(-5000, 1))
+        thr = int(r.integers(1, 1000))
+        v0 = int(r.integers(F, thr))
+        T = int(r.integers(1, 40))
+        net, ext = single_neuron(w, leak, thr, 0, v0, 32, True, T, floor=F)
+        ev, v, *_ = run1(net, ext, T, lib)
+        assert len(ev) == 0
+        assert int(v[0, 0]) == max(F, v0 + T * u), (w, leak, F, thr, v0, T)
+
+
+def pin_value_widths(lib=None):
+    """Leaks and reset potentials are signed values of leak_bits and
+    reset_bits bits, floors lie in the potential range, reset modes are 0 or
+    1: the oracle rejects a description with a value just outside its range
+    and accepts the values at the ends of it."""
+    lib = lib if lib is not None else O._load()
+    for bits in (2, 4, 9, 17):
+        lo, hi = -(1 << (bits - 1)), (1 << (bits - 1)) - 1
+        for v, ok in ((lo, True), (hi, True), (lo - 1, False), (hi + 1, False)):
+            assert (O.check(make_net(1, 1, 2, leak=[[0, v]], leak_bits=bits), lib) == 0) == ok, ("leak", bits, v)
+            assert (O.check(make_net(1, 1, 2, reset=[[0, v]], reset_bits=bits), lib) == 0) == ok, ("reset", bits, v)
+    for P in (8, 12):
+        lo, hi = -(1 << (P - 1)), (1 << (P - 1)) - 1
+        for v, ok in ((lo, True), (hi, True), (lo - 1, False), (hi + 1, False)):
+            assert (O.check(make_net(1, 1, 2, floor=[[0, v]], potential_bits=P), lib) == 0) == ok, ("floor", P, v)
+    for m, ok in ((0, True), (1, True), (2, False)):
+        assert (O.check(make_net(1, 1, 2, reset_mode=[[0, m]]), lib) == 0) == ok, ("reset_mode", m)
+    assert O.check(make_net(1, 1, 2, leak_bits=1), lib) != 0
+    assert O.check(make_net(1, 1, 2, reset_bits=33), lib) != 0
 
 
 def pin_closed_form_sweep(lib=None, n=60, seed=1):
@@ -227,7 +314,9 @@ def _tiny_random_net(r, seed):
                        leak_range=(-3, 3), thr_range=(1, max(2, min(lim, 2 * wmax))),
                        reset_range=(-2, 1), vinit_range=(-2, 2),
                        input_cores=sorted(set(r.integers(0, C, size=int(r.integers(1, C + 1))).tolist())),
-                       config_id=500)
+                       config_id=500,
+                       floor_range=(-6, 0) if r.random() < 0.3 else None,
+                       linear_frac=float(r.choice([0.0, 0.0, 0.5, 1.0])))
     return net
 
 
@@ -351,7 +440,8 @@ def pin_relabel(lib=None, seed=7):
     assert [tuple(int(x) for x in e) for e in ev2] == mapped
 
 
-ALL_PINS = [pin_single_neuron_cases, pin_closed_form_sweep, pin_axon_types,
+ALL_PINS = [pin_single_neuron_cases, pin_neuron_model_cases, pin_linear_reset_sweep, pin_floor_sweep,
+            pin_value_widths, pin_closed_form_sweep, pin_axon_types,
             pin_integration_matmul, pin_delay_delivery, pin_or_merge,
             pin_brute_force_random, pin_brute_force_exhaustive, pin_invariants,
             pin_resume_and_prefix, pin_relabel]

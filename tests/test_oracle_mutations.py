@@ -41,6 +41,16 @@ MUTATIONS = [
      "int row = (s->curr[dest] + n->dest_delay[cj]) % s->rows;", "int row = s->curr[dest];"),
     ("saturate_at_p_minus_1", "const int64_t vmax = ((int64_t)1 << (n->potential_bits - 1)) - 1;",
      "const int64_t vmax = ((int64_t)1 << (n->potential_bits - 2)) - 1;"),
+    ("linear_reset_absolute", "int64_t r = u - n->threshold[cj];", "int64_t r = n->reset[cj];"),
+    ("linear_reset_unclamped", "if (r > vmax) r = vmax;", ""),
+    ("linear_reset_to_zero", "int64_t r = u - n->threshold[cj];", "int64_t r = 0;"),
+    ("no_floor", "if (n->floor && u < n->floor[cj])", "if (0)"),
+    ("floor_as_ceiling", "if (n->floor && u < n->floor[cj])", "if (n->floor && u > n->floor[cj])"),
+    ("floor_on_reset_value", "                        s->potential[cj] = n->reset[cj];\n",
+     "                        s->potential[cj] = (n->floor && n->reset[cj] < n->floor[cj]) ? n->floor[cj] : n->reset[cj];\n"),
+    ("leak_width_off_by_one", "const int64_t lmax = ((int64_t)1 << (n->leak_bits - 1)) - 1,",
+     "const int64_t lmax = ((int64_t)1 << (n->leak_bits - 1)),"),
+    ("reset_width_unchecked", "if (n->reset[i] < rmin || n->reset[i] > rmax)", "if (0)"),
 ]
 
 
