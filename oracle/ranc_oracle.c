@@ -20,8 +20,10 @@
  *      per neuron selected by axon type; Algorithm 1 neuron loop and "additional
  *      computation / checks");
  *   4. router, every core and neuron that spiked: build the packet, move it one
- *      mesh hop at a time (east/west first, then north/south) to its
- *      destination core, and set the destination axon's bit in that core's
+ *      mesh hop at a time (along x first, then along y) to its
+ *      destination core, counting the mesh link each hop takes (Fig. 2: a
+ *      packet reaches its core through the routers of the cores between), and
+ *      set the destination axon's bit in that core's
  *      scheduler row at the packet's tick offset (Sec. II, Sec. III-D); a
  *      neuron whose destination is the output bus records (tick, core, neuron)
  *      instead (Sec. IV, output file).
@@ -65,6 +67,9 @@ enum { ORC_DEST_NONE = 0, ORC_DEST_CORE = 1, ORC_DEST_OUT = 2 };
 
 enum { ORC_RESET_ABSOLUTE = 0, ORC_RESET_LINEAR = 1 };
 
+/* Directions of the mesh link a hop takes, out of the core it leaves. */
+enum { ORC_LINK_XPLUS = 0, ORC_LINK_XMINUS, ORC_LINK_YPLUS, ORC_LINK_YMINUS, ORC_NLINKS };
+
 typedef struct orc_net {
     int32_t num_cores, num_axons, num_neurons, num_types;
     int32_t weight_bits, potential_bits, max_delay, grid_w, grid_h;
@@ -92,6 +97,7 @@ typedef struct orc_sim {
     int32_t *curr;         /* [C] row of the current tick */
     uint8_t *spiked;       /* [C][N] spike flags of the current tick */
     int32_t *active;       /* [A] axons of the core being integrated that hold a spike */
+    int64_t *links;        /* [C][ORC_NLINKS] packets that left core c over each of its links */
     int64_t counters[ORC_NCOUNTERS];
 } orc_sim;
 
@@ -115,12 +121,15 @@ static uint8_t *sram_row(orc_sim *s, int c, int row)
 }
 
 /* Move a packet hop by hop across the mesh; returns the destination core or
- * -1 if it would leave the grid. */
-static int route_hops(const orc_net *n, int core, int dx, int dy, int64_t *hops)
+ * -1 if it would leave the grid. Each hop is counted in *hops and, if links
+ * is not NULL, on the link it takes out of the core it leaves. */
+static int route_hops(const orc_net *n, int core, int dx, int dy, int64_t *hops, int64_t *links)
 {
     int x = core % n->grid_w, y = core / n->grid_w;
     while (dx != 0) {
-        int step = dx > 0 ? 1 : -1;   /* east or west */
+        int step = dx > 0 ? 1 : -1;   /* along x */
+        if (links)
+            ++links[((size_t)y * n->grid_w + x) * ORC_NLINKS + (step > 0 ? ORC_LINK_XPLUS : ORC_LINK_XMINUS)];
         x += step;
         dx -= step;
         ++*hops;
@@ -128,7 +137,9 @@ static int route_hops(const orc_net *n, int core, int dx, int dy, int64_t *hops)
             return -1;
     }
     while (dy != 0) {
-        int step = dy > 0 ? 1 : -1;   /* north or south */
+        int step = dy > 0 ? 1 : -1;   /* along y */
+        if (links)
+            ++links[((size_t)y * n->grid_w + x) * ORC_NLINKS + (step > 0 ? ORC_LINK_YPLUS : ORC_LINK_YMINUS)];
         y += step;
         dy -= step;
         ++*hops;
@@ -175,7 +186,7 @@ int orc_check(const orc_net *n)
                 return ORC_EBADNET;
             if (n->dest_axon[i] >= n->num_axons)
                 return ORC_EBADNET;
-            if (route_hops(n, c, n->dest_dx[i], n->dest_dy[i], &hops) < 0)
+            if (route_hops(n, c, n->dest_dx[i], n->dest_dy[i], &hops, NULL) < 0)
                 return ORC_EROUTE;
         }
     }
@@ -200,8 +211,9 @@ orc_sim *orc_new(const orc_net *n)
     s->sram = (uint8_t *)calloc((size_t)n->num_cores * s->rows * n->num_axons, 1);
     s->curr = (int32_t *)malloc((size_t)n->num_cores * sizeof(int32_t));
     s->active = (int32_t *)malloc((size_t)n->num_axons * sizeof(int32_t));
-    if (!s->potential || !s->spiked || !s->sram || !s->curr || !s->active) {
-        free(s->potential); free(s->spiked); free(s->sram); free(s->curr); free(s->active); free(s);
+    s->links = (int64_t *)calloc((size_t)n->num_cores * ORC_NLINKS, sizeof(int64_t));
+    if (!s->potential || !s->spiked || !s->sram || !s->curr || !s->active || !s->links) {
+        free(s->potential); free(s->spiked); free(s->sram); free(s->curr); free(s->active); free(s->links); free(s);
         return NULL;
     }
     memcpy(s->potential, n->v_init, cn * sizeof(int32_t));
@@ -217,7 +229,7 @@ void orc_free(orc_sim *s)
 {
     if (!s)
         return;
-    free(s->potential); free(s->spiked); free(s->sram); free(s->curr); free(s->active); free(s);
+    free(s->potential); free(s->spiked); free(s->sram); free(s->curr); free(s->active); free(s->links); free(s);
 }
 
 /*
@@ -322,7 +334,7 @@ int orc_run(orc_sim *s, const uint32_t *ext, int32_t T, int64_t *out_events, int
                     ++count;
                     s->counters[ORC_OUT] += 1;
                 } else if (n->dest_kind[cj] == ORC_DEST_CORE) {
-                    int dest = route_hops(n, c, n->dest_dx[cj], n->dest_dy[cj], &s->counters[ORC_HOPS]);
+                    int dest = route_hops(n, c, n->dest_dx[cj], n->dest_dy[cj], &s->counters[ORC_HOPS], s->links);
                     if (dest < 0)
                         return ORC_EROUTE;
                     int row = (s->curr[dest] + n->dest_delay[cj]) % s->rows;
@@ -349,6 +361,12 @@ void orc_potentials(const orc_sim *s, int32_t *out)
 void orc_counters(const orc_sim *s, int64_t *out)
 {
     memcpy(out, s->counters, sizeof(s->counters));
+}
+
+/* Packets per mesh link since the start: out[c][d], d = +x, -x, +y, -y. */
+void orc_links(const orc_sim *s, int64_t *out)
+{
+    memcpy(out, s->links, (size_t)s->net.num_cores * ORC_NLINKS * sizeof(int64_t));
 }
 
 int64_t orc_tick(const orc_sim *s)

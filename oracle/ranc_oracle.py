@@ -59,6 +59,7 @@ def _bind(path: str):
                             C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]
     lib.orc_potentials.argtypes = [C.c_void_p, C.c_void_p]
     lib.orc_counters.argtypes = [C.c_void_p, C.c_void_p]
+    lib.orc_links.argtypes = [C.c_void_p, C.c_void_p]
     lib.orc_tick.restype = C.c_int64
     lib.orc_tick.argtypes = [C.c_void_p]
     return lib
@@ -188,6 +189,13 @@ class OracleSim:
         self._lib.orc_potentials(self._p, _ptr(out))
         return out
 
+    def links(self) -> np.ndarray:
+        """Packets per mesh link since the start, int64 [C, 4]: out of core c
+        towards +x, -x, +y, -y."""
+        out = np.zeros((self._h.C, 4), dtype=np.int64)
+        self._lib.orc_links(self._p, _ptr(out))
+        return out
+
     def counters(self) -> dict:
         out = np.zeros(len(COUNTER_NAMES), dtype=np.int64)
         self._lib.orc_counters(self._p, _ptr(out))
@@ -216,7 +224,7 @@ def simulate(net, inputs: np.ndarray | None, T: int, samples=None, threads: int 
         sim = OracleSim(net, lib)
         ext = inputs[s, :T] if inputs is not None else None
         ev, st, vt = sim.run(ext, T, trace=trace)
-        r = dict(sample=s, events=ev, v=sim.potentials(), counters=sim.counters())
+        r = dict(sample=s, events=ev, v=sim.potentials(), counters=sim.counters(), links=sim.links())
         if trace:
             r["spikes"], r["vtrace"] = st, vt
         return r

@@ -41,7 +41,7 @@ def brute_simulate(net, ext, T, pending=None, V=None, t0=0):
         V = [[int(net.v_init[c][n]) for n in range(N)] for c in range(Cn)]
     if pending is None:
         pending = defaultdict(set)
-    counters = dict(emitted=0, routed=0, delivered=0, out=0, events=0)
+    counters = dict(emitted=0, routed=0, delivered=0, out=0, events=0, links=[0] * (4 * Cn))
     events = []
     per_tick = []
     for t in range(t0, t0 + T):
@@ -82,6 +82,14 @@ def brute_simulate(net, ext, T, pending=None, V=None, t0=0):
                 x = c % gw + int(net.dest_dx[c][n])
                 y = c // gw + int(net.dest_dy[c][n])
                 assert 0 <= x < gw and 0 <= y < net.grid_h
+                # the links of the x-then-y route: x from the source column to
+                # the destination column on the source row, then y along the
+                # destination column; each hop counted at the core it leaves
+                sx, sy = c % gw, c // gw
+                for xi in (range(sx, x) if x > sx else range(sx, x, -1)):
+                    counters["links"][4 * (sy * gw + xi) + (0 if x > sx else 1)] += 1
+                for yi in (range(sy, y) if y > sy else range(sy, y, -1)):
+                    counters["links"][4 * (yi * gw + x) + (2 if y > sy else 3)] += 1
                 pending[t + int(net.dest_delay[c][n])].add((y * gw + x, int(net.dest_axon[c][n])))
                 counters["routed"] += 1
         per_tick.append(fired)

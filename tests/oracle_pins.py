@@ -279,9 +279,37 @@ def pin_delay_delivery(lib=None):
                    dest_kind=[[W.DEST_CORE], [W.DEST_NONE], [W.DEST_OUT], [W.DEST_CORE]],
                    dest_dx=[[1], [0], [0], [-1]], dest_dy=[[1], [0], [0], [0]],
                    dest_delay=[[2], [0], [0], [3]], max_delay=3)
-    ev, _, cnt, *_ = run1(net, ext_from_ticks(8, 1, 1, [(0, 0, 0)]), 8, lib)
+    ev, _, cnt, _, _, sim = run1(net, ext_from_ticks(8, 1, 1, [(0, 0, 0)]), 8, lib)
     assert _events_str(ev) == g["two_hop"]["out"], _events_str(ev)
     assert cnt["hops"] == int(g["two_hop"]["hops"])
+    assert np.array_equal(sim.links(), _links_of(g["two_hop"]["links"], 4)), sim.links().tolist()
+
+
+def _links_of(text, C):
+    out = np.zeros((C, 4), np.int64)
+    for item in text.split(";"):
+        c, d, k = (int(x) for x in item.split())
+        out[c, d] = k
+    return out
+
+
+def pin_link_counts(lib=None):
+    """Packets per mesh link on the XY route (Sec. III-D, Fig. 2: packets hop
+    through the routers of the cores between source and destination)."""
+    g = parse_golden("routing_cases.txt")["ping_pong"]
+    dk = np.zeros((12, 1), np.uint8)
+    dx = np.zeros((12, 1), np.int16)
+    dy = np.zeros((12, 1), np.int16)
+    dd = np.zeros((12, 1), np.uint8)
+    dk[0], dx[0], dy[0], dd[0] = W.DEST_CORE, 3, 2, 1
+    dk[11], dx[11], dy[11], dd[11] = W.DEST_CORE, -3, -2, 1
+    net = make_net(12, 1, 1, G=1, grid_w=4, weight=10, threshold=10, dest_kind=dk, dest_dx=dx, dest_dy=dy,
+                   dest_delay=dd, max_delay=1)
+    _, _, cnt, st, _, sim = run1(net, ext_from_ticks(6, 1, 1, [(0, 0, 0)]), 6, lib, trace=True)
+    assert [int(t) for t in np.nonzero(st[:, 0, 0])[0]] == [0, 2, 4]
+    assert [int(t) for t in np.nonzero(st[:, 11, 0])[0]] == [1, 3, 5]
+    assert cnt["hops"] == int(g["hops"])
+    assert np.array_equal(sim.links(), _links_of(g["links"], 12)), sim.links().tolist()
 
 
 def pin_or_merge(lib=None):
@@ -321,8 +349,10 @@ def _tiny_random_net(r, seed):
 
 
 def _compare_with_brute(net, ext, T, lib):
-    ev, v, cnt, st, vt, _ = run1(net, ext, T, lib, trace=True)
+    ev, v, cnt, st, vt, sim = run1(net, ext, T, lib, trace=True)
     bev, bV, bcnt, _, per_tick = brute_simulate(net, ext, T)
+    assert np.array_equal(sim.links(), np.array(bcnt["links"], np.int64).reshape(-1, 4)), "link counts differ"
+    assert cnt["hops"] == sum(bcnt["links"])
     assert [tuple(int(x) for x in e) for e in ev] == bev, "output spikes differ"
     assert np.array_equal(v, np.array(bV, dtype=np.int64).astype(np.int32)), "potentials differ"
     for k in ("emitted", "routed", "delivered", "out", "events"):
@@ -391,6 +421,12 @@ def pin_invariants(lib=None, seed=5):
         (st[t].astype(bool) & (kind == W.DEST_CORE)).astype(np.int64).ravel()
         @ (np.abs(net.dest_dx.astype(np.int64)) + np.abs(net.dest_dy.astype(np.int64))).ravel()
         for t in range(T)))
+    links = O.OracleSim(net, lib)
+    links.run(ext, T)
+    assert int(links.links().sum()) == cnt["hops"]
+    # every hop leaves a core towards a neighbour inside the mesh
+    lk = links.links().reshape(net.grid_h, net.grid_w, 4)
+    assert not lk[:, -1, 0].any() and not lk[:, 0, 1].any() and not lk[-1, :, 2].any() and not lk[0, :, 3].any()
     # silence without drive: no input, leak <= 0, V0 <= 0, threshold > 0
     quiet = W.random_net(30_001, 4, 32, 32, 2, leak_range=(-5, 0), thr_range=(1, 100),
                          vinit_range=(-50, 0), config_id=503)
@@ -442,6 +478,6 @@ def pin_relabel(lib=None, seed=7):
 
 ALL_PINS = [pin_single_neuron_cases, pin_neuron_model_cases, pin_linear_reset_sweep, pin_floor_sweep,
             pin_value_widths, pin_closed_form_sweep, pin_axon_types,
-            pin_integration_matmul, pin_delay_delivery, pin_or_merge,
+            pin_integration_matmul, pin_delay_delivery, pin_link_counts, pin_or_merge,
             pin_brute_force_random, pin_brute_force_exhaustive, pin_invariants,
             pin_resume_and_prefix, pin_relabel]

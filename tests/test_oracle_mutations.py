@@ -10,6 +10,10 @@ import pytest
 from oracle import ranc_oracle as O
 from tests import oracle_pins as P
 
+_SRC = O.source_text()
+XBLOCK = _SRC[_SRC.index("    while (dx != 0) {"):_SRC.index("    while (dy != 0) {")]
+YBLOCK = _SRC[_SRC.index("    while (dy != 0) {"):_SRC.index("    return y * n->grid_w + x;\n}")]
+
 MUTATIONS = [
     ("strict_threshold", "if (u >= n->threshold[cj])", "if (u > n->threshold[cj])"),
     ("no_leak", "+ acc + n->leak[cj];", "+ acc;"),
@@ -29,10 +33,10 @@ MUTATIONS = [
     ("toggle_merge", "sram_row(s, dest, row)[n->dest_axon[cj]] = 1;",
      "sram_row(s, dest, row)[n->dest_axon[cj]] ^= 1;"),
     ("no_row_clear", "memset(sram_row(s, c, s->curr[c]), 0, (size_t)A);", ""),
-    ("swap_dx_dy", "route_hops(n, c, n->dest_dx[cj], n->dest_dy[cj], &s->counters[ORC_HOPS]);",
-     "route_hops(n, c, n->dest_dy[cj], n->dest_dx[cj], &s->counters[ORC_HOPS]);"),
-    ("wrong_dy_sign", "int step = dy > 0 ? 1 : -1;   /* north or south */",
-     "int step = dy > 0 ? -1 : 1;   /* north or south */"),
+    ("swap_dx_dy", "route_hops(n, c, n->dest_dx[cj], n->dest_dy[cj], &s->counters[ORC_HOPS], s->links);",
+     "route_hops(n, c, n->dest_dy[cj], n->dest_dx[cj], &s->counters[ORC_HOPS], s->links);"),
+    ("wrong_dy_sign", "int step = dy > 0 ? 1 : -1;   /* along y */",
+     "int step = dy > 0 ? -1 : 1;   /* along y */"),
     ("input_next_tick", "if (input_bit(ext, n, k, i, a))", "if (k > 0 && input_bit(ext, n, k - 1, i, a))"),
     ("input_wrong_core", "int c = n->input_cores[i];", "int c = i;"),
     ("dest_axon_off_by_one", "sram_row(s, dest, row)[n->dest_axon[cj]] = 1;",
@@ -51,6 +55,12 @@ MUTATIONS = [
     ("leak_width_off_by_one", "const int64_t lmax = ((int64_t)1 << (n->leak_bits - 1)) - 1,",
      "const int64_t lmax = ((int64_t)1 << (n->leak_bits - 1)),"),
     ("reset_width_unchecked", "if (n->reset[i] < rmin || n->reset[i] > rmax)", "if (0)"),
+    ("route_y_before_x", XBLOCK + YBLOCK, YBLOCK + XBLOCK),
+    ("link_counted_at_next_core",
+     "            ++links[((size_t)y * n->grid_w + x) * ORC_NLINKS + (step > 0 ? ORC_LINK_XPLUS : ORC_LINK_XMINUS)];\n        x += step;",
+     "            ++links[((size_t)y * n->grid_w + x + step) * ORC_NLINKS + (step > 0 ? ORC_LINK_XPLUS : ORC_LINK_XMINUS)];\n        x += step;"),
+    ("x_link_directions_swapped", "(step > 0 ? ORC_LINK_XPLUS : ORC_LINK_XMINUS)", "(step > 0 ? ORC_LINK_XMINUS : ORC_LINK_XPLUS)"),
+    ("y_link_as_x_link", "(step > 0 ? ORC_LINK_YPLUS : ORC_LINK_YMINUS)", "(step > 0 ? ORC_LINK_XPLUS : ORC_LINK_XMINUS)"),
 ]
 
 
