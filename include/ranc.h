@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define RANC_ABI_VERSION 1u
+#define RANC_ABI_VERSION 2u
 
 typedef enum ranc_status {
     RANC_OK = 0,
@@ -48,6 +48,15 @@ typedef enum ranc_status {
 
 /* Destination kinds of a neuron's spikes. */
 enum { RANC_DEST_NONE = 0, RANC_DEST_CORE = 1, RANC_DEST_OUT = 2 };
+
+/* What a spike does to the firing neuron's potential (Sec. II lists resetting
+ * the potential among the per-tick neuron operations; Sec. I and Sec. V make
+ * the reset potential's width a configurable axis). */
+enum {
+    RANC_RESET_ABSOLUTE = 0,  /* the potential becomes the neuron's reset value */
+    RANC_RESET_LINEAR = 1     /* the potential becomes U - threshold (what exceeded the
+                                 threshold is kept), clamped to the potential range */
+};
 
 /* Integration paths (fixed at load time; they differ in device data layout). */
 enum {
@@ -85,6 +94,10 @@ enum {
  * Supported shapes: num_axons, num_neurons in {64, 128, 256, 512};
  * num_types in {1, 2, 4, 8}; 2 <= weight_bits <= 9; 2 <= potential_bits <= 32;
  * 1 <= max_delay <= 15; num_cores * num_neurons <= 2^23.
+ * The neuron-model widths and options at the end of the struct (leak_bits,
+ * reset_bits, floor, reset_mode) cover the design space of Sec. I and Sec. V
+ * (configurable widths of weight, leak, potential and reset); zero / NULL
+ * keeps the defaults (32-bit leak and reset, no floor, absolute reset).
  */
 typedef struct ranc_net_desc {
     uint32_t abi_version;      /* must be RANC_ABI_VERSION */
@@ -110,6 +123,14 @@ typedef struct ranc_net_desc {
     const uint8_t *dest_delay; /* [C][N]: tick offset in [1, max_delay] (CORE only) */
     int32_t num_input_cores;   /* C_in >= 0 */
     const int32_t *input_cores;/* [C_in]: distinct cores that take external input */
+    int32_t leak_bits;         /* leaks are signed leak_bits-bit values, 2..32 (0: 32) */
+    int32_t reset_bits;        /* reset values are signed reset_bits-bit values, 2..32 (0: 32);
+                                  they must also lie in the potential range */
+    const int32_t *floor;      /* [C][N] or NULL (none): a neuron that does not fire and whose
+                                  saturated potential U lies below its floor keeps the floor
+                                  instead (a negative threshold); within the potential range;
+                                  not applied to the value a spike resets to */
+    const uint8_t *reset_mode; /* [C][N] RANC_RESET_*, or NULL (all absolute) */
 } ranc_net_desc;
 
 /* An output-bus spike. */
@@ -146,6 +167,11 @@ ranc_status ranc_workspace_bytes(const ranc_net_desc *desc, int32_t num_samples,
                                  int32_t max_ticks_per_call, int32_t path, size_t *bytes);
 
 /*
+ * Load a network (Sec. II: cores of axons, neurons, a binary crossbar and
+ * per-neuron weights selected by axon type, leak, threshold and reset;
+ * Sec. III-B: the per-core SRAM that holds these parameters and each
+ * neuron's destination packet fields; Algorithm 1: the initial state before
+ * the tick loop).
  * Validate the description, lay it out in the workspace (a device buffer of
  * at least ranc_workspace_bytes bytes, 256-byte aligned, owned by the caller
  * and kept alive until ranc_free), upload it on `stream`, and set every
@@ -158,6 +184,12 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples,
                               size_t workspace_bytes, void *stream, ranc_net **out);
 
 /*
+ * The tick loop of Algorithm 1, num_ticks iterations: per tick, scheduler
+ * rows advance and the tick's external input spikes are written; every
+ * neuron integrates its spiking connected axons' weights, leaks, compares
+ * with its threshold and resets (Sec. II, Sec. III-C); every spike is routed
+ * to its destination (core, axon) at its tick offset (Sec. III-D, III-E) or
+ * to the output bus (Sec. IV).
  * Advance every instance of each of the num_nets networks by num_ticks
  * ticks (1 <= num_ticks <= max_ticks_per_call). inputs[i] (may be NULL for
  * no external input) holds network i's external spikes as
@@ -186,7 +218,9 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets,
                            void *stream);
 
 /*
- * Output-bus spikes of one sample with tick_begin <= tick < tick_end, sorted
+ * The output file of Sec. IV (the spikes the network sends to its output
+ * bus, compared one to one between the serial and the GPU simulator):
+ * output-bus spikes of one sample with tick_begin <= tick < tick_end, sorted
  * by (tick, core, neuron). Ticks must lie in the retained window: the last
  * max_ticks_per_call ticks run (else RANC_ESTATE). If capacity is too small,
  * *count receives the required number and RANC_ETRUNC is returned.

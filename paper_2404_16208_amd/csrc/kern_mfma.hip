@@ -117,11 +117,13 @@ template <int A_, int N_> struct MfmaLds {
 // swap the partial sums of one group through LDS (`xch`): wave stg finishes
 // group stg with in = lo + 128 * hi. The LDS arrays come from the calling
 // kernel, so several shapes can share one kernel's LDS.
-// CLAMP: potentials narrower than 32 bits are clamped to [vmin, vmax] after
-// the saturating 32-bit add (with 32-bit potentials the add alone is exact).
+// EXT: the extended potential update (lif_update): potentials narrower than
+// 32 bits are clamped to [vmin, vmax] after the saturating 32-bit add (with
+// 32-bit potentials the add alone is exact), and the floor and linear-reset
+// options apply; without them the epilogue is the add, compare and select.
 // HBUF: history words are collected in `hbuf` and written in runs of HB
 // words per neuron; otherwise each tile's word is stored at once.
-template <int A_, int N_, bool TWO, bool CLAMP, bool HBUF>
+template <int A_, int N_, bool TWO, bool EXT, bool HBUF>
 __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickArgs &ta, int spw, int bid,
                                                     typename MfmaLds<A_, N_>::ATile *a_lds,
                                                     typename MfmaLds<A_, N_>::VTile *v_lds,
@@ -182,6 +184,12 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     const size_t cj = (size_t)c * n.N + slice * N_ + neuron;
     const int32_t lk = n.leak[cj], th = n.thr[cj], rs = n.rst[cj];
     const int32_t vmin = n.vmin, vmax = n.vmax;
+    int32_t fl = vmin;
+    bool lin = false;
+    if constexpr (EXT) {
+        fl = n.floor[cj];
+        lin = (n.linmask[cj >> 5] >> (cj & 31)) & 1u;
+    }
     const int oi = n.outidx[cj];
     const uint32_t cm32 = n.coremask[(size_t)c * n.NW + nbc];
     const uint32_t om32 = n.outmask[(size_t)c * n.NW + nbc];
@@ -475,10 +483,13 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
 #pragma unroll
                 for (int r = 15; r >= 0; --r) {
                     int32_t u = __builtin_elementwise_add_sat(vold[t][r >> 2][r & 3], in[r]);
-                    if constexpr (CLAMP)
+                    if constexpr (EXT)
                         u = min(max(u, vmin), vmax);
                     const bool fire = u >= th;
-                    vnew[t][r >> 2][r & 3] = fire ? rs : u;
+                    if constexpr (EXT)
+                        vnew[t][r >> 2][r & 3] = fire ? lif_reset(u, th, rs, vmax, lin) : max(u, fl);
+                    else
+                        vnew[t][r >> 2][r & 3] = fire ? rs : u;
                     hb = hb + hb + (uint32_t)fire;
                 }
                 // samples past the end never fire (their potentials are never read)
@@ -557,10 +568,13 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
                 for (int r = 15; r >= 0; --r) {
                     const int32_t in_leak = TWO ? acc_lo[r] + acc_hi[r] * 128 : acc_lo[r];
                     int32_t u = __builtin_elementwise_add_sat(vold[t][r >> 2][r & 3], in_leak);
-                    if constexpr (CLAMP)
+                    if constexpr (EXT)
                         u = min(max(u, vmin), vmax);
                     const bool fire = u >= th;
-                    vnew[t][r >> 2][r & 3] = fire ? rs : u;
+                    if constexpr (EXT)
+                        vnew[t][r >> 2][r & 3] = fire ? lif_reset(u, th, rs, vmax, lin) : max(u, fl);
+                    else
+                        vnew[t][r >> 2][r & 3] = fire ? rs : u;
                     hb = hb + hb + (uint32_t)fire;
                 }
                 // samples past the end never fire (their potentials are never read)
@@ -595,7 +609,7 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     }
 }
 
-template <int A_, int N_, bool TWO, bool CLAMP>
+template <int A_, int N_, bool TWO, bool EXT>
 __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, int spw)
 {
     typedef MfmaLds<A_, N_> L;
@@ -605,7 +619,7 @@ __global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, i
     __shared__ typename L::HBuf hbuf[1];
     __shared__ int32_t xch_raw[TWO && A_ == 512 ? sizeof(typename L::Xch) / 4 : 1];
     __shared__ unsigned s_cnt[2][MFMA_SPW_MAX];
-    integrate_mfma_unit<A_, N_, TWO, CLAMP, true>(n, ta, spw, blockIdx.x, a_lds, v_lds, x_lds, hbuf,
+    integrate_mfma_unit<A_, N_, TWO, EXT, true>(n, ta, spw, blockIdx.x, a_lds, v_lds, x_lds, hbuf,
                                                   reinterpret_cast<typename L::Xch *>(xch_raw), s_cnt);
 }
 
@@ -699,11 +713,11 @@ hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total
 }
 
 // ---------------------------------------------------------------------------
-// Several networks of one shape class (A, slice width, planes, clamp) in one
+// Several networks of one shape class (A, slice width, planes, potential update) in one
 // launch: workgroup u runs unit u - e.unit_begin of the entry e whose unit
 // range holds u. The entries come as kernel arguments and the LDS is exactly
 // the shape's, as in the single-network kernel.
-template <int A_, int N_, bool TWO, bool CLAMP>
+template <int A_, int N_, bool TWO, bool EXT>
 __global__ __launch_bounds__(512) void k_integrate_mfma_group(MfmaGroupArgs g, int k)
 {
     typedef MfmaLds<A_, N_> L;
@@ -723,41 +737,41 @@ __global__ __launch_bounds__(512) void k_integrate_mfma_group(MfmaGroupArgs g, i
     ta.k = k;
     ta.ext_t = e.ext_base ? e.ext_base + (size_t)k * e.tick_words : nullptr;
     ta.ext_sstride = e.ext_sstride;
-    integrate_mfma_unit<A_, N_, TWO, CLAMP, true>(e.n, ta, e.spw, u - e.unit_begin, a_lds, v_lds, x_lds, hbuf,
+    integrate_mfma_unit<A_, N_, TWO, EXT, true>(e.n, ta, e.spw, u - e.unit_begin, a_lds, v_lds, x_lds, hbuf,
                                                   reinterpret_cast<typename L::Xch *>(xch_raw), s_cnt);
 }
 
 template <int A_, int N_, bool TWO>
-static void launch_group_k(const MfmaGroupArgs &g, int total, int k, int clamp, hipStream_t st)
+static void launch_group_k(const MfmaGroupArgs &g, int total, int k, int ext, hipStream_t st)
 {
-    if (clamp)
+    if (ext)
         hipLaunchKernelGGL((k_integrate_mfma_group<A_, N_, TWO, true>), dim3(total), dim3(512), 0, st, g, k);
     else
         hipLaunchKernelGGL((k_integrate_mfma_group<A_, N_, TWO, false>), dim3(total), dim3(512), 0, st, g, k);
 }
 
-hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int clamp,
+hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int ext,
                                        hipStream_t st)
 {
     static_assert(sizeof(MfmaGroupArgs) + sizeof(int) <= 4096, "kernel arguments exceed 4 KiB");
     if (g.num < 1 || g.num > MFMA_GROUP_MAX || total < 1)
         return hipErrorInvalidValue;
     switch (code) {
-    case 0: launch_group_k<64, 128, false>(g, total, k, clamp, st); break;
-    case 1: launch_group_k<64, 128, true>(g, total, k, clamp, st); break;
-    case 2: launch_group_k<64, 256, false>(g, total, k, clamp, st); break;
-    case 3: launch_group_k<64, 256, true>(g, total, k, clamp, st); break;
-    case 4: launch_group_k<128, 128, false>(g, total, k, clamp, st); break;
-    case 5: launch_group_k<128, 128, true>(g, total, k, clamp, st); break;
-    case 6: launch_group_k<128, 256, false>(g, total, k, clamp, st); break;
-    case 7: launch_group_k<128, 256, true>(g, total, k, clamp, st); break;
-    case 8: launch_group_k<256, 128, false>(g, total, k, clamp, st); break;
-    case 9: launch_group_k<256, 128, true>(g, total, k, clamp, st); break;
-    case 10: launch_group_k<256, 256, false>(g, total, k, clamp, st); break;
-    case 11: launch_group_k<256, 256, true>(g, total, k, clamp, st); break;
-    case 12: launch_group_k<512, 128, false>(g, total, k, clamp, st); break;
-    case 13: launch_group_k<512, 128, true>(g, total, k, clamp, st); break;
-    case 14: launch_group_k<512, 256, false>(g, total, k, clamp, st); break;
+    case 0: launch_group_k<64, 128, false>(g, total, k, ext, st); break;
+    case 1: launch_group_k<64, 128, true>(g, total, k, ext, st); break;
+    case 2: launch_group_k<64, 256, false>(g, total, k, ext, st); break;
+    case 3: launch_group_k<64, 256, true>(g, total, k, ext, st); break;
+    case 4: launch_group_k<128, 128, false>(g, total, k, ext, st); break;
+    case 5: launch_group_k<128, 128, true>(g, total, k, ext, st); break;
+    case 6: launch_group_k<128, 256, false>(g, total, k, ext, st); break;
+    case 7: launch_group_k<128, 256, true>(g, total, k, ext, st); break;
+    case 8: launch_group_k<256, 128, false>(g, total, k, ext, st); break;
+    case 9: launch_group_k<256, 128, true>(g, total, k, ext, st); break;
+    case 10: launch_group_k<256, 256, false>(g, total, k, ext, st); break;
+    case 11: launch_group_k<256, 256, true>(g, total, k, ext, st); break;
+    case 12: launch_group_k<512, 128, false>(g, total, k, ext, st); break;
+    case 13: launch_group_k<512, 128, true>(g, total, k, ext, st); break;
+    case 14: launch_group_k<512, 256, false>(g, total, k, ext, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -789,7 +803,7 @@ static void launch_mfma_k(const DevNet &n, const TickArgs &a, int spw, hipStream
 {
     const int chunks = (n.S + spw - 1) / spw;
     const dim3 grid(n.C * n.slices * chunks), block(512);
-    if (n.vmin == INT32_MIN && n.vmax == INT32_MAX)
+    if (!n.model_ext)
         hipLaunchKernelGGL((k_integrate_mfma<A_, N_, TWO, false>), grid, block, 0, st, n, a, spw);
     else
         hipLaunchKernelGGL((k_integrate_mfma<A_, N_, TWO, true>), grid, block, 0, st, n, a, spw);

@@ -69,7 +69,13 @@ __device__ __forceinline__ void integrate_plain_unit(const DevNet &n, const Tick
     const size_t cj = (size_t)c * N + j;
     const size_t vi = ((size_t)c * n.S + s) * N + j;
     int32_t vnew;
-    const bool fire = lif_update(n.V[vi], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, vnew) && live;
+    int32_t fl = n.vmin;
+    bool lin = false;
+    if (n.model_ext) {   // uniform
+        fl = n.floor[cj];
+        lin = (n.linmask[cj >> 5] >> (j & 31)) & 1u;
+    }
+    const bool fire = lif_update(n.V[vi], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, fl, lin, vnew) && live;
     if (live)
         n.V[vi] = vnew;
     if (!live)
@@ -149,7 +155,13 @@ __device__ __forceinline__ void integrate_plain_wave(const DevNet &n, const Tick
     const size_t cj = (size_t)c * N + j;
     const size_t vi = ((size_t)c * n.S + s) * N + j;
     int32_t vnew;
-    const bool fire = lif_update(n.V[vi], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, vnew);
+    int32_t fl = n.vmin;
+    bool lin = false;
+    if (n.model_ext) {   // uniform
+        fl = n.floor[cj];
+        lin = (n.linmask[cj >> 5] >> (j & 31)) & 1u;
+    }
+    const bool fire = lif_update(n.V[vi], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, fl, lin, vnew);
     n.V[vi] = vnew;
     const unsigned long long b = __ballot(fire);
     const unsigned ev = wave_sum(e);

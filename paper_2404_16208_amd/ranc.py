@@ -16,13 +16,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libranc.so")
 
-RANC_ABI_VERSION = 1
+RANC_ABI_VERSION = 2
 RANC_OK, RANC_EINVAL, RANC_ERANGE, RANC_ENOMEM, RANC_EDEVICE, RANC_ESTATE, RANC_ETRUNC, RANC_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "RANC_OK", -1: "RANC_EINVAL", -2: "RANC_ERANGE", -3: "RANC_ENOMEM", -4: "RANC_EDEVICE",
                 -5: "RANC_ESTATE", -6: "RANC_ETRUNC", -7: "RANC_EUNSUPPORTED"}
 RANC_PATH_AUTO, RANC_PATH_PLAIN, RANC_PATH_MFMA, RANC_PATH_SPARSE = 0, 1, 2, 3
 PATHS = {"auto": RANC_PATH_AUTO, "plain": RANC_PATH_PLAIN, "mfma": RANC_PATH_MFMA, "sparse": RANC_PATH_SPARSE}
+RANC_RESET_ABSOLUTE, RANC_RESET_LINEAR = 0, 1
 RANC_INPUTS_ON_DEVICE = 1
 RANC_RUN_GRAPH = 2
 RANC_BATCH_PERSISTENT = 4
@@ -46,7 +47,8 @@ class ranc_net_desc(C.Structure):
         ("crossbar", C.c_void_p), ("axon_type", C.c_void_p), ("weight", C.c_void_p), ("leak", C.c_void_p),
         ("threshold", C.c_void_p), ("reset", C.c_void_p), ("v_init", C.c_void_p), ("dest_kind", C.c_void_p),
         ("dest_dx", C.c_void_p), ("dest_dy", C.c_void_p), ("dest_axon", C.c_void_p), ("dest_delay", C.c_void_p),
-        ("num_input_cores", C.c_int32), ("input_cores", C.c_void_p)]
+        ("num_input_cores", C.c_int32), ("input_cores", C.c_void_p),
+        ("leak_bits", C.c_int32), ("reset_bits", C.c_int32), ("floor", C.c_void_p), ("reset_mode", C.c_void_p)]
 
 
 class ranc_spike(C.Structure):
@@ -130,12 +132,19 @@ class Desc:
                            dest_dx=a(net.dest_dx, np.int16), dest_dy=a(net.dest_dy, np.int16),
                            dest_axon=a(net.dest_axon, np.uint16), dest_delay=a(net.dest_delay, np.uint8),
                            input_cores=a(net.input_cores, np.int32))
+        floor, mode = getattr(net, "floor", None), getattr(net, "reset_mode", None)
+        if floor is not None:
+            self.arrays["floor"] = a(floor, np.int32)
+        if mode is not None:
+            self.arrays["reset_mode"] = a(mode, np.uint8)
         p = {k: v.ctypes.data for k, v in self.arrays.items()}
         self.c = ranc_net_desc(RANC_ABI_VERSION, net.num_cores, net.num_axons, net.num_neurons, net.num_types,
                                net.weight_bits, net.potential_bits, net.max_delay, net.grid_w, net.grid_h,
                                p["crossbar"], p["axon_type"], p["weight"], p["leak"], p["threshold"], p["reset"],
                                p["v_init"], p["dest_kind"], p["dest_dx"], p["dest_dy"], p["dest_axon"],
-                               p["dest_delay"], len(self.arrays["input_cores"]), p["input_cores"])
+                               p["dest_delay"], len(self.arrays["input_cores"]), p["input_cores"],
+                               int(getattr(net, "leak_bits", 32)), int(getattr(net, "reset_bits", 32)),
+                               p.get("floor"), p.get("reset_mode"))
 
 
 def ranc_workspace_bytes(desc: Desc, num_samples: int, max_ticks_per_call: int, path: int = RANC_PATH_AUTO) -> int:

@@ -387,6 +387,12 @@ def sweep_variant(seed: int, v: int) -> Tuple[Net, Dict]:
     W ~ U[-wmax, wmax], threshold ~ U[wmax/4, 2 wmax], leak ~ U[-wmax/32, wmax/32];
     90% of neurons target a random (core, axon) with delay 1..4, the rest OUT;
     external input on the first ceil(C/4) cores.
+    Neuron-model axes (Sec. I and Sec. V: the widths of leak, potential and
+    reset are configurable), from a stream of their own: potential width 32
+    for half the variants, else uniform in [max(b + 4, 12), 31]; leak width
+    just wide enough for the leak range plus 0..3 bits; reset width 2..P; a
+    floor U[-4 wmax, 0] per neuron for a quarter of the variants and linear
+    reset for half the neurons of another quarter.
     """
     r = rng_for(seed, 4, 7000 + v)
     C = int(2 ** r.integers(4, 13))
@@ -398,9 +404,20 @@ def sweep_variant(seed: int, v: int) -> Tuple[Net, Dict]:
     wmax = (1 << (b - 1)) - 1
     gw = 1 << ((int(math.log2(C)) + 1) // 2)
     lk = wmax // 32
-    net = random_net(seed * 1000 + v, C, A, N, G, weight_bits=b, potential_bits=32, max_delay=4,
+    m = rng_for(seed, 4, 8000 + v)
+    P = 32 if m.random() < 0.5 else int(m.integers(max(b + 4, 12), 32))
+    leak_bits = max(2, int(lk).bit_length() + 1) + int(m.integers(0, 4))
+    reset_bits = int(m.integers(2, P + 1))
+    u = m.random()
+    floor_range = (-4 * wmax, 0) if u < 0.25 else None
+    linear_frac = 0.5 if 0.25 <= u < 0.5 else 0.0
+    net = random_net(seed * 1000 + v, C, A, N, G, weight_bits=b, potential_bits=P, max_delay=4,
                      grid_w=gw, density=dens, p_core=0.9, p_out=0.1,
                      leak_range=(-lk, lk), thr_range=(max(1, wmax // 4), 2 * wmax),
-                     config_id=4, input_cores=np.arange((C + 3) // 4))
-    net.name = f"sweep{v}_C{C}_A{A}_N{N}_G{G}_b{b}"
-    return net, dict(C=C, A=A, N=N, G=G, b=b, density=dens)
+                     config_id=4, input_cores=np.arange((C + 3) // 4),
+                     floor_range=floor_range, linear_frac=linear_frac,
+                     leak_bits=leak_bits, reset_bits=reset_bits)
+    model = f"_P{P}" + ("_floor" if floor_range else "") + ("_linear" if linear_frac else "")
+    net.name = f"sweep{v}_C{C}_A{A}_N{N}_G{G}_b{b}{model}"
+    return net, dict(C=C, A=A, N=N, G=G, b=b, density=dens, P=P, leak_bits=leak_bits, reset_bits=reset_bits,
+                     floor=floor_range is not None, linear=linear_frac > 0)
