@@ -212,11 +212,15 @@ def test_sparse_path_shapes(R):
     assert st == R.RANC_OK, msg
     st, msg, b_mfma = ws_status(R, net, S=64, path=R.RANC_PATH_MFMA)
     assert st == R.RANC_OK, msg
-    # the sparse path keeps crossbar rows (A*N/8 bytes per core), not int8 weight planes
+    # the sparse path keeps 2-byte row entries per connection (density 0.2:
+    # about 26 KB per core), not int8 weight planes (128 KB per core)
     assert b_sparse < b_mfma
+    # every core shape and number of axon types: the weights sit in the row entries
     big = W.random_net(10, 2, 64, 512, 8, grid_w=2, config_id=603)
-    st, msg, _ = ws_status(R, big, S=64, path=R.RANC_PATH_SPARSE)
-    assert R.STATUS_NAMES[st] == "RANC_EUNSUPPORTED" and "sparse" in msg
+    st, msg, b_big = ws_status(R, big, S=64, path=R.RANC_PATH_SPARSE)
+    assert st == R.RANC_OK, msg
+    nnz = int(np.unpackbits(big.crossbar.view(np.uint8)).sum())
+    assert b_big >= 2 * nnz
     st, msg, _ = ws_status(R, net, S=64, path=4)
     assert st == R.RANC_EINVAL
 
@@ -234,3 +238,48 @@ def test_autotune_cache_key_names_the_shape():
     net = W.random_net(11, 4, 128, 256, 2, weight_bits=7, max_delay=3, grid_w=2, config_id=604)
     k = autotune.shape_key(net, 96, "mfma", "MI355X")
     assert k == "MI355X|mfma|C4A128N256G2b7D3S96"
+
+
+@pytest.mark.parametrize("case,status,needle", [
+    ("leak_bits_width", "RANC_ERANGE", "leak_bits"),
+    ("reset_bits_width", "RANC_ERANGE", "reset_bits"),
+    ("leak_outside_width", "RANC_ERANGE", "4-bit leak range"),
+    ("reset_outside_width", "RANC_ERANGE", "3-bit reset range"),
+    ("floor_low", "RANC_ERANGE", "floor"),
+    ("floor_high", "RANC_ERANGE", "floor"),
+    ("reset_mode", "RANC_EINVAL", "reset_mode"),
+])
+def test_neuron_model_rejections(R, case, status, needle):
+    """The neuron-model widths and options (leak and reset widths, floor,
+    reset mode) are validated like every other field."""
+    net = W.random_net(7, 4, 64, 64, 4, grid_w=2, max_delay=3, p_core=0.6, p_out=0.3, potential_bits=16,
+                       input_cores=[0, 3], config_id=600, floor_range=(-100, 0), linear_frac=0.5)
+    if case == "leak_bits_width":
+        net.leak_bits = 33
+    elif case == "reset_bits_width":
+        net.reset_bits = 1
+    elif case == "leak_outside_width":
+        net.leak_bits = 4
+        net.leak[2, 5] = 8
+    elif case == "reset_outside_width":
+        net.reset_bits = 3
+        net.reset[1, 1] = -5
+    elif case == "floor_low":
+        net.floor[0, 0] = -(1 << 15) - 1
+    elif case == "floor_high":
+        net.floor[3, 63] = 1 << 15
+    elif case == "reset_mode":
+        net.reset_mode[2, 2] = 2
+    st, msg, _ = ws_status(R, net)
+    assert R.STATUS_NAMES[st] == status and needle in msg, (st, msg)
+
+
+def test_neuron_model_widths_at_their_limits_accepted(R):
+    net = W.random_net(7, 4, 64, 64, 4, grid_w=2, max_delay=3, p_core=0.6, p_out=0.3, potential_bits=16,
+                       input_cores=[0, 3], config_id=600, floor_range=(-(1 << 15), (1 << 15) - 1),
+                       linear_frac=1.0)
+    net.leak_bits, net.reset_bits = 4, 3
+    net.leak[:] = np.where(np.arange(64) % 2, 7, -8)
+    net.reset[:] = np.where(np.arange(64) % 2, 3, -4)
+    st, msg, _ = ws_status(R, net)
+    assert st == R.RANC_OK, msg
