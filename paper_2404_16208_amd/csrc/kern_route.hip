@@ -378,6 +378,10 @@ __global__ void k_reset_potentials(DevNet n)
             const size_t cnb = (i >> 10) / groups;   // c * NB + nb
             c = cnb / NB;
             j = (cnb % NB) * 32 + (lane & 31);
+        } else if (n.vlayout == VLAYOUT_SPARSE) {
+            // [C][N][S64]
+            c = i / (SV * n.N);
+            j = (i / SV) % n.N;
         } else {
             c = i / (SV * n.N);
             j = i % n.N;

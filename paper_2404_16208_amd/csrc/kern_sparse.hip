@@ -4,380 +4,292 @@
 // scheduler write of this tick's spikes.
 //
 // Integration (GPU-RANC Sec. II) touches only the spiking axons' part of the
-// crossbar: a neuron's input is the sum over axon types g of (number of
-// spiking axons of type g connected to it) * its weight for g, and the count
-// is a popcount of (the neuron's crossbar column word) AND (the sample's
-// spiking axons of type g) per 32-axon word. Words with no spiking axon, and
-// types with no spiking axon in a word, are skipped (wave-uniform tests), so
-// the work follows the activity: with spike rates of a few percent most of
-// the A/32 x G buckets are empty. It needs neither the weight planes of the
-// MFMA path nor LDS tiles per sample: the core's crossbar columns, type masks
-// and the neurons' G weights are loaded once per workgroup.
+// crossbar. The core's connections are kept as compressed rows, one per
+// (neuron slice, axon): the connected neurons of the slice, each entry with
+// the neuron's weight for the axon's type already in it (16 bits: neuron
+// within the slice in 7, signed 9-bit weight in 9). For every spiking axon
+// of a sample the row's weights are added to the sample's input currents,
+// so the work is the number of synaptic events, not A x N per sample.
 //
-// Scheduler and delivery are those of the MFMA path (same layouts): a
-// sample-sliced spike history of the last Q = D + 1 ticks, gathered by the
-// destination core for each of its axons at tick t - d, and the output raster
-// as neuron-major history words. Bits within a 32-sample group follow the
-// order sigma32 of kern_bits.h, so both paths read and write the same words.
-//
-// Mapping: one workgroup per (core, chunk of samples), 64 samples per tile,
-// of 4 wavefronts (8 when A = 512, whose history gather needs 8); wave w of
-// the workgroup's nw waves handles samples w, w + nw, ... of the tile, one at
-// a time, with lane l owning neurons l, l + 64, ... (N/64 per lane). Small
-// workgroups keep several independent workgroups per compute unit: with few
-// samples per core a workgroup is a short chain of dependent memory
-// accesses, and the chains of different workgroups overlap. A sample's axon
-// words are wave-uniform, so the bucket tests run on scalar
-// registers; per non-empty word each lane reads its neurons' column words
-// from LDS, per non-empty bucket it adds popcounts. The neurons' spike bits
-// of the wave's samples are collected per lane and ORed across the
-// workgroup's waves in LDS, giving each neuron's 64-sample history word of
-// the tile.
-#include <type_traits>
-
+// Mapping: one workgroup of 4 wavefronts per (core, slice of <= 128 neurons,
+// tile of 64 samples); a lane is a sample. Phases:
+//   0. every lane starts loading the potentials of its wave's neurons for
+//      its sample (V is neuron-major, [C][N][S64], so a wave's load of one
+//      neuron is 256 contiguous bytes); they are in flight during 1 and 2;
+//      the slice's rows are staged in LDS;
+//   1. delivery: for each axon, the OR of its sources' history words at
+//      t - d (the scheduler rows of Sec. III-E, kept as the last Q = D + 1
+//      ticks of every neuron's spikes, 64 samples per word, bit i = sample
+//      i of the tile); the per-axon sample words are bit-transposed into
+//      per-sample axon words;
+//   2. scatter: each lane walks the spiking axons of its sample in its
+//      wave's axon words and, flat over (axon, entry), adds every entry's
+//      weight to its sample's current of that neuron in LDS (LDS atomic
+//      add: waves share neurons);
+//   3. update: per neuron of the wave, leak, threshold and reset for all 64
+//      samples at once (lif_update); the wave's ballot of the spikes is the
+//      neuron's 64-sample history word; potentials are stored back.
+// Every scheduler word has one writer (the workgroup of the neuron's slice
+// and tile) and no global atomics are used.
 #include "kern_bits.h"
 #include "kern_common.h"
 #include "ranc_internal.h"
 
 namespace ranc {
 
-static constexpr int SP_TS = 64;        // samples per tile
-static constexpr int SP_SPW_MAX = 512;  // samples per workgroup (LDS counters)
+static constexpr int EV_TS = 64;          // samples per workgroup (one history word)
+static constexpr int EV_NS = 128;         // neurons per slice, at most
+static constexpr int EV_WAVES = 4;        // wavefronts per workgroup
+static constexpr int EV_CSR_LDS = 4096;   // row entries staged in LDS (8 KiB)
 
-template <int A_> constexpr int sp_waves() { return A_ == 512 ? 8 : 4; }
-
-// Four waves per SIMD where the per-lane weights, type counts and prefetched
-// potentials fit in 128 VGPRs without spilling.
-template <int A_, int N_, int G_>
-__global__ __launch_bounds__(64 * sp_waves<A_>()) __attribute__((amdgpu_waves_per_eu(N_ <= 128 || (N_ == 256 && A_ == 256 && G_ <= 4) ? 4 : 2)))
-void k_integrate_sparse(DevNet n, TickArgs ta, int spw)
-{
-    constexpr int NWV = sp_waves<A_>();  // wavefronts per workgroup
-    constexpr int W_ = A_ / 32;          // axon words
-    constexpr int NW_ = N_ / 32;         // neuron words per crossbar row
-    constexpr int NPL = N_ / 64;         // neurons per lane: lane + 64 j
-    constexpr int APW = A_ / 64;         // 64-axon blocks of the gather
-    // 32-sample groups gathered per wave: both when the (block, group) pairs
-    // outnumber the waves
-    constexpr int GPW = 2 * APW > NWV ? 2 : 1;
-    static_assert(APW * 2 / GPW <= NWV, "gather roles exceed the workgroup's waves");
-    typedef typename std::conditional<GPW == 2, uint64_t, uint32_t>::type RawT;
-
-    // crossbar columns: bit b of col[w][n] = crossbar(32w + b, n)
-    __shared__ uint32_t col[W_][N_];
-    __shared__ uint32_t tm[G_ * W_];                   // axon-type masks
-    __shared__ uint32_t x_lds[2][SP_TS][W_ + 1];        // delivered axon words per sample
-    __shared__ uint32_t xe_lds[2][SP_TS][W_ + 1];       // external input words per sample
-    __shared__ unsigned long long hacc[N_];            // the tile's spike words per neuron
-    // per sample of the chunk: [0] emitted | routed << 10 | out << 20,
-    // [1] events | delivered << 19 (events <= 512 * 512 = 2^18)
-    __shared__ unsigned s_cnt[2][SP_SPW_MAX];
-
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int h = lane >> 5;
-    const int sig = sigma32(lane & 31);
-    int c, chunk;   // XCD-grouped (core_unit_of)
-    core_unit_of(blockIdx.x, n.C, (n.S + spw - 1) / spw, c, chunk);
-    const int s_begin = chunk * spw;
-    const int s_end = min(n.S, s_begin + spw);
-
-    for (int i = threadIdx.x; i < W_ * N_; i += blockDim.x)
-        (&col[0][0])[i] = n.colbits[(size_t)c * W_ * N_ + i];
-    for (int i = threadIdx.x; i < G_ * W_; i += blockDim.x)
-        tm[i] = n.typemask[(size_t)c * G_ * W_ + i];
-    for (int i = threadIdx.x; i < N_; i += blockDim.x)
-        hacc[i] = 0ull;
-    for (int i = threadIdx.x; i < 2 * SP_SPW_MAX; i += blockDim.x)
-        (&s_cnt[0][0])[i] = 0u;
-
-    // neuron parameters of this lane
-    int32_t wt[G_][NPL], lk[NPL], th[NPL], rs[NPL];
-#pragma unroll
-    for (int j = 0; j < NPL; ++j) {
-        const size_t cj = (size_t)c * N_ + lane + 64 * j;
-        lk[j] = n.leak[cj];
-        th[j] = n.thr[cj];
-        rs[j] = n.rst[cj];
-#pragma unroll
-        for (int g = 0; g < G_; ++g)
-            wt[g][j] = n.wts[((size_t)c * G_ + g) * N_ + lane + 64 * j];
-    }
-    const int32_t vmin = n.vmin, vmax = n.vmax;
-
-    const int ci = n.in_index[c];
-    const uint32_t *ext_c = (ta.ext_t != nullptr && ci >= 0) ? ta.ext_t + (size_t)ci * W_ : nullptr;
-    const int q_now = tick_slot(n, ta.k), r_row = tick_row(n, ta.k);
-    const size_t HG = (size_t)n.S64 / 64;
-    const size_t CN = (size_t)n.C * N_;
-    int32_t *vc = n.V + (size_t)c * n.S64 * N_ + lane;
-
-    // ---- history gather (as on the MFMA path): wave w collects, for axon
-    // block w % APW, group w / APW of each tile's history bits (both groups
-    // with GPW = 2).
-    const bool gatherer = wave < 2 * APW / GPW;
-    const int axb = wave % APW;
-    const int grp = GPW == 2 ? 0 : wave / APW;
-    const int ga = axb * 64 + lane;
-    uint32_t e_beg = 0, e_end = 0;
-    if (gatherer) {
-        e_beg = n.rtx_ptr[(size_t)c * A_ + ga];
-        e_end = n.rtx_ptr[(size_t)c * A_ + ga + 1];
-    }
-    constexpr int FMAX = 4;
-    const uint64_t *src_row[FMAX];
-#pragma unroll
-    for (int k = 0; k < FMAX; ++k) {
-        src_row[k] = n.hist_zero;
-        if (e_beg + k < e_end) {
-            const uint32_t ent = n.rtx_ent[e_beg + k];
-            int slot = q_now - (int)(ent & 15u) - 1;
-            if (slot < 0)
-                slot += n.Q;
-            src_row[k] = n.hist + ((size_t)slot * CN + (ent >> 4)) * HG;
-        }
-    }
-    const bool multi = __ballot(e_end - e_beg > 1) != 0;
-    const bool long_lists = __ballot(e_end - e_beg > FMAX) != 0;
-    auto raw_word = [&](const uint64_t *row, int tile) -> RawT {
-        if constexpr (GPW == 2)
-            return row[tile];
-        else
-            return reinterpret_cast<const uint32_t *>(row + tile)[grp];
-    };
-    auto load_mask = [&](int s0, RawT (&raw)[FMAX]) {
-        const int tile = (s0 < s_end ? s0 : s_begin) / SP_TS;
-        raw[0] = raw_word(src_row[0], tile);
-        if (multi) {
-#pragma unroll
-            for (int k = 1; k < FMAX; ++k)
-                raw[k] = raw_word(src_row[k], tile);
-            for (uint32_t e = e_beg + FMAX; long_lists && e < e_end; ++e) {
-                const uint32_t ent = n.rtx_ent[e];
-                int slot = q_now - (int)(ent & 15u) - 1;
-                if (slot < 0)
-                    slot += n.Q;
-                raw[1] |= raw_word(n.hist + ((size_t)slot * CN + (ent >> 4)) * HG, tile);
-            }
-        }
-    };
-    auto mask_of = [&](const RawT (&raw)[FMAX]) -> RawT {
-        RawT m = raw[0];
-        if (multi) {
-#pragma unroll
-            for (int k = 1; k < FMAX; ++k)
-                m |= raw[k];
-        }
-        return m;
-    };
-    auto transpose_store = [&](RawT m, int buf) {
-#pragma unroll
-        for (int g = 0; g < GPW; ++g) {
-            const uint32_t t = transpose32((uint32_t)(m >> (32 * g)), lane);
-            x_lds[buf][32 * (GPW == 2 ? g : grp) + sig][2 * axb + h] = t;
-        }
-    };
-
-    // external input words of a tile into LDS (all threads, coalesced per sample)
-    auto stage_ext = [&](int s0, int buf) {
-        for (int i = threadIdx.x; i < SP_TS * W_; i += blockDim.x) {
-            const int t = i / W_, w = i % W_;
-            const int s = s0 + t;
-            xe_lds[buf][t][w] = (ext_c && s < s_end) ? ext_c[(size_t)s * ta.ext_sstride + w] : 0u;
-        }
-    };
-
-    RawT mraw[FMAX] = {};
-    if (gatherer) {
-        load_mask(s_begin, mraw);
-        transpose_store(mask_of(mraw), 0);
-        load_mask(s_begin + SP_TS, mraw);
-    }
-    stage_ext(s_begin, 0);
-    __syncthreads();
-
-    int it = 0;
-    for (int s0 = s_begin; s0 < s_end; s0 += SP_TS, ++it) {
-        const int buf = it & 1;
-        const int tile = s0 / SP_TS;
-        uint64_t hw[NPL];
-#pragma unroll
-        for (int j = 0; j < NPL; ++j)
-            hw[j] = 0ull;
-        // the potentials of PF of the wave's samples of the tile are loaded
-        // together, ahead of their use
-        constexpr int PF = NPL >= 4 ? 4 : 8;
-        constexpr int SPW = SP_TS / NWV;   // samples per wave per tile
-        for (int i0 = 0; i0 < SPW; i0 += PF) {
-        int32_t vbuf[PF][NPL];
-#pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int s = min(s0 + wave + NWV * (i0 + i), s_end - 1);
-#pragma unroll
-            for (int j = 0; j < NPL; ++j)
-                vbuf[i][j] = vc[(size_t)s * N_ + 64 * j];
-        }
-#pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int t = wave + NWV * (i0 + i);
-            const int s = s0 + t;
-            if (s >= s_end)
-                break;   // wave-uniform
-            // the sample's axon words: delivered | external input
-            uint32_t xw[W_];
-            unsigned delivered = 0;
-#pragma unroll
-            for (int w = 0; w < W_; ++w) {
-                const uint32_t xd = __builtin_amdgcn_readfirstlane(x_lds[buf][t][w]);
-                delivered += __popc(xd);
-                xw[w] = xd | __builtin_amdgcn_readfirstlane(xe_lds[buf][t][w]);
-            }
-            // per type, spiking connected axons of each of this lane's neurons
-            unsigned cnt[G_][NPL];
-#pragma unroll
-            for (int g = 0; g < G_; ++g)
-#pragma unroll
-                for (int j = 0; j < NPL; ++j)
-                    cnt[g][j] = 0u;
-#pragma unroll
-            for (int w = 0; w < W_; ++w) {
-                if (!xw[w])
-                    continue;   // wave-uniform
-                uint32_t cw[NPL];
-#pragma unroll
-                for (int j = 0; j < NPL; ++j)
-                    cw[j] = col[w][lane + 64 * j];
-#pragma unroll
-                for (int g = 0; g < G_; ++g) {
-                    const uint32_t m = xw[w] & tm[g * W_ + w];   // wave-uniform
-                    if (!m)
-                        continue;
-#pragma unroll
-                    for (int j = 0; j < NPL; ++j)
-                        cnt[g][j] += (unsigned)__popc(cw[j] & m);
-                }
-            }
-            int32_t acc[NPL];
-            unsigned ev = 0;
-#pragma unroll
-            for (int j = 0; j < NPL; ++j) {
-                acc[j] = lk[j];
-#pragma unroll
-                for (int g = 0; g < G_; ++g) {
-                    acc[j] += __mul24((int)cnt[g][j], wt[g][j]);
-                    ev += cnt[g][j];
-                }
-            }
-            const unsigned events = wave_sum(ev);
-            // leak was the accumulator's start; threshold, reset
-            unsigned emitted = 0, routed = 0, out = 0;
-            const int pos = 32 * (t >> 5) + sigma32_inv(t & 31);
-#pragma unroll
-            for (int j = 0; j < NPL; ++j) {
-                int32_t vn;
-                const bool fire = lif_update(vbuf[i][j], acc[j], 0, th[j], rs[j], vmin, vmax, vn);
-                vc[(size_t)s * N_ + 64 * j] = vn;
-                hw[j] |= fire ? (1ull << pos) : 0ull;
-                const unsigned long long m = __ballot(fire);
-                const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-                const size_t mw = (size_t)c * NW_ + 2 * j;
-                emitted += __popc(lo) + __popc(hi);
-                routed += __popc(lo & n.coremask[mw]) + __popc(hi & n.coremask[mw + 1]);
-                out += __popc(lo & n.outmask[mw]) + __popc(hi & n.outmask[mw + 1]);
-            }
-            if (lane == 0) {
-                s_cnt[0][s - s_begin] = emitted | (routed << 10) | (out << 20);
-                s_cnt[1][s - s_begin] = events | (delivered << 19);
-            }
-        }
-        }
-        // the tile's spike words of every neuron: OR of the waves' bits
-#pragma unroll
-        for (int j = 0; j < NPL; ++j)
-            if (hw[j])
-                atomicOr(&hacc[lane + 64 * j], hw[j]);
-        __syncthreads();
-        for (int i = threadIdx.x; i < N_; i += blockDim.x) {
-            const uint64_t w = hacc[i];
-            hacc[i] = 0ull;
-            const size_t cj = (size_t)c * N_ + i;
-            n.hist[((size_t)q_now * CN + cj) * HG + tile] = w;
-            const int oi = n.outidx[cj];
-            if (oi >= 0)
-                reinterpret_cast<uint64_t *>(n.raster)[((size_t)r_row * n.Nout + oi) * HG + tile] = w;
-        }
-        if (s0 + SP_TS < s_end) {
-            if (gatherer) {
-                transpose_store(mask_of(mraw), (it + 1) & 1);
-                load_mask(s0 + 2 * SP_TS, mraw);
-            }
-            stage_ext(s0 + SP_TS, (it + 1) & 1);
-        }
-        __syncthreads();
-    }
-    unsigned long long *cw_out = n.cring + ((size_t)r_row * n.C + c) * n.S + s_begin;   // one counter row per core
-    for (int i = threadIdx.x; i < s_end - s_begin; i += blockDim.x) {
-        const unsigned sp = s_cnt[0][i], ev = s_cnt[1][i];
-        cw_out[i] = pack_counts(sp & 1023u, (sp >> 10) & 1023u, sp >> 20, ev >> 19, ev & ((1u << 19) - 1u));
-    }
-}
-
-int sparse_max_samples_per_wg() { return SP_SPW_MAX; }
+int sparse_max_samples_per_wg() { return EV_TS; }
+int sparse_slice_width(int N) { return N < EV_NS ? N : EV_NS; }
+int sparse_row_align() { return 8; }
 
 bool sparse_shape_supported(int A, int N, int G)
 {
     const bool ok_a = A == 64 || A == 128 || A == 256 || A == 512;
     const bool ok_n = N == 64 || N == 128 || N == 256 || N == 512;
     const bool ok_g = G == 1 || G == 2 || G == 4 || G == 8;
-    // per-lane weights take G * N / 64 VGPRs
-    return ok_a && ok_n && ok_g && G * N <= 2048;
+    return ok_a && ok_n && ok_g;
 }
 
-template <int A_, int N_>
-static hipError_t launch_sparse_an(const DevNet &n, const TickArgs &a, int spw, hipStream_t st)
+// acc index of (sample s, neuron j of the slice): the neuron index is XORed
+// with the sample's low five bits, so the 32 samples a half-wave reads for
+// one neuron fall in 32 different banks.
+template <int NS_> __device__ inline int acc_index(int s, int j) { return s * NS_ + (j ^ (s & 31)); }
+
+// Scatter of one axon word of this lane's sample: a flat loop over
+// (spiking axon, row entry), so lanes with short rows move on to their next
+// axon instead of idling until the wave's longest row ends.
+template <int NS_, typename RowPtr>
+__device__ __forceinline__ void scatter_word(uint32_t bits, int word, int s, const uint32_t *rp, RowPtr rows,
+                                             int32_t *acc, unsigned &events)
 {
-    const int chunks = (n.S + spw - 1) / spw;
-    const dim3 grid(n.C * chunks), block(64 * sp_waves<A_>());
-    switch (n.G) {
-    case 1: hipLaunchKernelGGL((k_integrate_sparse<A_, N_, 1>), grid, block, 0, st, n, a, spw); break;
-    case 2: hipLaunchKernelGGL((k_integrate_sparse<A_, N_, 2>), grid, block, 0, st, n, a, spw); break;
-    case 4:
-        if constexpr (N_ <= 512)
-            hipLaunchKernelGGL((k_integrate_sparse<A_, N_, 4>), grid, block, 0, st, n, a, spw);
-        break;
-    case 8:
-        if constexpr (N_ <= 256)
-            hipLaunchKernelGGL((k_integrate_sparse<A_, N_, 8>), grid, block, 0, st, n, a, spw);
+    uint32_t e = 0, ee = 0;
+    for (;;) {
+        if (e >= ee) {
+            if (!bits)
+                break;
+            const int a = 32 * word + __builtin_ctz(bits);
+            bits &= bits - 1u;
+            e = rp[a];
+            ee = rp[a + 1];
+            events += ee - e;
+            continue;
+        }
+        const uint32_t ent = rows[e++];
+        const int j = (int)(ent & 127u);
+        const int w = (int)(ent << 16) >> 23;   // bits 7..15, sign-extended
+        atomicAdd(&acc[acc_index<NS_>(s, j)], w);
+    }
+}
+
+template <int A_, int NS_, bool EXT>
+__global__ __launch_bounds__(64 * EV_WAVES) void k_integrate_event(DevNet n, TickArgs ta)
+{
+    constexpr int W_ = A_ / 32;                             // axon words
+    constexpr int NPW = NS_ / EV_WAVES;                      // neurons per wave in the update
+    constexpr int WPW = (W_ + EV_WAVES - 1) / EV_WAVES;      // axon words per wave in the scatter
+    constexpr int APW = A_ / 64;                             // 64-axon blocks of the gather
+    constexpr int BPW = (APW + EV_WAVES - 1) / EV_WAVES;     // gather blocks per wave
+    constexpr int FMAX = 4;                                  // sources gathered without a loop
+
+    __shared__ __attribute__((aligned(16))) int32_t acc[EV_TS * NS_];
+    __shared__ uint32_t xw[EV_TS][W_ + 1];                   // delivered axon words per sample
+    __shared__ uint32_t rp[A_ + 1];                          // row starts, relative to the slice's first entry
+    __shared__ __attribute__((aligned(16))) uint16_t rows[EV_CSR_LDS];
+    // per sample: [0] emitted | routed << 10 | out << 20, [1] events | delivered << 20
+    __shared__ unsigned s_cnt[2][EV_TS];
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int tiles = n.S64 / EV_TS;
+    int c, v;   // XCD-grouped (core_unit_of)
+    core_unit_of(blockIdx.x, n.C, n.slices * tiles, c, v);
+    const int slice = v % n.slices;
+    const int tile = v / n.slices;
+    const int s = tile * EV_TS + lane;   // this lane's sample
+    const bool svalid = s < n.S;
+    const size_t CN = (size_t)n.C * n.N;
+    const size_t HG = (size_t)n.S64 / 64;
+    const int q_now = tick_slot(n, ta.k), r_row = tick_row(n, ta.k);
+    const int j0 = slice * NS_ + wave * NPW;   // first neuron (within the core) of this wave's update
+
+    // ---- 0. loads that start the chains: gather table heads, the slice's
+    // rows, then the potentials of this wave's neurons (used in phase 3)
+    uint32_t g_beg[BPW], g_end[BPW];
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        const int axb = wave + EV_WAVES * b;
+        g_beg[b] = g_end[b] = 0u;
+        if (axb < APW) {
+            const size_t a = (size_t)c * A_ + axb * 64 + lane;
+            g_beg[b] = n.rtx_ptr[a];
+            g_end[b] = n.rtx_ptr[a + 1];
+        }
+    }
+    const uint32_t *rp_g = n.ecsr_ptr + ((size_t)c * n.slices + slice) * (A_ + 1);
+    const uint32_t e_base = rp_g[0];
+    const uint32_t e_count = rp_g[A_] - e_base;
+    const uint32_t e_pad = (e_count + 7u) & ~7u;   // each slice's rows are padded to 8 entries
+    const bool staged = e_pad <= (uint32_t)EV_CSR_LDS;   // uniform
+    for (int i = threadIdx.x; i <= A_; i += 64 * EV_WAVES)
+        rp[i] = rp_g[i] - e_base;
+    if (staged) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(n.ecsr_ent + e_base);
+        for (int i = threadIdx.x; i < (int)(e_pad / 8); i += 64 * EV_WAVES)
+            reinterpret_cast<uint4 *>(rows)[i] = src[i];
+    }
+    int32_t vreg[NPW];
+    const int32_t *vin = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k)
+        vreg[k] = __builtin_nontemporal_load(vin + (size_t)k * n.S64);
+    compiler_fence();
+
+    // external input words of this lane's sample for the wave's scatter words
+    uint32_t xe[WPW];
+    const int ci = n.in_index[c];
+    const uint32_t *ext = (ta.ext_t != nullptr && ci >= 0 && svalid)
+                              ? ta.ext_t + (size_t)s * ta.ext_sstride + (size_t)ci * W_
+                              : nullptr;
+#pragma unroll
+    for (int k = 0; k < WPW; ++k) {
+        const int wi = wave + EV_WAVES * k;
+        xe[k] = (ext && wi < W_) ? ext[wi] : 0u;
+    }
+
+    for (int i = threadIdx.x; i < EV_TS * NS_ / 4; i += 64 * EV_WAVES)
+        reinterpret_cast<int4 *>(acc)[i] = int4{0, 0, 0, 0};
+    if (threadIdx.x < 2 * EV_TS)
+        (&s_cnt[0][0])[threadIdx.x] = 0u;
+
+    // ---- 1. delivery: lane = axon 64 axb + lane; its sources' history words
+    // at t - d (up to FMAX of them as independent loads, the rest in a loop)
+#pragma unroll
+    for (int b = 0; b < BPW; ++b) {
+        const int axb = wave + EV_WAVES * b;
+        if (axb >= APW)
+            break;   // wave-uniform
+        auto row_of = [&](uint32_t e) -> const uint64_t * {
+            int slot = q_now - (int)(e & 15u) - 1;
+            if (slot < 0)
+                slot += n.Q;
+            return n.hist + ((size_t)slot * CN + (e >> 4)) * HG + tile;
+        };
+        uint32_t ent[FMAX];
+#pragma unroll
+        for (int k = 0; k < FMAX; ++k)
+            ent[k] = g_beg[b] + k < g_end[b] ? n.rtx_ent[g_beg[b] + k] : 0xFFFFFFFFu;
+        uint64_t m = 0;
+#pragma unroll
+        for (int k = 0; k < FMAX; ++k)
+            if (ent[k] != 0xFFFFFFFFu)
+                m |= *row_of(ent[k]);
+        for (uint32_t e = g_beg[b] + FMAX; e < g_end[b]; ++e)
+            m |= *row_of(n.rtx_ent[e]);
+        // lane (h, j) holds axon 64 axb + 32 h + j; after the transpose lane
+        // (h, i) holds axon word 2 axb + h of sample 32 g + i
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+            xw[32 * g + (lane & 31)][2 * axb + (lane >> 5)] = transpose32((uint32_t)(m >> (32 * g)), lane);
+    }
+    __syncthreads();
+
+    // ---- 2. scatter: lane = sample; wave w takes axon words w, w + 4, ...
+    unsigned events = 0, delivered = 0;
+#pragma unroll
+    for (int k = 0; k < WPW; ++k) {
+        const int wi = wave + EV_WAVES * k;
+        if (wi >= W_)
+            break;   // wave-uniform
+        const uint32_t xd = svalid ? xw[lane][wi] : 0u;
+        delivered += (unsigned)__popc(xd);
+        const uint32_t bits = xd | xe[k];
+        if (staged)
+            scatter_word<NS_>(bits, wi, lane, rp, (const uint16_t *)rows, acc, events);
         else
-            return hipErrorInvalidValue;
-        break;
+            scatter_word<NS_>(bits, wi, lane, rp, n.ecsr_ent + e_base, acc, events);
+    }
+    if (svalid && (events | delivered))
+        atomicAdd(&s_cnt[1][lane], events | (slice == 0 ? delivered << 20 : 0u));   // delivered counted once per core
+    __syncthreads();
+
+    // ---- 3. update, one neuron of the wave at a time for all 64 samples
+    unsigned em = 0, ro = 0, ou = 0;
+    uint64_t myword = 0;   // lane k < NPW: the history word of neuron j0 + k
+    int32_t *vout = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+        const int jl = wave * NPW + k;                // within the slice
+        const size_t cj = (size_t)c * n.N + j0 + k;   // uniform
+        const int32_t in = acc[acc_index<NS_>(lane, jl)];
+        int32_t fl = n.vmin;
+        bool lin = false;
+        if constexpr (EXT) {
+            fl = n.floor[cj];
+            lin = (n.linmask[cj >> 5] >> (cj & 31)) & 1u;
+        }
+        int32_t vn;
+        const bool fire = lif_update(vreg[k], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, fl, lin, vn) &&
+                          svalid;
+        __builtin_nontemporal_store(vn, vout + (size_t)k * n.S64);
+        const uint64_t word = __ballot(fire);
+        myword = lane == k ? word : myword;
+        const uint32_t bit = 1u << (cj & 31);
+        em += fire;
+        ro += fire && (n.coremask[cj >> 5] & bit);
+        ou += fire && (n.outmask[cj >> 5] & bit);
+    }
+    if (lane < NPW) {
+        const size_t g = (size_t)c * n.N + j0 + lane;
+        n.hist[((size_t)q_now * CN + g) * HG + tile] = myword;
+        const int oi = n.outidx[g];
+        if (oi >= 0)
+            reinterpret_cast<uint64_t *>(n.raster)[((size_t)r_row * n.Nout + oi) * HG + tile] = myword;
+    }
+    if (svalid && (em | ro | ou))
+        atomicAdd(&s_cnt[0][lane], em | (ro << 10) | (ou << 20));
+    __syncthreads();
+    if (wave == 0 && svalid) {
+        const unsigned a0 = s_cnt[0][lane], a1 = s_cnt[1][lane];
+        n.cring[((size_t)r_row * n.C * n.cnt_rows + (size_t)c * n.cnt_rows + slice) * n.S + s] =
+            pack_counts(a0 & 1023u, (a0 >> 10) & 1023u, a0 >> 20, a1 >> 20, a1 & 0xFFFFFu);
+    }
+}
+
+template <int A_, int NS_>
+static void launch_event_k(const DevNet &n, const TickArgs &a, hipStream_t st)
+{
+    const dim3 grid(n.C * n.slices * (n.S64 / EV_TS)), block(64 * EV_WAVES);
+    if (n.model_ext)
+        hipLaunchKernelGGL((k_integrate_event<A_, NS_, true>), grid, block, 0, st, n, a);
+    else
+        hipLaunchKernelGGL((k_integrate_event<A_, NS_, false>), grid, block, 0, st, n, a);
+}
+
+template <int A_>
+static hipError_t launch_event_a(const DevNet &n, const TickArgs &a, hipStream_t st)
+{
+    switch (sparse_slice_width(n.N)) {
+    case 64: launch_event_k<A_, 64>(n, a, st); break;
+    case 128: launch_event_k<A_, 128>(n, a, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int A_>
-static hipError_t launch_sparse_a(const DevNet &n, const TickArgs &a, int spw, hipStream_t st)
-{
-    switch (n.N) {
-    case 64: return launch_sparse_an<A_, 64>(n, a, spw, st);
-    case 128: return launch_sparse_an<A_, 128>(n, a, spw, st);
-    case 256: return launch_sparse_an<A_, 256>(n, a, spw, st);
-    case 512: return launch_sparse_an<A_, 512>(n, a, spw, st);
-    default: return hipErrorInvalidValue;
-    }
-}
-
 hipError_t launch_integrate_sparse(const DevNet &n, const TickArgs &a, int samples_per_wg, hipStream_t st)
 {
-    if (!sparse_shape_supported(n.A, n.N, n.G) || samples_per_wg <= 0 || samples_per_wg % SP_TS ||
-        samples_per_wg > SP_SPW_MAX || n.vlayout != VLAYOUT_SPARSE || n.S64 % SP_TS || n.S > n.S64)
+    if (!sparse_shape_supported(n.A, n.N, n.G) || samples_per_wg != EV_TS || n.vlayout != VLAYOUT_SPARSE ||
+        n.S64 % EV_TS || n.S > n.S64 || n.slices != n.N / sparse_slice_width(n.N) || n.cnt_rows != n.slices)
         return hipErrorInvalidValue;
     switch (n.A) {
-    case 64: return launch_sparse_a<64>(n, a, samples_per_wg, st);
-    case 128: return launch_sparse_a<128>(n, a, samples_per_wg, st);
-    case 256: return launch_sparse_a<256>(n, a, samples_per_wg, st);
-    case 512: return launch_sparse_a<512>(n, a, samples_per_wg, st);
+    case 64: return launch_event_a<64>(n, a, st);
+    case 128: return launch_event_a<128>(n, a, st);
+    case 256: return launch_event_a<256>(n, a, st);
+    case 512: return launch_event_a<512>(n, a, st);
     default: return hipErrorInvalidValue;
     }
 }

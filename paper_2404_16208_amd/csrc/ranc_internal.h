@@ -10,6 +10,8 @@
 //   typemask u32 [C][G][W]     bit b of typemask[c][g][w] = (type(c, 32w+b) == g)
 //   wts      i32 [C][G][N]     weight of neuron n for axon type g
 //   leak, thr, rst, vinit i32 [C][N]
+//   floor    i32 [C][N]        lowest potential a neuron that does not fire keeps (vmin: none)
+//   linmask  u32 [C][NW]       neurons whose spike subtracts the threshold (linear reset)
 //   coremask, outmask u32 [C][NW]  neurons whose destination is a core / the output bus
 //   outword  i32 [C][NW]       raster column of that neuron word, -1 if it has no output neuron
 //   outidx   i32 [C][N]        (MFMA path) index of the neuron among output-bus neurons, -1 if none
@@ -23,7 +25,10 @@
 //   degb     u32 [C][2][A/4]   (MFMA path) connected neurons per axon, low byte
 //                              plane then high byte plane, 4 axons per word
 //   planes   int8 MFMA B operand tiles (MFMA path), see kern_mfma.hip
-//   rtx_ptr  u32 [C*A + 1], rtx_ent u32 [E]  (MFMA path) the same routing table keyed by
+//   ecsr_ptr u32 [C][slices][A+1], ecsr_ent u16  (sparse path) per (core, slice of <= 128
+//                              neurons) one row per axon: its connected neurons of the slice,
+//                              entry = neuron within the slice | weight for the axon's type << 7
+//   rtx_ptr  u32 [C*A + 1], rtx_ent u32 [E]  (MFMA and sparse) the same routing table keyed by
 //                              destination axon: entries (source neuron c*N + n) << 4 | (delay - 1)
 // State:
 //   V        i32, layout by path:
@@ -31,16 +36,17 @@
 //              MFMA:  [C][N/32][S64/32][4][64][4]: brick (c, nb, g) holds 32 samples
 //                     x 32 neurons; element (q, lane l, e) = sample 32g + 8q + 4(l/32) + e,
 //                     neuron 32nb + l%32 (the MFMA result layout)
-//              sparse: [C][S64][N]
+//              sparse: [C][N][S64] (a neuron's samples contiguous)
 //   plain path:
 //   ring     u32 [Q][S][C][W]  scheduler: slot t%Q holds the axon spikes of tick t
 //   spk      u32 [S][C][NW]    spikes of the current tick
 //   raster   u32 [RT][S][Wout] output-bus spikes of tick t in row t%RT
 //   MFMA and sparse paths:
 //   hist     u64 [Q][C*N][HG]  spikes of tick t in slot t%Q; word (slot, neuron, i)
-//                              covers samples 64i .. 64i+63, bit p = sample
+//                              covers samples 64i .. 64i+63; MFMA: bit p = sample
 //                              64i + 32(p/32) + sigma(p%32) with
-//                              sigma(b) = 8((b%16)/4) + 4(b/16) + b%4
+//                              sigma(b) = 8((b%16)/4) + 4(b/16) + b%4; sparse: bit p =
+//                              sample 64i + p
 //   raster   u64 [RT][Nout][HG] output-bus spikes of tick t in row t%RT, words as hist
 //   both:
 //   cnt      u64 [C*cnt_rows][S][5]  emitted, routed, delivered, out, events (summed over
@@ -66,11 +72,14 @@ static constexpr long long RT_MAX_NEURONS = 1LL << 23;
 struct DevNet {
     int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, vlayout;
     int cnt_rows;   // counter rows per core, summed when read (plain: one per 64 neurons, MFMA: one per slice)
-    int slices;     // MFMA: neuron slices per core, one workgroup each (N / slices <= 256)
+    int slices;     // neuron slices per core, one workgroup each (MFMA: N / slices <= 256; sparse: <= 128)
     int32_t vmin, vmax;
+    int model_ext;  // extended potential update: clamp to [vmin, vmax], floor, linear reset
     // parameters
     const uint32_t *colbits, *typemask;
     const int32_t *wts, *leak, *thr, *rst, *vinit;
+    const int32_t *floor;      // [C][N] (vmin where the neuron has none)
+    const uint32_t *linmask;   // [C][NW] neurons in linear-reset mode
     const uint32_t *coremask, *outmask;
     const int32_t *outword, *in_index;
     const uint16_t *rt_dcnt;
@@ -80,6 +89,8 @@ struct DevNet {
     const uint4 *planes;
     const uint32_t *rtx_ptr, *rtx_ent;
     const uint64_t *hist_zero;   // HG zero words (a history row with no spikes)
+    const uint32_t *ecsr_ptr;    // sparse path: row starts [C][slices][A+1]
+    const uint16_t *ecsr_ent;    // sparse path: row entries (neuron in slice | weight << 7)
     // state
     int32_t *V;
     uint32_t *ring, *spk, *raster;
@@ -199,6 +210,8 @@ hipError_t launch_integrate_plain(const DevNet &n, const TickArgs &a, hipStream_
 hipError_t launch_integrate_sparse(const DevNet &n, const TickArgs &a, int samples_per_wg, hipStream_t st);
 bool sparse_shape_supported(int A, int N, int G);
 int sparse_max_samples_per_wg();
+int sparse_slice_width(int N);   // neurons per sparse-path workgroup
+int sparse_row_align();          // entries each slice's rows are aligned to
 hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes,
                                  int samples_per_wg, hipStream_t st);
 hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st);
@@ -216,7 +229,7 @@ hipError_t launch_route_batch(const BatchEntry *tab, int num, int total, int k, 
 hipError_t launch_advance_batch(const BatchEntry *tab, int num, int num_ticks, unsigned *queue, hipStream_t st);
 hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k, unsigned *queue,
                                        int workgroups, hipStream_t st);
-hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int clamp,
+hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int ext,
                                        hipStream_t st);
 RouteCfg route_default_cfg(const DevNet &n);
 int route_dmax(int max_delay);

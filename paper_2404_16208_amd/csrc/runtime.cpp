@@ -45,16 +45,18 @@ ranc_status hip_fail(hipError_t e, const char *what)
 enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
     R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
+    R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT,
     R_PARAMS_END,  // everything before this is uploaded once at load
     R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_NREG
 };
 
 struct Plan {
     int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, path, two, spw;
-    int slices;          // MFMA: neuron slices per core (one workgroup each)
+    int slices;          // MFMA and sparse: neuron slices per core (one workgroup each)
     int cnt_rows;        // counter rows per core
     long long E;         // routed (CORE) neurons
     long long ell_words; // u32 words of the wave-interleaved routing table
+    long long ecsr_entries; // sparse path: row entries, each slice's rows padded to sparse_row_align()
     size_t off[R_NREG], size[R_NREG], params_bytes, total;
 };
 
@@ -115,14 +117,28 @@ ranc_status validate(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t path
     for (size_t i = 0; i < (size_t)C * N * G; ++i)
         if (d->weight[i] < wlo || d->weight[i] > whi)
             return fail(RANC_ERANGE, "weight[%zu] = %d outside %d-bit range", i, d->weight[i], d->weight_bits);
+    const int leak_bits = d->leak_bits ? d->leak_bits : 32, reset_bits = d->reset_bits ? d->reset_bits : 32;
+    if (leak_bits < 2 || leak_bits > 32)
+        return fail(RANC_ERANGE, "leak_bits must be 0 or in [2, 32] (got %d)", d->leak_bits);
+    if (reset_bits < 2 || reset_bits > 32)
+        return fail(RANC_ERANGE, "reset_bits must be 0 or in [2, 32] (got %d)", d->reset_bits);
     const long long vlo = -(1LL << (d->potential_bits - 1)), vhi = (1LL << (d->potential_bits - 1)) - 1;
+    const long long llo = -(1LL << (leak_bits - 1)), lhi = (1LL << (leak_bits - 1)) - 1;
+    const long long rlo = std::max(vlo, -(1LL << (reset_bits - 1))), rhi = std::min(vhi, (1LL << (reset_bits - 1)) - 1);
     for (size_t i = 0; i < (size_t)C * N; ++i) {
-        if (d->reset[i] < vlo || d->reset[i] > vhi)
-            return fail(RANC_ERANGE, "reset[%zu] = %d outside the potential range", i, d->reset[i]);
+        if (d->reset[i] < rlo || d->reset[i] > rhi)
+            return fail(RANC_ERANGE, "reset[%zu] = %d outside the potential range and the %d-bit reset range", i,
+                        d->reset[i], reset_bits);
         if (d->v_init[i] < vlo || d->v_init[i] > vhi)
             return fail(RANC_ERANGE, "v_init[%zu] = %d outside the potential range", i, d->v_init[i]);
+        if (d->leak[i] < llo || d->leak[i] > lhi)
+            return fail(RANC_ERANGE, "leak[%zu] = %d outside the %d-bit leak range", i, d->leak[i], leak_bits);
         if (d->leak[i] < -(1 << 30) || d->leak[i] > (1 << 30))
             return fail(RANC_ERANGE, "leak[%zu] = %d outside [-2^30, 2^30]", i, d->leak[i]);
+        if (d->floor && (d->floor[i] < vlo || d->floor[i] > vhi))
+            return fail(RANC_ERANGE, "floor[%zu] = %d outside the potential range", i, d->floor[i]);
+        if (d->reset_mode && d->reset_mode[i] > RANC_RESET_LINEAR)
+            return fail(RANC_EINVAL, "reset_mode[%zu] = %u unknown", i, d->reset_mode[i]);
         const uint8_t k = d->dest_kind[i];
         if (k > RANC_DEST_OUT)
             return fail(RANC_EINVAL, "dest_kind[%zu] = %u unknown", i, k);
@@ -152,6 +168,21 @@ ranc_status validate(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t path
     return RANC_OK;
 }
 
+// Whether the network needs the extended potential update: potentials
+// narrower than 32 bits (clamp), a floor above the potential range's lowest
+// value, or linear-reset neurons.
+bool neuron_model_ext(const ranc_net_desc *d)
+{
+    if (d->potential_bits < 32)
+        return true;
+    const size_t CN = (size_t)d->num_cores * d->num_neurons;
+    const int32_t vmin = (int32_t)(-(1LL << (d->potential_bits - 1)));
+    for (size_t i = 0; i < CN; ++i)
+        if ((d->floor && d->floor[i] > vmin) || (d->reset_mode && d->reset_mode[i] == RANC_RESET_LINEAR))
+            return true;
+    return false;
+}
+
 ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t path, Plan &p)
 {
     ranc_status st = validate(d, S, RT, path);
@@ -178,7 +209,8 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     if (path == RANC_PATH_SPARSE && !sparse_shape_supported(p.A, p.N, p.G))
         return fail(RANC_EUNSUPPORTED, "sparse path does not support N=%d with G=%d", p.N, p.G);
     p.path = path;
-    p.slices = path == RANC_PATH_MFMA ? mfma_slices(p.A, p.N, p.two) : 1;
+    p.slices = path == RANC_PATH_MFMA ? mfma_slices(p.A, p.N, p.two)
+             : path == RANC_PATH_SPARSE ? p.N / sparse_slice_width(p.N) : 1;
     p.cnt_rows = path == RANC_PATH_PLAIN ? p.N / 64 : p.slices;
     // Samples per workgroup (sample-tiled paths), in 64-sample tiles: aim for
     // >= 2048 workgroups, but keep >= 4 tiles per workgroup where the batch
@@ -231,6 +263,19 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
                 any |= d->dest_kind[(size_t)c * p.N + 32 * w + b] == RANC_DEST_OUT;
             wout += any;
         }
+    p.ecsr_entries = 0;
+    if (path == RANC_PATH_SPARSE) {
+        // connections per neuron slice, each slice's rows padded
+        const int NW = p.N / 32, SW = sparse_slice_width(p.N) / 32, al = sparse_row_align();
+        for (int c = 0; c < p.C; ++c)
+            for (int sl = 0; sl < p.slices; ++sl) {
+                long long k = 0;
+                for (int a = 0; a < p.A; ++a)
+                    for (int w = sl * SW; w < (sl + 1) * SW; ++w)
+                        k += __builtin_popcount(d->crossbar[((size_t)c * p.A + a) * NW + w]);
+                p.ecsr_entries += (k + al - 1) / al * al;
+            }
+    }
     p.E = E;
     p.Wout = (int)wout;
     p.Nout = (int)nout;
@@ -238,10 +283,13 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     const bool mf = p.path == RANC_PATH_MFMA;
     const bool sp = p.path == RANC_PATH_SPARSE;
     const bool tiled = mf || sp;   // sample-tiled paths: spike history, neuron-major raster
-    p.size[R_COLBITS] = mf ? 0 : C * W * N * 4;
+    p.size[R_COLBITS] = tiled ? 0 : C * W * N * 4;
     p.size[R_TYPEMASK] = C * G * W * 4;
     p.size[R_WTS] = C * G * N * 4;
-    p.size[R_LEAK] = p.size[R_THR] = p.size[R_RST] = p.size[R_VINIT] = C * N * 4;
+    p.size[R_LEAK] = p.size[R_THR] = p.size[R_RST] = p.size[R_VINIT] = p.size[R_FLOOR] = C * N * 4;
+    p.size[R_LINMASK] = C * NW * 4;
+    p.size[R_ECSRPTR] = sp ? C * p.slices * (A + 1) * 4 : 0;
+    p.size[R_ECSRENT] = sp ? std::max<size_t>((size_t)p.ecsr_entries, 8) * 2 : 0;
     p.size[R_COREMASK] = p.size[R_OUTMASK] = p.size[R_OUTWORD] = C * NW * 4;
     p.size[R_ININDEX] = C * 4;
     p.size[R_RTDCNT] = tiled ? 0 : (C * W + 63) / 64 * 64 * route_dmax(p.D) * 2;
@@ -259,7 +307,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_SPK] = tiled ? 0 : (size_t)S * C * NW * 4;
     p.size[R_HIST] = tiled ? (size_t)p.Q * C * N * HG * 8 : 0;
     p.size[R_RASTER] = tiled ? (size_t)RT * p.Nout * HG * 8 : (size_t)RT * S * p.Wout * 4;
-    p.size[R_CNT] = C * p.cnt_rows * S * CNT_N * 8;   // plain: one row per 64 neurons, MFMA: per slice
+    p.size[R_CNT] = C * p.cnt_rows * S * CNT_N * 8;   // plain: one row per 64 neurons, MFMA and sparse: per slice
     p.size[R_CRING] = (size_t)RT * C * p.cnt_rows * S * 8;   // one packed word per row, sample and tick of a call
     p.size[R_TICK] = 16;
     p.size[R_BATCH] = BATCH_TABLE_BYTES;
@@ -305,6 +353,16 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
     memcpy(at(R_THR), d->threshold, (size_t)C * N * 4);
     memcpy(at(R_RST), d->reset, (size_t)C * N * 4);
     memcpy(at(R_VINIT), d->v_init, (size_t)C * N * 4);
+    // floor: the lowest potential of the range where none is given (a no-op
+    // after the clamp); linear-reset neurons as one bit per neuron
+    int32_t *fl = (int32_t *)at(R_FLOOR);
+    const int32_t vmin = (int32_t)(-(1LL << (d->potential_bits - 1)));
+    for (size_t i = 0; i < (size_t)C * N; ++i)
+        fl[i] = d->floor ? std::max(d->floor[i], vmin) : vmin;
+    uint32_t *lin = (uint32_t *)at(R_LINMASK);
+    if (d->reset_mode)
+        for (size_t i = 0; i < (size_t)C * N; ++i)
+            lin[i / 32] |= (uint32_t)(d->reset_mode[i] == RANC_RESET_LINEAR) << (i % 32);
     uint32_t *cmask = (uint32_t *)at(R_COREMASK), *omask = (uint32_t *)at(R_OUTMASK);
     int32_t *oword = (int32_t *)at(R_OUTWORD);
     out_words.clear();
@@ -382,6 +440,35 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
         for (size_t i = 0; i < (size_t)C * N; ++i)
             if (d->dest_kind[i] == RANC_DEST_CORE)
                 ent[fill[dest_of(i)]++] = ((uint32_t)i << 4) | (uint32_t)(d->dest_delay[i] - 1);
+    }
+    if (p.size[R_ECSRPTR]) {
+        // Sparse path: per (core, neuron slice) one row per axon, listing the
+        // slice's connected neurons with their weight for the axon's type:
+        // entry = neuron within the slice (7 bits) | weight (9 bits) << 7.
+        // Row starts are absolute; each slice's rows start on a multiple of
+        // sparse_row_align() entries (the padding entries are never read as
+        // connections).
+        uint32_t *ptr = (uint32_t *)at(R_ECSRPTR);
+        uint16_t *ent = (uint16_t *)at(R_ECSRENT);
+        const int NS = sparse_slice_width(N), al = sparse_row_align();
+        uint32_t off = 0;
+        for (int c = 0; c < C; ++c)
+            for (int sl = 0; sl < p.slices; ++sl) {
+                uint32_t *rp = ptr + ((size_t)c * p.slices + sl) * (A + 1);
+                for (int a = 0; a < A; ++a) {
+                    rp[a] = off;
+                    const int g = d->axon_type[(size_t)c * A + a];
+                    for (int jl = 0; jl < NS; ++jl) {
+                        const int j = sl * NS + jl;
+                        if (conn(c, a, j)) {
+                            const int w = d->weight[((size_t)c * N + j) * G + g];
+                            ent[off++] = (uint16_t)(jl | ((w & 511) << 7));
+                        }
+                    }
+                }
+                rp[A] = off;
+                off = (off + al - 1) / al * al;
+            }
     }
     if (p.size[R_DEGB]) {
         // connected neurons per axon within each neuron slice, as a low-byte
@@ -462,7 +549,7 @@ struct Batch {
     int num_ticks = 0;
     std::vector<BatchEntry> mf, pl;
     // MFMA shape classes (one launch each per tick), unless persistent
-    struct Group { int first, num, units, code, clamp; MfmaGroupArgs args; };
+    struct Group { int first, num, units, code, ext; MfmaGroupArgs args; };
     std::vector<Group> groups;
     // Phases: networks whose combined per-tick state fits the GPU's last-level
     // cache; all ticks of a phase run before the next phase starts. Groups
@@ -747,7 +834,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
     auto work = [](const BatchEntry &e) {
         return (double)e.spw * (e.n.N / e.n.slices) * (e.n.A + 64) * ((e.code & 1) ? 2 : 1);
     };
-    auto clamp = [](const BatchEntry &e) { return e.n.vmin == INT32_MIN && e.n.vmax == INT32_MAX ? 0 : 1; };
+    auto ext = [](const BatchEntry &e) { return e.n.model_ext; };
     long long mu = 0, pu = 0, ru = 0;
     if (persistent) {
         // one unit numbering, largest units first
@@ -764,14 +851,14 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
                 return x.phase < y.phase;
             if (x.code != y.code)
                 return x.code < y.code;
-            if (clamp(x) != clamp(y))
-                return clamp(x) < clamp(y);
+            if (ext(x) != ext(y))
+                return ext(x) < ext(y);
             return work(x) > work(y);
         });
         for (size_t i = 0; i < b.mf.size(); ++i) {
             BatchEntry &e = b.mf[i];
             if (b.groups.empty() || b.mf[b.groups.back().first].phase != e.phase ||
-                b.groups.back().code != e.code || b.groups.back().clamp != clamp(e) ||
+                b.groups.back().code != e.code || b.groups.back().ext != ext(e) ||
                 b.groups.back().num == MFMA_GROUP_MAX) {
                 b.groups.push_back(Batch::Group());
                 Batch::Group &g = b.groups.back();
@@ -779,7 +866,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
                 g.first = (int)i;
                 g.num = g.units = 0;
                 g.code = e.code;
-                g.clamp = clamp(e);
+                g.ext = ext(e);
             }
             Batch::Group &g = b.groups.back();
             if ((long long)g.units + e.units > INT32_MAX)
@@ -859,7 +946,7 @@ static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t
                 e = launch_integrate_mfma_batch(tmf, (int)b.mf.size(), b.mf_units, k, queue, b.mf_workgroups, s);
             for (int g = ph.g_first; e == hipSuccess && !b.persistent && g < ph.g_first + ph.g_num; ++g)
                 e = launch_integrate_mfma_group(b.groups[g].args, b.groups[g].units, k, b.groups[g].code,
-                                                b.groups[g].clamp, s);
+                                                b.groups[g].ext, s);
             if (e == hipSuccess && timed)
                 e = prof_end(lead, slot, s);
             if (e != hipSuccess)
@@ -1033,6 +1120,9 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.vlayout = p.path == RANC_PATH_MFMA ? VLAYOUT_BRICK : p.path == RANC_PATH_SPARSE ? VLAYOUT_SPARSE : VLAYOUT_CSN;
     n.vmin = (int32_t)(-(1LL << (desc->potential_bits - 1)));
     n.vmax = (int32_t)((1LL << (desc->potential_bits - 1)) - 1);
+    n.model_ext = neuron_model_ext(desc) ? 1 : 0;
+    n.floor = (const int32_t *)reg(R_FLOOR);
+    n.linmask = (const uint32_t *)reg(R_LINMASK);
     n.colbits = (const uint32_t *)reg(R_COLBITS);
     n.typemask = (const uint32_t *)reg(R_TYPEMASK);
     n.wts = (const int32_t *)reg(R_WTS);
@@ -1057,6 +1147,8 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.rtx_ptr = (const uint32_t *)reg(R_RTXPTR);
     n.rtx_ent = (const uint32_t *)reg(R_RTXENT);
     n.hist_zero = (const uint64_t *)reg(R_HZERO);
+    n.ecsr_ptr = (const uint32_t *)reg(R_ECSRPTR);
+    n.ecsr_ent = (const uint16_t *)reg(R_ECSRENT);
     n.raster = (uint32_t *)reg(R_RASTER);
     n.cnt = (unsigned long long *)reg(R_CNT);
     n.cring = (unsigned long long *)reg(R_CRING);
@@ -1210,10 +1302,12 @@ ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, 
         ++k;
     };
     if (mf) {
-        // neuron-major words of 64 samples; the bit of a sample inverts the
-        // spike-word order sigma(b) = 8((b%16)/4) + 4(b/16) + b%4
+        // neuron-major words of 64 samples; on the MFMA path the bit of a
+        // sample inverts the spike-word order sigma(b) = 8((b%16)/4) + 4(b/16)
+        // + b%4, on the sparse path it is the sample's index in its tile
         const int i = sample % 32;
-        const int bit = 32 * ((sample % 64) / 32) + 16 * ((i % 8) / 4) + 4 * (i / 8) + i % 4;
+        const int bit = p.path == RANC_PATH_SPARSE ? sample % 64
+                                                   : 32 * ((sample % 64) / 32) + 16 * ((i % 8) / 4) + 4 * (i / 8) + i % 4;
         const uint64_t *r64 = reinterpret_cast<const uint64_t *>(net->raster_host.data());
         for (int64_t t = tick_begin; t < tick_end; ++t) {
             const uint64_t *row = r64 + (size_t)(t % p.RT) * p.Nout * HG + sample / 64;
@@ -1264,6 +1358,11 @@ ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out)
                                     "reading potentials");
     if (st != RANC_OK)
         return st;
+    if (net->dn.vlayout == VLAYOUT_SPARSE) {   // [C][N][S64]
+        for (size_t cj = 0; cj < (size_t)p.C * p.N; ++cj)
+            out[cj] = net->v_host[cj * SV + sample];
+        return RANC_OK;
+    }
     if (!brick) {
         for (int c = 0; c < p.C; ++c)
             memcpy(out + (size_t)c * p.N, net->v_host.data() + ((size_t)c * SV + sample) * p.N, (size_t)p.N * 4);
