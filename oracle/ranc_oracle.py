@@ -126,14 +126,15 @@ def check(net, lib=None) -> int:
     return (lib if lib is not None else _load()).orc_check(C.byref(h.c))
 
 
-def build_variant(src_text: str, out_path: str):
+def build_variant(src_text: str, out_path: str, extra_flags=(), bind: bool = True):
     """Compile an alternative oracle source (used to check that the pins catch
-    deliberate mistakes planted in a copy of the oracle) and bind it."""
+    deliberate mistakes planted in a copy of the oracle, or to build the oracle
+    with the address and undefined-behaviour sanitizers) and bind it."""
     src = out_path + ".c"
     with open(src, "w") as f:
         f.write(src_text)
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", src, "-o", out_path])
-    return _bind(out_path)
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *extra_flags, src, "-o", out_path])
+    return _bind(out_path) if bind else out_path
 
 
 def source_text() -> str:
