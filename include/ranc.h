@@ -235,6 +235,26 @@ ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out);
 /* Counters of one sample. Synchronizes. */
 ranc_status ranc_read_counters(ranc_net *net, int32_t sample, ranc_counters *out);
 
+/*
+ * Packets per mesh link. In RANC a spike packet reaches its destination core
+ * hop by hop through the routers of the cores between, along x first, then
+ * along y (Sec. III-D, Fig. 2); the library delivers it directly, and counts,
+ * when asked, the links such a route takes.
+ * ranc_link_counts_enable: count (1) or stop counting (0) on every tick that
+ * later calls of ranc_run_ticks run on this handle (alone or in a batch).
+ * Counting adds one small kernel per tick. Changing the setting drops the
+ * handle's captured tick loops. Counts start at zero at load and at
+ * ranc_reset_state, and accumulate over the ticks run while enabled.
+ * ranc_read_links: the counts of one sample into out[C][4] (host): out[c][d]
+ * is the number of packets that left core c over its link in direction d
+ * (RANC_LINK_XPLUS, _XMINUS, _YPLUS, _YMINUS; +x is towards the core at
+ * x + 1, +y towards y + 1). Their sum is the total number of hops. A packet to
+ * a neuron's own core takes no link. Synchronizes the stream of the last run.
+ */
+enum { RANC_LINK_XPLUS = 0, RANC_LINK_XMINUS = 1, RANC_LINK_YPLUS = 2, RANC_LINK_YMINUS = 3 };
+ranc_status ranc_link_counts_enable(ranc_net *net, int32_t enable);
+ranc_status ranc_read_links(ranc_net *net, int32_t sample, int64_t *out);
+
 /* Next tick to be simulated (ticks run since load or reset). */
 ranc_status ranc_current_tick(const ranc_net *net, int64_t *tick);
 

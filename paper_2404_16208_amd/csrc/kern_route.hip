@@ -397,7 +397,7 @@ __global__ void k_fill_u32(uint32_t *p, size_t count)
         p[i] = 0u;
 }
 
-hipError_t launch_reset_state(const DevNet &n, hipStream_t st)
+hipError_t launch_reset_state(const DevNet &n, const LinkArgs &l, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reset_potentials, dim3(2048), dim3(256), 0, st, n);
     const bool hist = n.vlayout != VLAYOUT_CSN;
@@ -415,6 +415,8 @@ hipError_t launch_reset_state(const DevNet &n, hipStream_t st)
     if (raster_words)
         hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, n.raster, raster_words);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, (uint32_t *)n.cnt, cnt_words);
+    if (l.d)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, st, (uint32_t *)l.d, (size_t)4 * n.C * n.S64 * 2);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)n.tick, (size_t)4);
     return hipGetLastError();
 }

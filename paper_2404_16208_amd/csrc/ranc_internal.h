@@ -30,6 +30,9 @@
 //                              entry = neuron within the slice | weight for the axon's type << 7
 //   rtx_ptr  u32 [C*A + 1], rtx_ent u32 [E]  (MFMA and sparse) the same routing table keyed by
 //                              destination axon: entries (source neuron c*N + n) << 4 | (delay - 1)
+//   linkrec  int2 [C][N]       mesh path ends of each neuron's packets (kern_links.hip): x = -1
+//                              if the packet takes no x hop, else 2 * (core at (xd, ys)) + (dx < 0);
+//                              y = -1 if it takes no y hop, else 2 * (core at (xd, yd)) + (dy < 0)
 // State:
 //   V        i32, layout by path:
 //              plain: [C][S][N]
@@ -51,6 +54,8 @@
 //   both:
 //   cnt      u64 [C*cnt_rows][S][5]  emitted, routed, delivered, out, events (summed over
 //                              the rows of a core when read)
+//   linkd    i64 [4][C][S64]   difference arrays of the packets per mesh link (+x, -x, +y, -y),
+//                              summed along mesh rows / columns when read
 //   tick     i32 [4]           scheduler slot (t % Q) and raster row (t % RT) of the
 //                              first tick of the next call, and t as two u32 halves;
 //                              kept on the device so a captured tick loop replays
@@ -98,6 +103,13 @@ struct DevNet {
     unsigned long long *cnt;     // totals [C][cnt_rows][S][CNT_N]
     unsigned long long *cring;   // per-tick packed counts [RT][C * cnt_rows][S], folded per call
     int *tick;
+};
+
+// Mesh link statistics (kern_links.hip); kept out of DevNet, which travels
+// in batched kernels' arguments.
+struct LinkArgs {
+    const int2 *rec;   // linkrec [C][N]
+    long long *d;      // linkd [4][C][S64]
 };
 
 // Per-tick launch arguments: the tick's position k in the call (the tick is
@@ -215,9 +227,10 @@ int sparse_row_align();          // entries each slice's rows are aligned to
 hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes,
                                  int samples_per_wg, hipStream_t st);
 hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st);
-hipError_t launch_reset_state(const DevNet &n, hipStream_t st);
+hipError_t launch_reset_state(const DevNet &n, const LinkArgs &l, hipStream_t st);
 hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st);
 hipError_t launch_fold_counts(const DevNet &n, int num_ticks, hipStream_t st);
+hipError_t launch_link_counts(const DevNet &n, const LinkArgs &l, int k, hipStream_t st);
 bool mfma_shape_supported(int A, int N, int two_planes);
 int mfma_width(int A, int N, int two_planes);   // neurons per MFMA workgroup (128 or 256)
 int mfma_slices(int A, int N, int two_planes);  // MFMA workgroups per core and sample chunk

@@ -45,13 +45,14 @@ ranc_status hip_fail(hipError_t e, const char *what)
 enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
     R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
-    R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT,
+    R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT, R_LINKREC,
     R_PARAMS_END,  // everything before this is uploaded once at load
-    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_NREG
+    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_LINKD, R_NREG
 };
 
 struct Plan {
     int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, path, two, spw;
+    int grid_w, grid_h;  // mesh size
     int slices;          // MFMA and sparse: neuron slices per core (one workgroup each)
     int cnt_rows;        // counter rows per core
     long long E;         // routed (CORE) neurons
@@ -200,6 +201,8 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.S64 = (S + 63) / 64 * 64;
     p.RT = RT;
     p.Cin = d->num_input_cores;
+    p.grid_w = d->grid_w;
+    p.grid_h = d->grid_h;
     p.two = d->weight_bits > 8;
     if (path == RANC_PATH_AUTO)
         path = (S >= 64 && mfma_shape_supported(p.A, p.N, p.two)) ? RANC_PATH_MFMA : RANC_PATH_PLAIN;
@@ -312,6 +315,8 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_TICK] = 16;
     p.size[R_BATCH] = BATCH_TABLE_BYTES;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
+    p.size[R_LINKREC] = C * N * 8;
+    p.size[R_LINKD] = (size_t)4 * C * p.S64 * 8;
     size_t off = 0;
     for (int r = 0; r < R_NREG; ++r) {
         if (r == R_PARAMS_END)
@@ -486,6 +491,25 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
                     db[(r * 2 + 1) * A + a] = (uint8_t)(k >> 8);
                 }
     }
+    {
+        // mesh path ends of each neuron's packets (x first, then y; see
+        // kern_links.hip): no hop is -1, else 2 * end core + (negative step)
+        int32_t *lr = (int32_t *)at(R_LINKREC);
+        for (size_t i = 0; i < (size_t)C * N; ++i) {
+            int32_t xc = -1, yc = -1;
+            if (d->dest_kind[i] == RANC_DEST_CORE) {
+                const int c = (int)(i / N), gw = d->grid_w;
+                const int xs = c % gw, ys = c / gw, dx = d->dest_dx[i], dy = d->dest_dy[i];
+                const int xd = xs + dx, yd = ys + dy;
+                if (dx != 0)
+                    xc = 2 * (ys * gw + xd) + (dx < 0);
+                if (dy != 0)
+                    yc = 2 * (yd * gw + xd) + (dy < 0);
+            }
+            lr[2 * i] = xc;
+            lr[2 * i + 1] = yc;
+        }
+    }
     if (p.size[R_OUTIDX]) {
         int32_t *oi = (int32_t *)at(R_OUTIDX);
         int32_t next = 0;
@@ -557,6 +581,8 @@ struct Batch {
     // pl_num), numbered from 0 within the phase. One phase when persistent.
     struct Phase { int g_first, g_num, pl_first, pl_num, pl_units, rt_units; };
     std::vector<Phase> phases;
+    std::vector<std::vector<int>> phase_links;   // per phase: networks (index in nets) counting mesh links
+    std::vector<char> links;                     // links_on of each network when the batch was set up
     bool persistent = false;
     int mf_units = 0, pl_units = 0, rt_units = 0, mf_workgroups = 0;
     size_t rt_lds = 0;
@@ -584,6 +610,10 @@ struct ranc_net {
     std::vector<int32_t> v_host;       // mirror of the potentials
     uint64_t cnt_version = 0;
     std::vector<unsigned long long> cnt_host; // mirror of the counters
+    LinkArgs lk{nullptr, nullptr};     // mesh link path ends and counts in the workspace
+    bool links_on = false;             // count packets per mesh link on every tick run
+    uint64_t links_version = 0;
+    std::vector<long long> links_host; // mirror of the link difference arrays
 };
 
 static hipError_t prof_begin(ranc_net *net, int kind, hipStream_t s, int *slot)
@@ -672,6 +702,11 @@ static ranc_status queue_ticks(ranc_net *net, const uint32_t *base, int num_tick
                 e = prof_end(net, slot, s);
             if (e != hipSuccess)
                 return hip_fail(e, "launching routing");
+        }
+        if (net->links_on) {
+            e = launch_link_counts(net->dn, net->lk, k, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "launching the mesh link count");
         }
     }
     hipError_t e = launch_fold_counts(net->dn, num_ticks, s);
@@ -892,6 +927,13 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
     for (int i = 0; i < num; ++i)
         nphases = std::max(nphases, phase_of[i] + 1);
     b.phases.assign(nphases, Batch::Phase{0, 0, 0, 0, 0, 0});
+    b.phase_links.assign(nphases, std::vector<int>());
+    b.links.assign(num, 0);
+    for (int i = 0; i < num; ++i) {
+        b.links[i] = nets[i]->links_on ? 1 : 0;
+        if (nets[i]->links_on)
+            b.phase_links[phase_of[i]].push_back(i);
+    }
     for (size_t g = b.groups.size(); g-- > 0;) {
         Batch::Phase &ph = b.phases[b.mf[b.groups[g].first].phase];
         ph.g_first = (int)g;
@@ -968,6 +1010,11 @@ static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t
             if (e != hipSuccess)
                 return hip_fail(e, "launching batch integration (plain)");
         }
+        for (int i : b.phase_links[&ph - b.phases.data()]) {
+            e = launch_link_counts(b.nets[i]->dn, b.nets[i]->lk, k, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "launching the mesh link count");
+        }
     }
     hipError_t e = hipSuccess;
     for (size_t i = 0; e == hipSuccess && i < b.nets.size(); ++i)
@@ -993,7 +1040,7 @@ static ranc_status run_batch(ranc_net *const *nets, int num, const uint32_t *con
     bool same = b.num_ticks == num_ticks && b.persistent == persistent && (int)b.nets.size() == num &&
                 std::equal(b.nets.begin(), b.nets.end(), nets) && std::equal(b.bases.begin(), b.bases.end(), bases);
     for (int i = 0; same && i < num; ++i)
-        same = b.uids[i] == nets[i]->uid;
+        same = b.uids[i] == nets[i]->uid && b.links[i] == (nets[i]->links_on ? 1 : 0);
     if (!same) {
         if (b.exec)
             hipGraphExecDestroy(b.exec);
@@ -1025,6 +1072,8 @@ static ranc_status run_batch(ranc_net *const *nets, int num, const uint32_t *con
         b.pl = std::move(nb.pl);
         b.groups = std::move(nb.groups);
         b.phases = std::move(nb.phases);
+        b.phase_links = std::move(nb.phase_links);
+        b.links = std::move(nb.links);
         b.persistent = nb.persistent;
         b.mf_units = nb.mf_units;
         b.pl_units = nb.pl_units;
@@ -1070,6 +1119,8 @@ static ranc_status run_batch(ranc_net *const *nets, int num, const uint32_t *con
         return hip_fail(e, "launching the batch tick loop");
     return RANC_OK;
 }
+
+static void drop_graphs(ranc_net *net);
 
 extern "C" {
 
@@ -1153,6 +1204,8 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.cnt = (unsigned long long *)reg(R_CNT);
     n.cring = (unsigned long long *)reg(R_CRING);
     n.tick = (int *)reg(R_TICK);
+    net->lk.rec = (const int2 *)reg(R_LINKREC);
+    net->lk.d = (long long *)reg(R_LINKD);
     std::vector<uint8_t> host;
     pack_params(desc, p, host, net->out_words);
     for (size_t i = 0; i < (size_t)p.C * p.N; ++i)
@@ -1163,7 +1216,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(net->ws, host.data(), p.params_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = launch_reset_state(n, s);
+        e = launch_reset_state(n, net->lk, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -1405,6 +1458,58 @@ ranc_status ranc_read_counters(ranc_net *net, int32_t sample, ranc_counters *out
     return RANC_OK;
 }
 
+ranc_status ranc_link_counts_enable(ranc_net *net, int32_t enable)
+{
+    if (!net)
+        return fail(RANC_EINVAL, "net is NULL");
+    if (enable != 0 && enable != 1)
+        return fail(RANC_EINVAL, "enable must be 0 or 1");
+    if (net->links_on != (enable == 1)) {
+        drop_graphs(net);
+        net->links_on = enable == 1;
+    }
+    return RANC_OK;
+}
+
+ranc_status ranc_read_links(ranc_net *net, int32_t sample, int64_t *out)
+{
+    if (!net || !out)
+        return fail(RANC_EINVAL, "net or out is NULL");
+    const Plan &p = net->p;
+    if (sample < 0 || sample >= p.S)
+        return fail(RANC_EINVAL, "sample %d out of range", sample);
+    net->links_host.resize((size_t)4 * p.C * p.S64);
+    ranc_status st = refresh_mirror(net, net->lk.d, net->links_host.size() * 8, net->links_host.data(),
+                                    net->links_version, "reading mesh link counts");
+    if (st != RANC_OK)
+        return st;
+    // difference arrays [dir][core][S64] -> counts: prefix sums along each
+    // mesh row (+x ascending x, -x descending), column (+y, -y)
+    const int gw = p.grid_w, gh = p.grid_h;
+    auto dv = [&](int dir, int core) { return net->links_host[((size_t)dir * p.C + core) * p.S64 + sample]; };
+    for (int y = 0; y < gh; ++y) {
+        long long up = 0, down = 0;
+        for (int x = 0; x < gw; ++x) {
+            up += dv(RANC_LINK_XPLUS, y * gw + x);
+            out[(size_t)(y * gw + x) * 4 + RANC_LINK_XPLUS] = up;
+            const int xr = gw - 1 - x;
+            down += dv(RANC_LINK_XMINUS, y * gw + xr);
+            out[(size_t)(y * gw + xr) * 4 + RANC_LINK_XMINUS] = down;
+        }
+    }
+    for (int x = 0; x < gw; ++x) {
+        long long up = 0, down = 0;
+        for (int y = 0; y < gh; ++y) {
+            up += dv(RANC_LINK_YPLUS, y * gw + x);
+            out[(size_t)(y * gw + x) * 4 + RANC_LINK_YPLUS] = up;
+            const int yr = gh - 1 - y;
+            down += dv(RANC_LINK_YMINUS, yr * gw + x);
+            out[(size_t)(yr * gw + x) * 4 + RANC_LINK_YMINUS] = down;
+        }
+    }
+    return RANC_OK;
+}
+
 ranc_status ranc_current_tick(const ranc_net *net, int64_t *tick)
 {
     if (!net || !tick)
@@ -1463,7 +1568,7 @@ ranc_status ranc_reset_state(ranc_net *net, void *stream)
     if (!net)
         return fail(RANC_EINVAL, "net is NULL");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_reset_state(net->dn, s);
+    hipError_t e = launch_reset_state(net->dn, net->lk, s);
     if (e != hipSuccess)
         return hip_fail(e, "resetting state");
     net->tick = 0;
@@ -1572,9 +1677,9 @@ ranc_status ranc_autotune(ranc_net *net, const uint32_t *inputs, uint32_t flags,
         p.spw = c.spw;
         net->rcfg = c.rc;
         // one untimed pass, then a timed pass, each from the initial state
-        e = launch_reset_state(net->dn, s);
+        e = launch_reset_state(net->dn, net->lk, s);
         if (e == hipSuccess && (st = queue_ticks(net, base, num_ticks, s, false)) == RANC_OK)
-            e = launch_reset_state(net->dn, s);
+            e = launch_reset_state(net->dn, net->lk, s);
         if (e == hipSuccess && st == RANC_OK)
             e = hipEventRecord(e0, s);
         if (e == hipSuccess && st == RANC_OK && (st = queue_ticks(net, base, num_ticks, s, false)) == RANC_OK)
@@ -1599,7 +1704,7 @@ ranc_status ranc_autotune(ranc_net *net, const uint32_t *inputs, uint32_t flags,
     if (st != RANC_OK)
         return st;
     if (e == hipSuccess)
-        e = launch_reset_state(net->dn, s);
+        e = launch_reset_state(net->dn, net->lk, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess)

@@ -31,7 +31,9 @@ RANC_BATCH_PERSISTENT = 4
 EXPORTED = ("ranc_last_error", "ranc_workspace_bytes", "ranc_load_network", "ranc_run_ticks",
             "ranc_read_spikes", "ranc_read_potentials", "ranc_read_counters", "ranc_current_tick",
             "ranc_get_path", "ranc_profile_enable", "ranc_profile_read", "ranc_reset_state", "ranc_free",
-            "ranc_autotune", "ranc_set_launch_shape", "ranc_get_launch_shape")
+            "ranc_autotune", "ranc_set_launch_shape", "ranc_get_launch_shape",
+            "ranc_link_counts_enable", "ranc_read_links")
+RANC_LINK_XPLUS, RANC_LINK_XMINUS, RANC_LINK_YPLUS, RANC_LINK_YMINUS = 0, 1, 2, 3
 
 
 class RancError(RuntimeError):
@@ -89,6 +91,8 @@ def _load_lib():
         "ranc_read_potentials": (C.c_int, [vp, i32, vp]),
         "ranc_read_counters": (C.c_int, [vp, i32, C.POINTER(ranc_counters)]),
         "ranc_current_tick": (C.c_int, [vp, C.POINTER(i64)]),
+        "ranc_link_counts_enable": (C.c_int, [vp, i32]),
+        "ranc_read_links": (C.c_int, [vp, i32, vp]),
         "ranc_get_path": (C.c_int, [vp, C.POINTER(i32)]),
         "ranc_profile_enable": (C.c_int, [vp, i32]),
         "ranc_profile_read": (C.c_int, [vp, C.POINTER(ranc_profile)]),
@@ -196,6 +200,17 @@ def ranc_read_counters(handle: int, sample: int) -> dict:
     c = ranc_counters()
     _check(_lib.ranc_read_counters(handle, sample, C.byref(c)))
     return {k: int(getattr(c, k)) for k, _ in ranc_counters._fields_}
+
+
+def ranc_link_counts_enable(handle: int, enable: bool) -> None:
+    _check(_lib.ranc_link_counts_enable(handle, 1 if enable else 0))
+
+
+def ranc_read_links(handle: int, sample: int, C_: int) -> np.ndarray:
+    """Packets per mesh link of one sample, int64 [C, 4] (+x, -x, +y, -y)."""
+    out = np.empty((C_, 4), dtype=np.int64)
+    _check(_lib.ranc_read_links(handle, sample, out.ctypes.data))
+    return out
 
 
 def ranc_current_tick(handle: int) -> int:
@@ -320,6 +335,16 @@ class RancNet:
 
     def counters(self, sample: int) -> dict:
         return ranc_read_counters(self.handle, sample)
+
+    def count_links(self, enable: bool = True):
+        """Count packets per mesh link on the ticks run from now on."""
+        ranc_link_counts_enable(self.handle, enable)
+        return self
+
+    def links(self, sample: int) -> np.ndarray:
+        """Packets per mesh link of one sample since load or reset, int64 [C, 4]:
+        out of core c towards +x, -x, +y, -y."""
+        return ranc_read_links(self.handle, sample, self.net.num_cores)
 
     def reset(self):
         ranc_reset_state(self.handle, self.stream.cuda_stream)

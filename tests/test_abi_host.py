@@ -283,3 +283,10 @@ def test_neuron_model_widths_at_their_limits_accepted(R):
     net.reset[:] = np.where(np.arange(64) % 2, 3, -4)
     st, msg, _ = ws_status(R, net)
     assert st == R.RANC_OK, msg
+
+
+
+def test_link_calls_reject_null_handles(R):
+    assert R._lib.ranc_link_counts_enable(None, 1) == R.RANC_EINVAL
+    out = np.zeros((4, 4), np.int64)
+    assert R._lib.ranc_read_links(None, 0, out.ctypes.data) == R.RANC_EINVAL
