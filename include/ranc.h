@@ -13,7 +13,9 @@
  *
  * The library simulates S independent instances ("samples") of one network
  * side by side on one GPU. All device memory it uses lives in a
- * caller-provided workspace; the library never allocates device memory.
+ * caller-provided workspace (or, for ranc_load_network_static, in a
+ * fixed-size workspace held in the library's code object); the library never
+ * allocates device memory.
  *
  * Conventions for every call:
  *   - the return value is a ranc_status; on failure ranc_last_error() gives a
@@ -306,6 +308,30 @@ ranc_status ranc_autotune(ranc_net *net, const uint32_t *inputs, uint32_t flags,
  * captured tick loops; the simulation state is unchanged. */
 ranc_status ranc_set_launch_shape(ranc_net *net, const ranc_tune *shape);
 ranc_status ranc_get_launch_shape(const ranc_net *net, ranc_tune *out);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): load a
+ * network as ranc_load_network does, into a workspace the library holds
+ * instead of a caller-provided one. The library keeps one such workspace of
+ * RANC_STATIC_WORKSPACE_BYTES bytes per device, in its code object (each
+ * device the library runs on holds it until the process ends); the network
+ * goes to the current device's. Allocates no device memory and calls no
+ * allocating HIP or library routine.
+ * Errors: RANC_ENOMEM if the network, num_samples and max_ticks_per_call
+ * need more than RANC_STATIC_WORKSPACE_BYTES (ranc_workspace_bytes gives the
+ * need); RANC_ESTATE while another handle loaded this way on the same device
+ * has not been freed (one handle per device at a time; ranc_free releases the
+ * workspace); RANC_EUNSUPPORTED for a device index >= 64; otherwise as
+ * ranc_load_network. The workspace keeps what the previous handle left in
+ * it; loading overwrites everything the simulation reads. Calls on a handle
+ * loaded this way behave exactly as on any other handle, and as for any
+ * handle, calls that overlap on it (from several threads or streams) race.
+ */
+#define RANC_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+ranc_status ranc_load_network_static(const ranc_net_desc *desc, int32_t num_samples,
+                                     int32_t max_ticks_per_call, int32_t path, void *stream,
+                                     ranc_net **out);
 
 /* Return every instance to its initial state (queued on `stream`). */
 ranc_status ranc_reset_state(ranc_net *net, void *stream);

@@ -248,4 +248,12 @@ RouteCfg route_default_cfg(const DevNet &n);
 int route_dmax(int max_delay);
 int mfma_max_samples_per_wg();
 
+// The library-held workspace of ranc_load_network_static (static_ws.hip).
+// static_ws_claim looks up the device address of device `dev`'s array (the
+// first time, with `dev` current) and claims it for one handle; *held is set
+// (and *addr left null) while another handle holds it.
+constexpr int STATIC_WS_MAX_DEVICES = 64;
+hipError_t static_ws_claim(int dev, void **addr, bool *held);
+void static_ws_release(int dev);
+
 }  // namespace ranc

@@ -614,6 +614,7 @@ struct ranc_net {
     bool links_on = false;             // count packets per mesh link on every tick run
     uint64_t links_version = 0;
     std::vector<long long> links_host; // mirror of the link difference arrays
+    int static_dev = -1;               // device whose library-held workspace this handle holds, or -1
 };
 
 static hipError_t prof_begin(ranc_net *net, int kind, hipStream_t s, int *slot)
@@ -1246,6 +1247,43 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     return RANC_OK;
 }
 
+ranc_status ranc_load_network_static(const ranc_net_desc *desc, int32_t num_samples, int32_t max_ticks_per_call,
+                                     int32_t path, void *stream, ranc_net **out)
+{
+    if (!out)
+        return fail(RANC_EINVAL, "out is NULL");
+    *out = nullptr;
+    Plan p;
+    ranc_status st = make_plan(desc, num_samples, max_ticks_per_call, path, p);
+    if (st != RANC_OK)
+        return st;
+    if (p.total > RANC_STATIC_WORKSPACE_BYTES)
+        return fail(RANC_ENOMEM, "the network needs %zu bytes of workspace; the library-held workspace has %zu",
+                    p.total, (size_t)RANC_STATIC_WORKSPACE_BYTES);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "querying the current device");
+    if (dev < 0 || dev >= STATIC_WS_MAX_DEVICES)
+        return fail(RANC_EUNSUPPORTED, "device %d: the library-held workspace exists for devices 0..%d", dev,
+                    STATIC_WS_MAX_DEVICES - 1);
+    void *ws = nullptr;
+    bool held = false;
+    e = static_ws_claim(dev, &ws, &held);
+    if (e != hipSuccess)
+        return hip_fail(e, "looking up the library-held workspace");
+    if (held)
+        return fail(RANC_ESTATE, "the library-held workspace of device %d is used by a handle not yet freed", dev);
+    st = ranc_load_network(desc, num_samples, max_ticks_per_call, path, ws, RANC_STATIC_WORKSPACE_BYTES, stream,
+                           out);
+    if (st != RANC_OK) {
+        static_ws_release(dev);
+        return st;
+    }
+    (*out)->static_dev = dev;
+    return RANC_OK;
+}
+
 ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32_t *const *inputs, uint32_t flags,
                            int32_t num_ticks, void *stream)
 {
@@ -1780,6 +1818,8 @@ void ranc_free(ranc_net *net)
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
     }
+    if (net->static_dev >= 0)
+        static_ws_release(net->static_dev);
     delete net;
 }
 

@@ -31,9 +31,10 @@ RANC_BATCH_PERSISTENT = 4
 EXPORTED = ("ranc_last_error", "ranc_workspace_bytes", "ranc_load_network", "ranc_run_ticks",
             "ranc_read_spikes", "ranc_read_potentials", "ranc_read_counters", "ranc_current_tick",
             "ranc_get_path", "ranc_profile_enable", "ranc_profile_read", "ranc_reset_state", "ranc_free",
-            "ranc_autotune", "ranc_set_launch_shape", "ranc_get_launch_shape",
+            "ranc_autotune", "ranc_set_launch_shape", "ranc_get_launch_shape", "ranc_load_network_static",
             "ranc_link_counts_enable", "ranc_read_links")
 RANC_LINK_XPLUS, RANC_LINK_XMINUS, RANC_LINK_YPLUS, RANC_LINK_YMINUS = 0, 1, 2, 3
+RANC_STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 class RancError(RuntimeError):
@@ -86,6 +87,7 @@ def _load_lib():
         "ranc_last_error": (C.c_char_p, []),
         "ranc_workspace_bytes": (C.c_int, [C.POINTER(ranc_net_desc), i32, i32, i32, C.POINTER(sz)]),
         "ranc_load_network": (C.c_int, [C.POINTER(ranc_net_desc), i32, i32, i32, vp, sz, vp, C.POINTER(vp)]),
+        "ranc_load_network_static": (C.c_int, [C.POINTER(ranc_net_desc), i32, i32, i32, vp, C.POINTER(vp)]),
         "ranc_run_ticks": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp), u32, i32, vp]),
         "ranc_read_spikes": (C.c_int, [vp, i32, i64, i64, vp, i64, C.POINTER(i64)]),
         "ranc_read_potentials": (C.c_int, [vp, i32, vp]),
@@ -162,6 +164,13 @@ def ranc_load_network(desc: Desc, num_samples: int, max_ticks_per_call: int, pat
     h = C.c_void_p(0)
     _check(_lib.ranc_load_network(C.byref(desc.c), num_samples, max_ticks_per_call, path, workspace_ptr,
                                   workspace_bytes, stream, C.byref(h)))
+    return int(h.value)
+
+
+def ranc_load_network_static(desc: Desc, num_samples: int, max_ticks_per_call: int, path: int, stream: int) -> int:
+    h = C.c_void_p(0)
+    _check(_lib.ranc_load_network_static(C.byref(desc.c), num_samples, max_ticks_per_call, path, stream,
+                                         C.byref(h)))
     return int(h.value)
 
 
@@ -267,9 +276,12 @@ def ranc_free(handle: int) -> None:
 # ------------------------------------------------------------- convenience
 
 class RancNet:
-    """A loaded network with its torch-owned workspace on the current CUDA device."""
+    """A loaded network with its torch-owned workspace on the current CUDA device
+    (or, with ``static_workspace``, in the library-held workspace of that
+    device: ranc_load_network_static)."""
 
-    def __init__(self, net, num_samples: int, max_ticks_per_call: int, path="auto", device="cuda"):
+    def __init__(self, net, num_samples: int, max_ticks_per_call: int, path="auto", device="cuda",
+                 static_workspace: bool = False):
         import torch
 
         self.net = net
@@ -277,12 +289,18 @@ class RancNet:
         self.RT = max_ticks_per_call
         self.desc = Desc(net)
         p = PATHS[path] if isinstance(path, str) else int(path)
-        nbytes = ranc_workspace_bytes(self.desc, num_samples, max_ticks_per_call, p)
-        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
-        self.stream = torch.cuda.current_stream(self.workspace.device)
-        self.handle = ranc_load_network(self.desc, num_samples, max_ticks_per_call, p,
-                                        self.workspace.data_ptr(), self.workspace.numel(),
-                                        self.stream.cuda_stream)
+        if static_workspace:
+            self.workspace = None
+            self.stream = torch.cuda.current_stream(torch.device(device))
+            self.handle = ranc_load_network_static(self.desc, num_samples, max_ticks_per_call, p,
+                                                   self.stream.cuda_stream)
+        else:
+            nbytes = ranc_workspace_bytes(self.desc, num_samples, max_ticks_per_call, p)
+            self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            self.stream = torch.cuda.current_stream(self.workspace.device)
+            self.handle = ranc_load_network(self.desc, num_samples, max_ticks_per_call, p,
+                                            self.workspace.data_ptr(), self.workspace.numel(),
+                                            self.stream.cuda_stream)
         self.path = {RANC_PATH_PLAIN: "plain", RANC_PATH_MFMA: "mfma", RANC_PATH_SPARSE: "sparse"}[ranc_get_path(self.handle)]
 
     def close(self):

@@ -290,3 +290,23 @@ def test_link_calls_reject_null_handles(R):
     assert R._lib.ranc_link_counts_enable(None, 1) == R.RANC_EINVAL
     out = np.zeros((4, 4), np.int64)
     assert R._lib.ranc_read_links(None, 0, out.ctypes.data) == R.RANC_EINVAL
+
+
+def test_static_load_rejects_bad_arguments(R):
+    """Checks made before any device call: a null output, an unsupported shape,
+    and a network too large for the library-held workspace."""
+    d = R.Desc(W.mnist_net(0))
+    h = ctypes.c_void_p(0)
+    assert R._lib.ranc_load_network_static(ctypes.byref(d.c), 4, 8, R.RANC_PATH_MFMA, None, None) == R.RANC_EINVAL
+    assert R.ranc_workspace_bytes(d, 64, 32, R.RANC_PATH_MFMA) > R.RANC_STATIC_WORKSPACE_BYTES
+    st = R._lib.ranc_load_network_static(ctypes.byref(d.c), 64, 32, R.RANC_PATH_MFMA, None, ctypes.byref(h))
+    assert st == R.RANC_ENOMEM and not h.value
+    assert "library-held workspace" in R.ranc_last_error()
+    d.c.num_axons = 96
+    assert R._lib.ranc_load_network_static(ctypes.byref(d.c), 4, 8, 0, None, ctypes.byref(h)) == R.RANC_EUNSUPPORTED
+
+
+def test_static_workspace_size_matches_header(R):
+    text = open(os.path.join(ROOT, "include", "ranc.h")).read()
+    m = re.search(r"#define RANC_STATIC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == R.RANC_STATIC_WORKSPACE_BYTES
