@@ -1,36 +1,47 @@
-// kern_sparse.hip -- one tick of the event-driven path: delivery of the
-// spikes scheduled for this tick, integration by scattering each spiking
-// axon's weights to its connected neurons, leak/threshold/reset, and the
-// scheduler write of this tick's spikes.
+// kern_sparse.hip -- one tick of the event-driven path, as two kernels:
+// delivery of the spikes scheduled for this tick, then integration by
+// scattering each spiking axon's weights to its connected neurons,
+// leak/threshold/reset, and the scheduler write of this tick's spikes.
 //
-// Integration (GPU-RANC Sec. II) touches only the spiking axons' part of the
-// crossbar. The core's connections are kept as compressed rows, one per
-// (neuron slice, axon): the connected neurons of the slice, each entry with
-// the neuron's weight for the axon's type already in it (16 bits: neuron
-// within the slice in 7, signed 9-bit weight in 9). For every spiking axon
-// of a sample the row's weights are added to the sample's input currents,
-// so the work is the number of synaptic events, not A x N per sample.
+// Scheduler (Sec. III-E): the spikes of the last Q = D + 1 ticks of every
+// neuron are kept as a sample-sliced history, 64 samples per word (bit i =
+// sample i of the word's 64-sample tile). A spike sent at tick t with offset d
+// is read by its destination axon at tick t + d from the history slot of
+// tick t, so every scheduler word has one writer (the firing neuron's
+// workgroup) and no atomics are needed.
 //
-// Mapping: one workgroup of 4 wavefronts per (core, slice of <= 128 neurons,
-// tile of 64 samples); a lane is a sample. Phases:
-//   0. every lane starts loading the potentials of its wave's neurons for
-//      its sample (V is neuron-major, [C][N][S64], so a wave's load of one
-//      neuron is 256 contiguous bytes); they are in flight during 1 and 2;
-//      the slice's rows are staged in LDS;
-//   1. delivery: for each axon, the OR of its sources' history words at
-//      t - d (the scheduler rows of Sec. III-E, kept as the last Q = D + 1
-//      ticks of every neuron's spikes, 64 samples per word, bit i = sample
-//      i of the tile); the per-axon sample words are bit-transposed into
-//      per-sample axon words;
-//   2. scatter: each lane walks the spiking axons of its sample in its
-//      wave's axon words and, flat over (axon, entry), adds every entry's
-//      weight to its sample's current of that neuron in LDS (LDS atomic
-//      add: waves share neurons);
-//   3. update: per neuron of the wave, leak, threshold and reset for all 64
+// k_deliver_event: one lane per destination axon and 64-sample tile ORs the
+// history words of the axon's sources at t - d (the routing table keyed by
+// destination axon) and, after a 32 x 32 bit transpose within each half
+// wavefront, writes each sample's axon words of the tick to the delivery
+// buffer [C][S64][A/32] (the scheduler row the tick reads). These are random
+// 8-byte reads with few per lane; kept out of the integration kernel they run
+// at the occupancy of a small kernel, and the integration kernel becomes a
+// stream over the potentials.
+//
+// k_integrate_event (Sec. II): integration touches only the spiking axons'
+// part of the crossbar. The core's connections are kept as compressed rows,
+// one per (neuron slice, axon): the connected neurons of the slice, each
+// entry with the neuron's weight for the axon's type already in it (16 bits:
+// neuron within the slice in 7, signed 9-bit weight in 9). For every spiking
+// axon of a sample the row's weights are added to the sample's input
+// currents, so the work is the number of synaptic events, not A x N per
+// sample. One workgroup of 4 wavefronts per (core, slice of <= 128 neurons,
+// 64-sample tile); a lane is a sample:
+//   0. loads that do not depend on each other are issued first and together:
+//      the slice's row starts and rows (for LDS), the lane's delivered and
+//      external input words, then the potentials of the wave's neurons (V is
+//      neuron-major, [C][N][S64], so a wave's load of one neuron is 256
+//      contiguous bytes), which stay in flight through the scatter;
+//   1. scatter: each lane walks the spiking axons of its sample in its wave's
+//      axon words and, flat over (axon, entry), adds every entry's weight to
+//      its sample's current of that neuron in LDS (LDS atomic add: waves
+//      share neurons);
+//   2. update: per neuron of the wave, leak, threshold and reset for all 64
 //      samples at once (lif_update); the wave's ballot of the spikes is the
 //      neuron's 64-sample history word; potentials are stored back.
-// Every scheduler word has one writer (the workgroup of the neuron's slice
-// and tile) and no global atomics are used.
+// Barriers order LDS only (lds_barrier), so no wave waits for the potential
+// loads of the others.
 #include "kern_bits.h"
 #include "kern_common.h"
 #include "ranc_internal.h"
@@ -39,8 +50,9 @@ namespace ranc {
 
 static constexpr int EV_TS = 64;          // samples per workgroup (one history word)
 static constexpr int EV_NS = 128;         // neurons per slice, at most
-static constexpr int EV_WAVES = 4;        // wavefronts per workgroup
-static constexpr int EV_CSR_LDS = 4096;   // row entries staged in LDS (8 KiB)
+static constexpr int EV_WAVES = 4;        // wavefronts per integration workgroup
+static constexpr int EV_CSR_LDS = 3072;   // row entries staged in LDS (6 KiB)
+static constexpr int DV_WAVES = 4;        // wavefronts per delivery workgroup
 
 int sparse_max_samples_per_wg() { return EV_TS; }
 int sparse_slice_width(int N) { return N < EV_NS ? N : EV_NS; }
@@ -53,6 +65,59 @@ bool sparse_shape_supported(int A, int N, int G)
     const bool ok_g = G == 1 || G == 2 || G == 4 || G == 8;
     return ok_a && ok_n && ok_g;
 }
+
+// ---------------------------------------------------------------------------
+// Delivery: wave (core c, tile, 64-axon block axb), lane = axon 64 axb + lane.
+
+template <int A_>
+__global__ __launch_bounds__(64 * DV_WAVES) void k_deliver_event(DevNet n, TickArgs ta)
+{
+    constexpr int W_ = A_ / 32;
+    constexpr int APB = A_ / 64;   // 64-axon blocks per core
+    constexpr int FMAX = 4;        // sources gathered without a loop
+    const int HG = n.S64 / 64;
+    const long long wv = (long long)blockIdx.x * DV_WAVES + (threadIdx.x >> 6);
+    if (wv >= (long long)n.C * HG * APB)
+        return;   // whole wavefronts
+    const int lane = threadIdx.x & 63;
+    const int axb = (int)(wv % APB);
+    const long long ct = wv / APB;
+    const int tile = (int)(ct % HG);
+    const int c = (int)(ct / HG);
+    const size_t CN = (size_t)n.C * n.N;
+    const int q_now = tick_slot(n, ta.k);
+    const size_t a = (size_t)c * A_ + axb * 64 + lane;
+    const uint32_t b = n.rtx_ptr[a], e = n.rtx_ptr[a + 1];
+    auto word_of = [&](uint32_t x) -> uint64_t {
+        int slot = q_now - (int)(x & 15u) - 1;   // history slot of tick t - d
+        if (slot < 0)
+            slot += n.Q;
+        return n.hist[((size_t)slot * CN + (x >> 4)) * HG + tile];
+    };
+    uint32_t ent[FMAX];
+#pragma unroll
+    for (int k = 0; k < FMAX; ++k)
+        ent[k] = b + k < e ? n.rtx_ent[b + k] : 0xFFFFFFFFu;
+    uint64_t m = 0;
+#pragma unroll
+    for (int k = 0; k < FMAX; ++k)
+        if (ent[k] != 0xFFFFFFFFu)
+            m |= word_of(ent[k]);
+    for (uint32_t k = b + FMAX; k < e; ++k)
+        m |= word_of(n.rtx_ent[k]);
+    // lane (h, j) holds the 64-sample word of axon 64 axb + 32 h + j; after
+    // the transpose of half g, lane (h, i) holds axon word 2 axb + h of
+    // sample 32 g + i of the tile
+    uint32_t *out = n.ring + ((size_t)c * n.S64 + (size_t)tile * 64) * W_;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const uint32_t t = transpose32((uint32_t)(m >> (32 * g)), lane);
+        out[(size_t)(32 * g + (lane & 31)) * W_ + 2 * axb + (lane >> 5)] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Integration.
 
 // acc index of (sample s, neuron j of the slice): the neuron index is XORed
 // with the sample's low five bits, so the 32 samples a half-wave reads for
@@ -86,17 +151,17 @@ __device__ __forceinline__ void scatter_word(uint32_t bits, int word, int s, con
 }
 
 template <int A_, int NS_, bool EXT>
-__global__ __launch_bounds__(64 * EV_WAVES) void k_integrate_event(DevNet n, TickArgs ta)
+__global__ __launch_bounds__(64 * EV_WAVES) __attribute__((amdgpu_waves_per_eu(4)))
+void k_integrate_event(DevNet n, TickArgs ta)
 {
     constexpr int W_ = A_ / 32;                             // axon words
     constexpr int NPW = NS_ / EV_WAVES;                      // neurons per wave in the update
     constexpr int WPW = (W_ + EV_WAVES - 1) / EV_WAVES;      // axon words per wave in the scatter
-    constexpr int APW = A_ / 64;                             // 64-axon blocks of the gather
-    constexpr int BPW = (APW + EV_WAVES - 1) / EV_WAVES;     // gather blocks per wave
-    constexpr int FMAX = 4;                                  // sources gathered without a loop
+    constexpr int NT = 64 * EV_WAVES;                        // threads
+    constexpr int RPT = (A_ + 1 + NT - 1) / NT;              // row starts per thread
+    constexpr int CPT = (EV_CSR_LDS / 8 + NT - 1) / NT;      // 16-byte row chunks per thread
 
     __shared__ __attribute__((aligned(16))) int32_t acc[EV_TS * NS_];
-    __shared__ uint32_t xw[EV_TS][W_ + 1];                   // delivered axon words per sample
     __shared__ uint32_t rp[A_ + 1];                          // row starts, relative to the slice's first entry
     __shared__ __attribute__((aligned(16))) uint16_t rows[EV_CSR_LDS];
     // per sample: [0] emitted | routed << 10 | out << 20, [1] events | delivered << 20
@@ -116,30 +181,38 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_integrate_event(DevNet n, Tic
     const int q_now = tick_slot(n, ta.k), r_row = tick_row(n, ta.k);
     const int j0 = slice * NS_ + wave * NPW;   // first neuron (within the core) of this wave's update
 
-    // ---- 0. loads that start the chains: gather table heads, the slice's
-    // rows, then the potentials of this wave's neurons (used in phase 3)
-    uint32_t g_beg[BPW], g_end[BPW];
-#pragma unroll
-    for (int b = 0; b < BPW; ++b) {
-        const int axb = wave + EV_WAVES * b;
-        g_beg[b] = g_end[b] = 0u;
-        if (axb < APW) {
-            const size_t a = (size_t)c * A_ + axb * 64 + lane;
-            g_beg[b] = n.rtx_ptr[a];
-            g_end[b] = n.rtx_ptr[a + 1];
-        }
-    }
+    // ---- 0. independent loads, in the order they are needed
     const uint32_t *rp_g = n.ecsr_ptr + ((size_t)c * n.slices + slice) * (A_ + 1);
     const uint32_t e_base = rp_g[0];
     const uint32_t e_count = rp_g[A_] - e_base;
     const uint32_t e_pad = (e_count + 7u) & ~7u;   // each slice's rows are padded to 8 entries
     const bool staged = e_pad <= (uint32_t)EV_CSR_LDS;   // uniform
-    for (int i = threadIdx.x; i <= A_; i += 64 * EV_WAVES)
-        rp[i] = rp_g[i] - e_base;
-    if (staged) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(n.ecsr_ent + e_base);
-        for (int i = threadIdx.x; i < (int)(e_pad / 8); i += 64 * EV_WAVES)
-            reinterpret_cast<uint4 *>(rows)[i] = src[i];
+    uint32_t rpv[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int i = threadIdx.x + r * NT;
+        rpv[r] = i <= A_ ? rp_g[i] - e_base : 0u;
+    }
+    uint4 rv[CPT];
+    const uint4 *src = reinterpret_cast<const uint4 *>(n.ecsr_ent + e_base);
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        const int i = threadIdx.x + r * NT;
+        rv[r] = staged && i < (int)(e_pad / 8) ? src[i] : uint4{0u, 0u, 0u, 0u};
+    }
+    // delivered (scheduler row of the tick) and external input words of this
+    // lane's sample for the wave's scatter words w = wave, wave + 4, ...
+    uint32_t xd[WPW], xe[WPW];
+    const int ci = n.in_index[c];
+    const uint32_t *dlv = n.ring + ((size_t)c * n.S64 + s) * W_;
+    const uint32_t *ext = (ta.ext_t != nullptr && ci >= 0 && svalid)
+                              ? ta.ext_t + (size_t)s * ta.ext_sstride + (size_t)ci * W_
+                              : nullptr;
+#pragma unroll
+    for (int k = 0; k < WPW; ++k) {
+        const int wi = wave + EV_WAVES * k;
+        xd[k] = (svalid && wi < W_) ? dlv[wi] : 0u;
+        xe[k] = (ext && wi < W_) ? ext[wi] : 0u;
     }
     int32_t vreg[NPW];
     const int32_t *vin = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
@@ -148,65 +221,33 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_integrate_event(DevNet n, Tic
         vreg[k] = __builtin_nontemporal_load(vin + (size_t)k * n.S64);
     compiler_fence();
 
-    // external input words of this lane's sample for the wave's scatter words
-    uint32_t xe[WPW];
-    const int ci = n.in_index[c];
-    const uint32_t *ext = (ta.ext_t != nullptr && ci >= 0 && svalid)
-                              ? ta.ext_t + (size_t)s * ta.ext_sstride + (size_t)ci * W_
-                              : nullptr;
-#pragma unroll
-    for (int k = 0; k < WPW; ++k) {
-        const int wi = wave + EV_WAVES * k;
-        xe[k] = (ext && wi < W_) ? ext[wi] : 0u;
-    }
-
-    for (int i = threadIdx.x; i < EV_TS * NS_ / 4; i += 64 * EV_WAVES)
+    for (int i = threadIdx.x; i < EV_TS * NS_ / 4; i += NT)
         reinterpret_cast<int4 *>(acc)[i] = int4{0, 0, 0, 0};
     if (threadIdx.x < 2 * EV_TS)
         (&s_cnt[0][0])[threadIdx.x] = 0u;
-
-    // ---- 1. delivery: lane = axon 64 axb + lane; its sources' history words
-    // at t - d (up to FMAX of them as independent loads, the rest in a loop)
 #pragma unroll
-    for (int b = 0; b < BPW; ++b) {
-        const int axb = wave + EV_WAVES * b;
-        if (axb >= APW)
-            break;   // wave-uniform
-        auto row_of = [&](uint32_t e) -> const uint64_t * {
-            int slot = q_now - (int)(e & 15u) - 1;
-            if (slot < 0)
-                slot += n.Q;
-            return n.hist + ((size_t)slot * CN + (e >> 4)) * HG + tile;
-        };
-        uint32_t ent[FMAX];
-#pragma unroll
-        for (int k = 0; k < FMAX; ++k)
-            ent[k] = g_beg[b] + k < g_end[b] ? n.rtx_ent[g_beg[b] + k] : 0xFFFFFFFFu;
-        uint64_t m = 0;
-#pragma unroll
-        for (int k = 0; k < FMAX; ++k)
-            if (ent[k] != 0xFFFFFFFFu)
-                m |= *row_of(ent[k]);
-        for (uint32_t e = g_beg[b] + FMAX; e < g_end[b]; ++e)
-            m |= *row_of(n.rtx_ent[e]);
-        // lane (h, j) holds axon 64 axb + 32 h + j; after the transpose lane
-        // (h, i) holds axon word 2 axb + h of sample 32 g + i
-#pragma unroll
-        for (int g = 0; g < 2; ++g)
-            xw[32 * g + (lane & 31)][2 * axb + (lane >> 5)] = transpose32((uint32_t)(m >> (32 * g)), lane);
+    for (int r = 0; r < RPT; ++r) {
+        const int i = threadIdx.x + r * NT;
+        if (i <= A_)
+            rp[i] = rpv[r];
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        const int i = threadIdx.x + r * NT;
+        if (staged && i < (int)(e_pad / 8))
+            reinterpret_cast<uint4 *>(rows)[i] = rv[r];
+    }
+    lds_barrier();
 
-    // ---- 2. scatter: lane = sample; wave w takes axon words w, w + 4, ...
+    // ---- 1. scatter: lane = sample; wave w takes axon words w, w + 4, ...
     unsigned events = 0, delivered = 0;
 #pragma unroll
     for (int k = 0; k < WPW; ++k) {
         const int wi = wave + EV_WAVES * k;
         if (wi >= W_)
             break;   // wave-uniform
-        const uint32_t xd = svalid ? xw[lane][wi] : 0u;
-        delivered += (unsigned)__popc(xd);
-        const uint32_t bits = xd | xe[k];
+        delivered += (unsigned)__popc(xd[k]);
+        const uint32_t bits = xd[k] | xe[k];
         if (staged)
             scatter_word<NS_>(bits, wi, lane, rp, (const uint16_t *)rows, acc, events);
         else
@@ -214,9 +255,9 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_integrate_event(DevNet n, Tic
     }
     if (svalid && (events | delivered))
         atomicAdd(&s_cnt[1][lane], events | (slice == 0 ? delivered << 20 : 0u));   // delivered counted once per core
-    __syncthreads();
+    lds_barrier();
 
-    // ---- 3. update, one neuron of the wave at a time for all 64 samples
+    // ---- 2. update, one neuron of the wave at a time for all 64 samples
     unsigned em = 0, ro = 0, ou = 0;
     uint64_t myword = 0;   // lane k < NPW: the history word of neuron j0 + k
     int32_t *vout = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
@@ -251,7 +292,7 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_integrate_event(DevNet n, Tic
     }
     if (svalid && (em | ro | ou))
         atomicAdd(&s_cnt[0][lane], em | (ro << 10) | (ou << 20));
-    __syncthreads();
+    lds_barrier();
     if (wave == 0 && svalid) {
         const unsigned a0 = s_cnt[0][lane], a1 = s_cnt[1][lane];
         n.cring[((size_t)r_row * n.C * n.cnt_rows + (size_t)c * n.cnt_rows + slice) * n.S + s] =
@@ -262,6 +303,9 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_integrate_event(DevNet n, Tic
 template <int A_, int NS_>
 static void launch_event_k(const DevNet &n, const TickArgs &a, hipStream_t st)
 {
+    const long long dv_waves = (long long)n.C * (n.S64 / 64) * (A_ / 64);
+    hipLaunchKernelGGL((k_deliver_event<A_>), dim3((unsigned)((dv_waves + DV_WAVES - 1) / DV_WAVES)),
+                       dim3(64 * DV_WAVES), 0, st, n, a);
     const dim3 grid(n.C * n.slices * (n.S64 / EV_TS)), block(64 * EV_WAVES);
     if (n.model_ext)
         hipLaunchKernelGGL((k_integrate_event<A_, NS_, true>), grid, block, 0, st, n, a);
@@ -283,7 +327,8 @@ static hipError_t launch_event_a(const DevNet &n, const TickArgs &a, hipStream_t
 hipError_t launch_integrate_sparse(const DevNet &n, const TickArgs &a, int samples_per_wg, hipStream_t st)
 {
     if (!sparse_shape_supported(n.A, n.N, n.G) || samples_per_wg != EV_TS || n.vlayout != VLAYOUT_SPARSE ||
-        n.S64 % EV_TS || n.S > n.S64 || n.slices != n.N / sparse_slice_width(n.N) || n.cnt_rows != n.slices)
+        n.S64 % EV_TS || n.S > n.S64 || n.slices != n.N / sparse_slice_width(n.N) || n.cnt_rows != n.slices ||
+        !n.ring)
         return hipErrorInvalidValue;
     switch (n.A) {
     case 64: return launch_event_a<64>(n, a, st);

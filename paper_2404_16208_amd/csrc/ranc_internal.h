@@ -44,6 +44,9 @@
 //   ring     u32 [Q][S][C][W]  scheduler: slot t%Q holds the axon spikes of tick t
 //   spk      u32 [S][C][NW]    spikes of the current tick
 //   raster   u32 [RT][S][Wout] output-bus spikes of tick t in row t%RT
+//   sparse path:
+//   ring     u32 [C][S64][W]   delivered axon spikes of the tick being integrated (the
+//                              scheduler row it reads), written by the delivery kernel
 //   MFMA and sparse paths:
 //   hist     u64 [Q][C*N][HG]  spikes of tick t in slot t%Q; word (slot, neuron, i)
 //                              covers samples 64i .. 64i+63; MFMA: bit p = sample
@@ -231,6 +234,13 @@ hipError_t launch_reset_state(const DevNet &n, const LinkArgs &l, hipStream_t st
 hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st);
 hipError_t launch_fold_counts(const DevNet &n, int num_ticks, hipStream_t st);
 hipError_t launch_link_counts(const DevNet &n, const LinkArgs &l, int k, hipStream_t st);
+// Output-bus spikes of ticks [t0, t0 + T) (all retained) into dst, by neuron
+// (u64 [T][Nout][S64/64]) or by sample (u32 [T][S][ceil(Nout/32)]), bits in
+// sample order (kern_raster.hip). Plain path tables: outcol[ow] = (index
+// c * NW + w of raster column ow's neuron word, output index of its first
+// output neuron); opos[o] = raster column of output neuron o << 5 | its bit.
+hipError_t launch_pack_raster(const DevNet &n, const int2 *outcol, const int32_t *opos, int by_sample, long long t0,
+                              int T, void *dst, hipStream_t st);
 bool mfma_shape_supported(int A, int N, int two_planes);
 int mfma_width(int A, int N, int two_planes);   // neurons per MFMA workgroup (128 or 256)
 int mfma_slices(int A, int N, int two_planes);  // MFMA workgroups per core and sample chunk

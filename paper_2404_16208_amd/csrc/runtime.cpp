@@ -45,7 +45,7 @@ ranc_status hip_fail(hipError_t e, const char *what)
 enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
     R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
-    R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT, R_LINKREC,
+    R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT, R_LINKREC, R_OUTCOL, R_OUTPOS,
     R_PARAMS_END,  // everything before this is uploaded once at load
     R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_LINKD, R_NREG
 };
@@ -306,7 +306,9 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_OUTIDX] = tiled ? C * N * 4 : 0;
     p.size[R_PLANES] = mf ? C * A * N * (p.two ? 2 : 1) : 0;
     p.size[R_V] = C * (tiled ? (size_t)p.S64 : (size_t)S) * N * 4;
-    p.size[R_RING] = tiled ? 0 : (size_t)p.Q * S * C * W * 4;
+    // plain path: the scheduler ring; sparse path: the scheduler row of the
+    // tick being integrated, [C][S64][W], written by the delivery kernel
+    p.size[R_RING] = mf ? 0 : sp ? C * (size_t)p.S64 * W * 4 : (size_t)p.Q * S * C * W * 4;
     p.size[R_SPK] = tiled ? 0 : (size_t)S * C * NW * 4;
     p.size[R_HIST] = tiled ? (size_t)p.Q * C * N * HG * 8 : 0;
     p.size[R_RASTER] = tiled ? (size_t)RT * p.Nout * HG * 8 : (size_t)RT * S * p.Wout * 4;
@@ -316,6 +318,8 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_BATCH] = BATCH_TABLE_BYTES;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
     p.size[R_LINKREC] = C * N * 8;
+    p.size[R_OUTCOL] = tiled ? 0 : std::max<size_t>((size_t)p.Wout, 1) * 8;
+    p.size[R_OUTPOS] = tiled ? 0 : std::max<size_t>((size_t)p.Nout, 1) * 4;
     p.size[R_LINKD] = (size_t)4 * C * p.S64 * 8;
     size_t off = 0;
     for (int r = 0; r < R_NREG; ++r) {
@@ -387,6 +391,25 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
                 out_words.push_back(w);
             }
         }
+    if (p.size[R_OUTCOL]) {
+        // plain-path raster columns: neuron word and the output index of its
+        // first output neuron (output neurons numbered in (core, neuron) order)
+        int32_t *oc = (int32_t *)at(R_OUTCOL);
+        int base = 0;
+        for (size_t ow = 0; ow < out_words.size() / 2; ++ow) {
+            const int c = out_words[2 * ow], w = out_words[2 * ow + 1];
+            oc[2 * ow] = c * NW + w;
+            oc[2 * ow + 1] = base;
+            base += __builtin_popcount(omask[(size_t)c * NW + w]);
+        }
+        int32_t *op = (int32_t *)at(R_OUTPOS);
+        int o = 0;
+        for (size_t ow = 0; ow < out_words.size() / 2; ++ow) {
+            const int c = out_words[2 * ow], w = out_words[2 * ow + 1];
+            for (uint32_t m = omask[(size_t)c * NW + w]; m; m &= m - 1u)
+                op[o++] = (int32_t)(ow << 5) | __builtin_ctz(m);
+        }
+    }
     int32_t *inidx = (int32_t *)at(R_ININDEX);
     for (int c = 0; c < C; ++c)
         inidx[c] = -1;
@@ -604,13 +627,15 @@ struct ranc_net {
     int64_t tick;
     uint64_t version, raster_version;
     std::vector<int> out_words;        // (core, word) pairs of raster columns (plain path)
-    std::vector<int> out_neurons;      // (core, neuron) of each output-bus neuron (MFMA path)
+    std::vector<int> out_neurons;      // (core, neuron) of each output-bus neuron, in index order
     std::vector<uint32_t> raster_host; // mirror of the raster
     uint64_t v_version = 0;
     std::vector<int32_t> v_host;       // mirror of the potentials
     uint64_t cnt_version = 0;
     std::vector<unsigned long long> cnt_host; // mirror of the counters
     LinkArgs lk{nullptr, nullptr};     // mesh link path ends and counts in the workspace
+    const int2 *outcol = nullptr;      // plain path: raster columns (kern_raster.hip)
+    const int32_t *opos = nullptr;     // plain path: raster position of each output neuron
     bool links_on = false;             // count packets per mesh link on every tick run
     uint64_t links_version = 0;
     std::vector<long long> links_host; // mirror of the link difference arrays
@@ -1206,6 +1231,8 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.cring = (unsigned long long *)reg(R_CRING);
     n.tick = (int *)reg(R_TICK);
     net->lk.rec = (const int2 *)reg(R_LINKREC);
+    net->outcol = p.size[R_OUTCOL] ? (const int2 *)reg(R_OUTCOL) : nullptr;
+    net->opos = p.size[R_OUTPOS] ? (const int32_t *)reg(R_OUTPOS) : nullptr;
     net->lk.d = (long long *)reg(R_LINKD);
     std::vector<uint8_t> host;
     pack_params(desc, p, host, net->out_words);
@@ -1432,6 +1459,59 @@ ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, 
     *count = k;
     if (k > capacity)
         return fail(RANC_ETRUNC, "%lld spikes do not fit capacity %lld", (long long)k, (long long)capacity);
+    return RANC_OK;
+}
+
+ranc_status ranc_raster_bytes(const ranc_net *net, int64_t num_ticks, uint32_t layout, size_t *bytes)
+{
+    if (!net || !bytes)
+        return fail(RANC_EINVAL, "net or bytes is NULL");
+    if (num_ticks < 0)
+        return fail(RANC_EINVAL, "num_ticks %lld < 0", (long long)num_ticks);
+    const Plan &p = net->p;
+    if (layout == RANC_RASTER_BY_NEURON)
+        *bytes = (size_t)num_ticks * p.Nout * (p.S64 / 64) * 8;
+    else if (layout == RANC_RASTER_BY_SAMPLE)
+        *bytes = (size_t)num_ticks * p.S * ((p.Nout + 31) / 32) * 4;
+    else
+        return fail(RANC_EINVAL, "unknown raster layout %u", layout);
+    return RANC_OK;
+}
+
+ranc_status ranc_copy_raster(ranc_net *net, int64_t tick_begin, int64_t tick_end, uint32_t layout, void *dst,
+                             size_t dst_bytes, void *stream)
+{
+    if (!net || !dst)
+        return fail(RANC_EINVAL, "net or dst is NULL");
+    if (layout != RANC_RASTER_BY_NEURON && layout != RANC_RASTER_BY_SAMPLE)
+        return fail(RANC_EINVAL, "unknown raster layout %u", layout);
+    const Plan &p = net->p;
+    const int64_t lo = std::max<int64_t>(0, net->tick - p.RT);
+    if (tick_begin < lo || tick_end > net->tick || tick_begin >= tick_end)
+        return fail(RANC_ESTATE, "ticks [%lld, %lld) empty or outside the retained window [%lld, %lld)",
+                    (long long)tick_begin, (long long)tick_end, (long long)lo, (long long)net->tick);
+    size_t need = 0;
+    ranc_raster_bytes(net, tick_end - tick_begin, layout, &need);
+    if (dst_bytes < need)
+        return fail(RANC_ENOMEM, "dst has %zu bytes, needs %zu", dst_bytes, need);
+    hipError_t e = launch_pack_raster(net->dn, net->outcol, net->opos, layout == RANC_RASTER_BY_SAMPLE, tick_begin,
+                                      (int)(tick_end - tick_begin), dst, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "packing the output raster");
+    return RANC_OK;
+}
+
+ranc_status ranc_output_neurons(const ranc_net *net, int32_t *out, int64_t capacity, int64_t *count)
+{
+    if (!net || !count)
+        return fail(RANC_EINVAL, "net or count is NULL");
+    const int64_t n = (int64_t)net->out_neurons.size() / 2;
+    *count = n;
+    if (capacity < n)
+        return fail(RANC_ETRUNC, "%lld output neurons do not fit capacity %lld", (long long)n, (long long)capacity);
+    if (n && !out)
+        return fail(RANC_EINVAL, "out is NULL");
+    memcpy(out, net->out_neurons.data(), (size_t)n * 2 * sizeof(int32_t));
     return RANC_OK;
 }
 
