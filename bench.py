@@ -231,16 +231,6 @@ def bench_sparse_mesh(args, torch, np):
     print(json.dumps(out), flush=True)
 
 
-# The applications of the paper's Table I: name, ticks, cores, axons and
-# neurons per core (the networks are synthetic stand-ins of these shapes, so
-# the table's times are not compared with).
-TABLE1 = [("MNIST-12c", 10010, 12, 256, 256), ("MNIST-128c", 10010, 128, 256, 256),
-          ("MNIST-512c", 10010, 512, 256, 256), ("VMM 32x32", 788, 21, 256, 256),
-          ("VMM 50x50", 889, 45, 512, 256), ("VMM 60x60", 1095, 51, 512, 256),
-          ("CIFAR10", 10010, 36, 256, 256), ("TrueNorth Ref.", 500, 4096, 256, 256)]
-TABLE1_GRID_W = {12: 4, 128: 16, 512: 32, 21: 7, 45: 9, 51: 17, 36: 6, 4096: 64}
-
-
 def bench_table1(args, torch, np):
     """The shapes of the paper's Table I applications as seeded synthetic
     networks, one instance each, simulated for the table's number of ticks
@@ -257,16 +247,13 @@ def bench_table1(args, torch, np):
     RT = 128
     rows = []
     apps = [a.strip() for a in args.apps.split(",")] if args.apps else None
-    for i, (name, T, C, A, N) in enumerate(TABLE1):
+    for name, T, C, A, N in W.TABLE1:
         if apps is not None and name not in apps:
             continue
-        idle = name.startswith("TrueNorth")
         print(f"[bench] {name}: {C} cores of {A}x{N}, {T} ticks", file=sys.stderr, flush=True)
-        net = W.random_net(900 + i, C, A, N, 4, weight_bits=9, max_delay=4, grid_w=TABLE1_GRID_W[C], density=0.2,
-                           p_core=0.8, p_out=0.1, leak_range=(0, 0) if idle else (-8, 8),
-                           input_cores=[] if idle else list(range(0, C, 4)), config_id=716)
-        x = None if idle else torch.from_numpy(
-            W.bernoulli_inputs(i, net, 1, RT, 0.1, config_id=716).view(np.int32)).cuda()
+        net = W.table1_net(name)
+        xi = W.table1_inputs(name, net, 1, RT)
+        x = None if xi is None else torch.from_numpy(xi.view(np.int32)).cuda()
         g = RancNet(net, 1, RT, path=args.path)
         full, rem = divmod(T, RT)
         xr = None if x is None or rem == 0 else x[:, :rem].contiguous()
@@ -301,15 +288,37 @@ def bench_table1(args, torch, np):
     print(json.dumps(out), flush=True)
 
 
+def class_masks(net, out_neurons, np):
+    """Per class, u32 masks over the output-neuron words of a by-sample raster
+    (class of an output neuron = its global neuron index mod 10)."""
+    from paper_2404_16208_amd import workloads as W
+    cls = W.mnist_class_of_output(net)[out_neurons[:, 0], out_neurons[:, 1]]
+    nw = (len(out_neurons) + 31) // 32
+    m = np.zeros((10, nw * 32), dtype=bool)
+    m[cls, np.arange(len(out_neurons))] = True
+    return np.packbits(m, axis=1, bitorder="little").view(np.uint32)
+
+
+def class_votes(words, masks, np):
+    """Spikes per class of every sample from a by-sample raster [T][S][NW]."""
+    w = words.reshape(-1, words.shape[1], words.shape[2])
+    return np.stack([np.bitwise_count(w & masks[c]).sum(axis=(0, 2), dtype=np.int64)
+                     for c in range(len(masks))], axis=1)
+
+
 def bench_stream(args, torch, np):
     """Streaming, as the paper runs its applications: one instance of the
     512-core MNIST-shaped net for 10010 ticks with the inputs in pinned host
-    memory. Chunks of 128 ticks: the next chunk's inputs are copied to the
-    GPU on a second stream while the current chunk runs as a graph replay,
-    and each chunk's output-bus spikes are read back before the raster
-    wraps. Host clock over the whole run (upload, simulation, readback)."""
+    memory, through paper_2404_16208_amd.stream: 128-tick chunks, the next
+    chunk's inputs uploaded on a second stream while the current chunk runs
+    (graph replay), each chunk's output spikes packed by ranc_copy_raster and
+    drained to pinned host memory on a third stream, and the host counting
+    spikes per class of the previous chunk meanwhile. Host clock over the
+    whole run (upload, simulation, drain, read-out), against the same ticks
+    simulated with the inputs already on the GPU and no output drained."""
     from paper_2404_16208_amd import workloads as W
     from paper_2404_16208_amd.ranc import RancNet
+    from paper_2404_16208_amd.stream import Streamer
 
     T, RT = 10010, 128
     print(f"[bench] generating the 512-core net and 1 x {T} inputs", file=sys.stderr, flush=True)
@@ -317,57 +326,50 @@ def bench_stream(args, torch, np):
     x = W.mnist_inputs(0, 1, T)
     host = torch.from_numpy(x.view(np.int32)).pin_memory()
     g = RancNet(net, 1, RT, path=args.path)
-    cstream = torch.cuda.Stream()
-    bufs = [torch.empty((1, RT) + tuple(host.shape[2:]), dtype=torch.int32, device="cuda") for _ in range(2)]
-    chunks = [(t0, min(RT, T - t0)) for t0 in range(0, T, RT)]
-    # the last, shorter chunk has a buffer of its own (a fixed address, so its captured graph is reused)
-    tail = torch.empty((1, chunks[-1][1]) + tuple(host.shape[2:]), dtype=torch.int32, device="cuda")
+    masks = class_masks(net, g.output_neurons(), np)
+    st = Streamer(g, RT)
+    votes = np.zeros((1, 10), np.int64)
 
-    def buf_of(i):
-        return tail if chunks[i][1] < RT else bufs[i % 2]
+    def consume(t0, words):
+        votes[:] += class_votes(words, masks, np)
 
-    def run(read: bool):
-        g.reset()
-        done = [None, None]
-        copied = []
-        spikes = 0
-
-        def upload(i):
-            t0, k = chunks[i]
-            b = buf_of(i)
-            with torch.cuda.stream(cstream):
-                if done[i % 2] is not None:
-                    cstream.wait_event(done[i % 2])   # the chunk that last used this buffer has run
-                b.copy_(host[:, t0:t0 + k], non_blocking=True)
-                ev = torch.cuda.Event()
-                ev.record(cstream)
-            return ev
-
-        copied.append(upload(0))
-        for i, (t0, k) in enumerate(chunks):
-            if i + 1 < len(chunks):
-                copied.append(upload(i + 1))
-            torch.cuda.current_stream().wait_event(copied[i])
-            g.run(buf_of(i), k, graph=True)
-            ev = torch.cuda.Event()
-            ev.record(torch.cuda.current_stream())
-            done[i % 2] = ev
-            if read:
-                spikes += len(g.spikes(0, t0, t0 + k))
-        torch.cuda.synchronize()
-        return spikes
-
-    run(False)   # captures the graphs (both buffers, and the last partial chunk)
+    st.run(host, T, consume)   # captures the tick loops (both input buffers and the last chunk)
+    g.reset()
+    votes[:] = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    n_out = run(True)
+    st.run(host, T, consume)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same ticks with the inputs resident on the GPU, no output drained
+    xd = torch.from_numpy(x.view(np.int32)).cuda()
+    chunks = [(t, min(RT, T - t)) for t in range(0, T, RT)]
+    bufs = {}
+    for t, k in chunks:
+        bufs.setdefault(k, torch.empty((1, k) + tuple(xd.shape[2:]), dtype=torch.int32, device="cuda"))
+    sim_runs = []
+    for rep in range(2):   # the first pass captures the loops
+        g.reset()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for t, k in chunks:
+            b = bufs[k]
+            b.copy_(xd[:, t:t + k])
+            g.run(b, k, graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        sim_runs.append(e0.elapsed_time(e1) / 1e3)
+    sim = sim_runs[-1]
     out = {"metric": "end-to-end time of a streamed 10010-tick single-instance run (512-core MNIST-shaped net)",
            "unit": "s", "value": dt, "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
            "config": {"workload": f"512-core MNIST-shaped net, 1 instance, {T} ticks in {RT}-tick chunks, inputs "
-                                  "in pinned host memory uploaded on a second stream, output spikes read back "
-                                  "per chunk", "path": g.path},
-           "ticks_per_s": T / dt, "us_per_tick": 1e6 * dt / T, "output_spikes": n_out}
+                                  "in pinned host memory uploaded on a second stream, output rasters drained to "
+                                  "pinned host memory on a third stream while the next chunk runs, spikes counted "
+                                  "per class on the host", "path": g.path},
+           "ticks_per_s": T / dt, "us_per_tick": 1e6 * dt / T,
+           "simulation_s": sim, "end_to_end_over_simulation": dt / sim,
+           "output_spikes": int(votes.sum()), "class_votes": votes[0].tolist()}
     g.close()
     print(json.dumps(out), flush=True)
 
@@ -469,6 +471,7 @@ def main():
         sys.exit(2)
 
     if args.apps:
+        from paper_2404_16208_amd.workloads import TABLE1
         unknown = sorted({a.strip() for a in args.apps.split(",")} - {r[0] for r in TABLE1})
         if args.workload != "table1" or unknown:
             ap.error(f"--apps applies to --workload table1 and takes names from {[r[0] for r in TABLE1]}")
@@ -580,22 +583,38 @@ def main():
 
     # End to end, as a user sees one step from a cold handle: load (parameter
     # upload), one step with the inputs in host memory (staged over PCIe), and
-    # reading every sample's output spikes back; host clock, first call
-    # included (no graph capture).
+    # every sample's output spikes back in host memory (ranc_copy_raster, by
+    # sample, then one copy to pinned host memory); host clock, first call
+    # included (no graph capture). The class read-out from those bits on the
+    # host is timed beside it.
+    n_out_neurons = int((net.dest_kind == 2).sum())
+    rbytes = T * S * ((n_out_neurons + 31) // 32) * 4
+    rdev = torch.empty(rbytes, dtype=torch.uint8, device="cuda")
+    rhost = torch.empty(rbytes, dtype=torch.uint8, pin_memory=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ge = RancNet(net, S, T, path="mfma")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    assert ge.raster_bytes(T, "sample") == rbytes
     ge.run(x, T)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    n_out = sum(len(ge.spikes(s)) for s in range(S))
+    ge.copy_raster(0, T, rdev, "sample")
+    rhost.copy_(rdev)
+    torch.cuda.synchronize()
     t3 = time.perf_counter()
+    words = rhost.numpy().view(np.uint32).reshape(T, S, -1)
+    votes = class_votes(words, class_masks(net, ge.output_neurons(), np), np)
+    t4 = time.perf_counter()
+    n_out = int(votes.sum())
     out["end_to_end"] = {"ms": (t3 - t0) * 1e3, "load_ms": (t1 - t0) * 1e3, "run_ms": (t2 - t1) * 1e3,
-                         "read_ms": (t3 - t2) * 1e3, "output_spikes": n_out,
-                         "includes": f"load + host-input staging + {T} ticks + reading all {S} samples' "
-                                     "output spikes (host clock)"}
+                         "read_ms": (t3 - t2) * 1e3, "readout_ms": (t4 - t3) * 1e3, "output_spikes": n_out,
+                         "raster_bytes": rbytes,
+                         "includes": f"load + host-input staging + {T} ticks + every sample's output-bus spikes "
+                                     "in pinned host memory as a by-sample bit raster (host clock; buffer "
+                                     "allocation excluded); readout_ms: spikes per class of all samples on the "
+                                     "host, not included"}
     ge.close()
     del ge
     torch.cuda.empty_cache()

@@ -231,6 +231,42 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets,
 ranc_status ranc_read_spikes(ranc_net *net, int32_t sample, int64_t tick_begin, int64_t tick_end,
                              ranc_spike *out, int64_t capacity, int64_t *count);
 
+/*
+ * The same output file in bulk, for every sample at once, so that a long run
+ * can be drained chunk by chunk while the next chunk runs (streaming, Sec. V:
+ * an application's inputs pass through one instance tick after tick, and its
+ * output spikes leave the same way) and decoded away from the critical path.
+ * ranc_copy_raster queues on `stream` a kernel that writes the output-bus
+ * spikes of ticks [tick_begin, tick_end) (T ticks) into dst, in one of two
+ * layouts:
+ *   RANC_RASTER_BY_NEURON: uint64 words [T][Nout][ceil(S/64)]; bit i of word
+ *     (t, o, w) is set if sample 64 w + i sent a spike from output neuron o to
+ *     the output bus at tick tick_begin + t;
+ *   RANC_RASTER_BY_SAMPLE: uint32 words [T][S][ceil(Nout/32)]; bit o % 32 of
+ *     word (t, s, o / 32) is set for the same event (compact for few samples).
+ * Output neurons are numbered in ascending (core, neuron) order among the
+ * neurons whose destination is the output bus (ranc_output_neurons lists
+ * them). Bits past S samples or Nout neurons are zero; every word of the
+ * range is written. dst is any memory the device can write: device memory,
+ * or pinned host memory (hipHostMalloc), which the kernel then writes across
+ * the bus with no further copy. The ticks must lie in the retained window
+ * (the last max_ticks_per_call ticks queued; else RANC_ESTATE) when the call
+ * is made, the range must not be empty, and the kernel must run after the
+ * runs that produced them (same stream, or ordered by events) and before
+ * later runs overwrite them (a run of k ticks reuses the rows of the k oldest
+ * retained ticks). RANC_ENOMEM if dst_bytes is below
+ * ranc_raster_bytes(net, T, layout); RANC_EINVAL for another layout. Returns
+ * after queueing.
+ */
+#define RANC_RASTER_BY_NEURON 0u
+#define RANC_RASTER_BY_SAMPLE 1u
+ranc_status ranc_raster_bytes(const ranc_net *net, int64_t num_ticks, uint32_t layout, size_t *bytes);
+ranc_status ranc_copy_raster(ranc_net *net, int64_t tick_begin, int64_t tick_end, uint32_t layout, void *dst,
+                             size_t dst_bytes, void *stream);
+/* (core, neuron) of output neuron o at out[2 o], out[2 o + 1]; *count = Nout.
+ * RANC_ETRUNC (with *count set) if capacity < Nout. Host only. */
+ranc_status ranc_output_neurons(const ranc_net *net, int32_t *out, int64_t capacity, int64_t *count);
+
 /* Current potentials of one sample into out[C][N] (host). Synchronizes. */
 ranc_status ranc_read_potentials(ranc_net *net, int32_t sample, int32_t *out);
 

@@ -32,8 +32,11 @@ EXPORTED = ("ranc_last_error", "ranc_workspace_bytes", "ranc_load_network", "ran
             "ranc_read_spikes", "ranc_read_potentials", "ranc_read_counters", "ranc_current_tick",
             "ranc_get_path", "ranc_profile_enable", "ranc_profile_read", "ranc_reset_state", "ranc_free",
             "ranc_autotune", "ranc_set_launch_shape", "ranc_get_launch_shape", "ranc_load_network_static",
-            "ranc_link_counts_enable", "ranc_read_links")
+            "ranc_link_counts_enable", "ranc_read_links", "ranc_raster_bytes", "ranc_copy_raster",
+            "ranc_output_neurons")
 RANC_LINK_XPLUS, RANC_LINK_XMINUS, RANC_LINK_YPLUS, RANC_LINK_YMINUS = 0, 1, 2, 3
+RANC_RASTER_BY_NEURON, RANC_RASTER_BY_SAMPLE = 0, 1
+RASTER_LAYOUTS = {"neuron": RANC_RASTER_BY_NEURON, "sample": RANC_RASTER_BY_SAMPLE}
 RANC_STATIC_WORKSPACE_BYTES = 64 << 20
 
 
@@ -94,6 +97,9 @@ def _load_lib():
         "ranc_read_counters": (C.c_int, [vp, i32, C.POINTER(ranc_counters)]),
         "ranc_current_tick": (C.c_int, [vp, C.POINTER(i64)]),
         "ranc_link_counts_enable": (C.c_int, [vp, i32]),
+        "ranc_raster_bytes": (C.c_int, [vp, i64, u32, C.POINTER(sz)]),
+        "ranc_copy_raster": (C.c_int, [vp, i64, i64, u32, vp, sz, vp]),
+        "ranc_output_neurons": (C.c_int, [vp, vp, i64, C.POINTER(i64)]),
         "ranc_read_links": (C.c_int, [vp, i32, vp]),
         "ranc_get_path": (C.c_int, [vp, C.POINTER(i32)]),
         "ranc_profile_enable": (C.c_int, [vp, i32]),
@@ -219,6 +225,28 @@ def ranc_read_links(handle: int, sample: int, C_: int) -> np.ndarray:
     """Packets per mesh link of one sample, int64 [C, 4] (+x, -x, +y, -y)."""
     out = np.empty((C_, 4), dtype=np.int64)
     _check(_lib.ranc_read_links(handle, sample, out.ctypes.data))
+    return out
+
+
+def ranc_raster_bytes(handle: int, num_ticks: int, layout: int = RANC_RASTER_BY_SAMPLE) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.ranc_raster_bytes(handle, num_ticks, layout, C.byref(out)))
+    return int(out.value)
+
+
+def ranc_copy_raster(handle: int, tick_begin: int, tick_end: int, layout: int, dst_ptr: int, dst_bytes: int,
+                     stream: int) -> None:
+    _check(_lib.ranc_copy_raster(handle, tick_begin, tick_end, layout, dst_ptr, dst_bytes, stream))
+
+
+def ranc_output_neurons(handle: int) -> np.ndarray:
+    """(core, neuron) of every output neuron, int32 [Nout, 2], in output-index order."""
+    count = C.c_int64(0)
+    st = _lib.ranc_output_neurons(handle, None, 0, C.byref(count))
+    if st not in (RANC_OK, RANC_ETRUNC):
+        _check(st)
+    out = np.zeros((int(count.value), 2), dtype=np.int32)
+    _check(_lib.ranc_output_neurons(handle, out.ctypes.data if len(out) else None, len(out), C.byref(count)))
     return out
 
 
@@ -348,6 +376,26 @@ class RancNet:
         return np.stack([sp["tick"], sp["core"].astype(np.int64), sp["neuron"].astype(np.int64)], axis=1) \
             if len(sp) else np.zeros((0, 3), np.int64)
 
+    def raster_bytes(self, num_ticks: int, layout: str = "sample") -> int:
+        return ranc_raster_bytes(self.handle, num_ticks, RASTER_LAYOUTS[layout])
+
+    def copy_raster(self, tick_begin: int, tick_end: int, dst, layout: str = "sample", stream=None):
+        """Queue the bulk copy of ticks [tick_begin, tick_end) of every sample's
+        output-bus spikes into ``dst`` (a CUDA tensor, or a pinned host tensor, of
+        at least raster_bytes(T, layout) bytes). layout "sample": u32 words
+        [T][S][ceil(Nout/32)], bit o % 32 of word (t, s, o // 32); "neuron": u64
+        words [T][Nout][ceil(S/64)], bit i of word (t, o, w) = sample 64 w + i.
+        ``stream``: a torch stream (default: the handle's stream)."""
+        st = (stream or self.stream).cuda_stream
+        ranc_copy_raster(self.handle, tick_begin, tick_end, RASTER_LAYOUTS[layout], dst.data_ptr(),
+                         dst.numel() * dst.element_size(), st)
+        return dst
+
+    def output_neurons(self) -> np.ndarray:
+        if getattr(self, "_out_neurons", None) is None:
+            self._out_neurons = ranc_output_neurons(self.handle)
+        return self._out_neurons
+
     def potentials(self, sample: int) -> np.ndarray:
         return ranc_read_potentials(self.handle, sample, self.net.num_cores, self.net.num_neurons)
 
@@ -437,3 +485,23 @@ def run_batch(nets, inputs, num_ticks: int, graph: bool = False, persistent: boo
     if kinds == {"host"}:
         stream.synchronize()   # host buffers must outlive the staging copies
     return nets
+
+
+def decode_raster(words: np.ndarray, out_neurons: np.ndarray, tick_begin: int, sample: int,
+                  layout: str = "sample") -> np.ndarray:
+    """Output-bus spikes of one sample from a bulk raster (as ranc_copy_raster
+    writes it: "sample" u32 [T][S][ceil(Nout/32)] or "neuron" u64
+    [T][Nout][ceil(S/64)]), int64 [n, 3] rows (tick, core, neuron) sorted by
+    (tick, core, neuron), as RancNet.spikes returns them."""
+    nout = len(out_neurons)
+    if layout == "sample":
+        w = np.ascontiguousarray(np.asarray(words).view(np.uint32)[:, sample, :])
+        bits = np.unpackbits(w.view(np.uint8), axis=1, bitorder="little")[:, :nout].astype(bool)
+    else:
+        w = np.asarray(words).view(np.uint64)
+        bits = ((w[:, :, sample // 64] >> np.uint64(sample % 64)) & np.uint64(1)).astype(bool)
+    t, o = np.nonzero(bits)
+    if not len(t):
+        return np.zeros((0, 3), np.int64)
+    return np.stack([t.astype(np.int64) + tick_begin, out_neurons[o, 0].astype(np.int64),
+                     out_neurons[o, 1].astype(np.int64)], axis=1)

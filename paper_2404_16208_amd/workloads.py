@@ -421,3 +421,38 @@ def sweep_variant(seed: int, v: int) -> Tuple[Net, Dict]:
     net.name = f"sweep{v}_C{C}_A{A}_N{N}_G{G}_b{b}{model}"
     return net, dict(C=C, A=A, N=N, G=G, b=b, density=dens, P=P, leak_bits=leak_bits, reset_bits=reset_bits,
                      floor=floor_range is not None, linear=linear_frac > 0)
+
+
+# --------------------------------------------------------------------------
+# The applications of the paper's Table I: name, ticks, cores, axons and
+# neurons per core. Their trained networks and data are not available; the
+# networks below are seeded random stand-ins of the same core counts and core
+# sizes (crossbar density 0.2, 4 axon types, 9-bit weights, random routing
+# with delays 1..4, Bernoulli(0.1) input on every fourth core). The TrueNorth
+# reference runs without input or leak, so no neuron ever spikes.
+# --------------------------------------------------------------------------
+
+TABLE1 = [("MNIST-12c", 10010, 12, 256, 256), ("MNIST-128c", 10010, 128, 256, 256),
+          ("MNIST-512c", 10010, 512, 256, 256), ("VMM 32x32", 788, 21, 256, 256),
+          ("VMM 50x50", 889, 45, 512, 256), ("VMM 60x60", 1095, 51, 512, 256),
+          ("CIFAR10", 10010, 36, 256, 256), ("TrueNorth Ref.", 500, 4096, 256, 256)]
+TABLE1_GRID_W = {12: 4, 128: 16, 512: 32, 21: 7, 45: 9, 51: 17, 36: 6, 4096: 64}
+
+
+def table1_net(name: str) -> Net:
+    i = [r[0] for r in TABLE1].index(name)
+    _, _, C, A, N = TABLE1[i]
+    idle = name.startswith("TrueNorth")
+    net = random_net(900 + i, C, A, N, 4, weight_bits=9, max_delay=4, grid_w=TABLE1_GRID_W[C], density=0.2,
+                     p_core=0.8, p_out=0.1, leak_range=(0, 0) if idle else (-8, 8),
+                     input_cores=[] if idle else list(range(0, C, 4)), config_id=716)
+    net.name = name
+    return net
+
+
+def table1_inputs(name: str, net: Net, S: int, T: int):
+    """Input bitmaps of a Table I stand-in, or None for the TrueNorth reference."""
+    i = [r[0] for r in TABLE1].index(name)
+    if name.startswith("TrueNorth"):
+        return None
+    return bernoulli_inputs(i, net, S, T, 0.1, config_id=716)
