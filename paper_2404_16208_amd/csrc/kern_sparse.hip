@@ -219,6 +219,19 @@ void k_integrate_event(DevNet n, TickArgs ta)
 #pragma unroll
     for (int k = 0; k < NPW; ++k)
         vreg[k] = __builtin_nontemporal_load(vin + (size_t)k * n.S64);
+    // parameters of the wave's neurons, lane k holding neuron j0 + k (one
+    // load each, broadcast per neuron in the update): the kernel stores
+    // through other pointers, so per-neuron loads inside the update would be
+    // vector loads waited for one neuron at a time
+    const size_t cw = (size_t)c * n.N + j0;   // first neuron of the wave (a multiple of NPW)
+    const size_t cl = cw + (lane < NPW ? lane : 0);
+    const int32_t p_leak = n.leak[cl], p_thr = n.thr[cl], p_rst = n.rst[cl];
+    int32_t p_fl = n.vmin;
+    if constexpr (EXT)
+        p_fl = n.floor[cl];
+    // the wave's NPW neurons lie in one 32-neuron word of the masks, from bit cw % 32
+    const uint32_t cm_w = n.coremask[cw >> 5] >> (cw & 31), om_w = n.outmask[cw >> 5] >> (cw & 31);
+    const uint32_t lin_w = EXT ? n.linmask[cw >> 5] >> (cw & 31) : 0u;
     compiler_fence();
 
     for (int i = threadIdx.x; i < EV_TS * NS_ / 4; i += NT)
@@ -264,24 +277,19 @@ void k_integrate_event(DevNet n, TickArgs ta)
 #pragma unroll
     for (int k = 0; k < NPW; ++k) {
         const int jl = wave * NPW + k;                // within the slice
-        const size_t cj = (size_t)c * n.N + j0 + k;   // uniform
         const int32_t in = acc[acc_index<NS_>(lane, jl)];
-        int32_t fl = n.vmin;
-        bool lin = false;
-        if constexpr (EXT) {
-            fl = n.floor[cj];
-            lin = (n.linmask[cj >> 5] >> (cj & 31)) & 1u;
-        }
+        const int32_t lk = __builtin_amdgcn_readlane(p_leak, k), th = __builtin_amdgcn_readlane(p_thr, k);
+        const int32_t rs = __builtin_amdgcn_readlane(p_rst, k);
+        const int32_t fl = EXT ? __builtin_amdgcn_readlane(p_fl, k) : n.vmin;
+        const bool lin = (lin_w >> k) & 1u;
         int32_t vn;
-        const bool fire = lif_update(vreg[k], in, n.leak[cj], n.thr[cj], n.rst[cj], n.vmin, n.vmax, fl, lin, vn) &&
-                          svalid;
+        const bool fire = lif_update(vreg[k], in, lk, th, rs, n.vmin, n.vmax, fl, lin, vn) && svalid;
         __builtin_nontemporal_store(vn, vout + (size_t)k * n.S64);
         const uint64_t word = __ballot(fire);
         myword = lane == k ? word : myword;
-        const uint32_t bit = 1u << (cj & 31);
         em += fire;
-        ro += fire && (n.coremask[cj >> 5] & bit);
-        ou += fire && (n.outmask[cj >> 5] & bit);
+        ro += fire && ((cm_w >> k) & 1u);
+        ou += fire && ((om_w >> k) & 1u);
     }
     if (lane < NPW) {
         const size_t g = (size_t)c * n.N + j0 + lane;
