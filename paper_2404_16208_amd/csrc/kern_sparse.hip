@@ -119,15 +119,16 @@ __global__ __launch_bounds__(64 * DV_WAVES) void k_deliver_event(DevNet n, TickA
 // ---------------------------------------------------------------------------
 // Integration.
 
-// acc index of (sample s, neuron j of the slice): the neuron index is XORed
-// with the sample's low five bits, so the 32 samples a half-wave reads for
-// one neuron fall in 32 different banks.
-template <int NS_> __device__ inline int acc_index(int s, int j) { return s * NS_ + (j ^ (s & 31)); }
+// acc index of (sample s, neuron j of the slice): neuron-major, so the
+// scatter's lanes (one sample each) always hit the bank of their own sample,
+// whatever neurons they add to, and the update's read of one neuron for the
+// wave's 64 samples is 256 contiguous bytes.
+__device__ inline int acc_index(int s, int j) { return j * EV_TS + s; }
 
 // Scatter of one axon word of this lane's sample: a flat loop over
 // (spiking axon, row entry), so lanes with short rows move on to their next
 // axon instead of idling until the wave's longest row ends.
-template <int NS_, typename RowPtr>
+template <typename RowPtr>
 __device__ __forceinline__ void scatter_word(uint32_t bits, int word, int s, const uint32_t *rp, RowPtr rows,
                                              int32_t *acc, unsigned &events)
 {
@@ -146,7 +147,7 @@ __device__ __forceinline__ void scatter_word(uint32_t bits, int word, int s, con
         const uint32_t ent = rows[e++];
         const int j = (int)(ent & 127u);
         const int w = (int)(ent << 16) >> 23;   // bits 7..15, sign-extended
-        atomicAdd(&acc[acc_index<NS_>(s, j)], w);
+        atomicAdd(&acc[acc_index(s, j)], w);
     }
 }
 
@@ -262,9 +263,9 @@ void k_integrate_event(DevNet n, TickArgs ta)
         delivered += (unsigned)__popc(xd[k]);
         const uint32_t bits = xd[k] | xe[k];
         if (staged)
-            scatter_word<NS_>(bits, wi, lane, rp, (const uint16_t *)rows, acc, events);
+            scatter_word(bits, wi, lane, rp, (const uint16_t *)rows, acc, events);
         else
-            scatter_word<NS_>(bits, wi, lane, rp, n.ecsr_ent + e_base, acc, events);
+            scatter_word(bits, wi, lane, rp, n.ecsr_ent + e_base, acc, events);
     }
     if (svalid && (events | delivered))
         atomicAdd(&s_cnt[1][lane], events | (slice == 0 ? delivered << 20 : 0u));   // delivered counted once per core
@@ -277,7 +278,7 @@ void k_integrate_event(DevNet n, TickArgs ta)
 #pragma unroll
     for (int k = 0; k < NPW; ++k) {
         const int jl = wave * NPW + k;                // within the slice
-        const int32_t in = acc[acc_index<NS_>(lane, jl)];
+        const int32_t in = acc[acc_index(lane, jl)];
         const int32_t lk = __builtin_amdgcn_readlane(p_leak, k), th = __builtin_amdgcn_readlane(p_thr, k);
         const int32_t rs = __builtin_amdgcn_readlane(p_rst, k);
         const int32_t fl = EXT ? __builtin_amdgcn_readlane(p_fl, k) : n.vmin;
