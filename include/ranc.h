@@ -325,6 +325,13 @@ typedef struct ranc_tune {
     int32_t route_stage;             /* plain path router: spike bitmaps staged in LDS (0/1) */
     double ms_per_tick;              /* ranc_autotune: time per tick of the chosen shape */
     int32_t candidates;              /* ranc_autotune: number of shapes timed */
+    int32_t route_lanes_per_word;    /* plain path router: 1 = one lane per destination word
+                                        (the three router fields above apply); 8 = eight lanes
+                                        per word, one sample per block row (they do not); 0 in
+                                        ranc_set_launch_shape = chosen automatically (8 when
+                                        the one-lane launch would have fewer blocks than the
+                                        GPU has compute units). Batched routing of several
+                                        networks always runs one lane per word. */
 } ranc_tune;
 
 /*

@@ -33,7 +33,7 @@ def tuned(g, inputs, num_ticks: int, cache_path: str | None = DEFAULT_CACHE) -> 
     shape and whether it came from the cache."""
     import torch
 
-    key = shape_key(g.net, g.S, g.path, torch.cuda.get_device_name(g.workspace.device))
+    key = shape_key(g.net, g.S, g.path, torch.cuda.get_device_name(g.stream.device))
     cache = _load(cache_path) if cache_path else {}
     if key in cache:
         shape = g.launch_shape(cache[key])
@@ -42,7 +42,7 @@ def tuned(g, inputs, num_ticks: int, cache_path: str | None = DEFAULT_CACHE) -> 
     if cache_path:
         cache = _load(cache_path)
         cache[key] = {k: shape[k] for k in ("samples_per_wg", "route_samples_per_block", "route_split",
-                                            "route_stage")}
+                                            "route_stage", "route_lanes_per_word")}
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:

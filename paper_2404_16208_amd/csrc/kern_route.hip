@@ -178,13 +178,12 @@ __global__ __launch_bounds__(ROUTE_THREADS) void k_route_split(DevNet n, int k)
 // Lanes per destination word of the split router.
 static constexpr int ROUTE_SPLIT_K = 8;
 
-// Whether one tick's router runs as k_route_split: the one-lane-per-word
-// launch of this configuration would have fewer blocks than the GPU has
-// compute units.
-static bool route_use_split(const DevNet &n, const RouteCfg &cfg)
+int route_split_lanes() { return ROUTE_SPLIT_K; }
+
+int route_auto_lanes(const DevNet &n, const RouteCfg &cfg)
 {
     const long groups = (n.S + cfg.samples_per_block - 1) / cfg.samples_per_block;
-    return (long)cfg.blocks_per_group * groups < 256;
+    return (long)cfg.blocks_per_group * groups < 256 ? ROUTE_SPLIT_K : 1;
 }
 
 template <int DMAX>
@@ -294,6 +293,7 @@ RouteCfg route_default_cfg(const DevNet &n)
     if (split < 1)
         split = 1;
     c.blocks_per_group = split;
+    c.lanes = route_auto_lanes(n, c);
     return c;
 }
 
@@ -339,20 +339,21 @@ static hipError_t launch_route_s(const DevNet &n, int k, const RouteCfg &cfg, hi
 
 hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st)
 {
-    if (cfg.blocks_per_group < 1)
-        return hipErrorInvalidValue;
-    if (cfg.stage && (size_t)n.C * n.NW * 4 * cfg.samples_per_block > ROUTE_LDS_BYTES)
-        return hipErrorInvalidValue;
-    if ((n.S + cfg.samples_per_block - 1) / cfg.samples_per_block > 65535)
-        return hipErrorInvalidValue;
-    if (route_use_split(n, cfg)) {
-        // S < 256 x samples per block <= 2048 here: one sample per grid row fits
+    if (cfg.lanes == ROUTE_SPLIT_K) {
+        if (n.S > 65535)
+            return hipErrorInvalidValue;   // one sample per grid row
         switch (route_dmax(n.D)) {
         case 4: return launch_route_split<4>(n, k, st);
         case 8: return launch_route_split<8>(n, k, st);
         default: return launch_route_split<16>(n, k, st);
         }
     }
+    if (cfg.lanes != 1 || cfg.blocks_per_group < 1)
+        return hipErrorInvalidValue;
+    if (cfg.stage && (size_t)n.C * n.NW * 4 * cfg.samples_per_block > ROUTE_LDS_BYTES)
+        return hipErrorInvalidValue;
+    if ((n.S + cfg.samples_per_block - 1) / cfg.samples_per_block > 65535)
+        return hipErrorInvalidValue;
     switch (cfg.samples_per_block) {
     case 1: return launch_route_s<1>(n, k, cfg, st);
     case 2: return launch_route_s<2>(n, k, cfg, st);

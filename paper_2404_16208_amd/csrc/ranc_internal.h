@@ -218,6 +218,8 @@ struct RouteCfg {
     int samples_per_block;  // 1, 2, 4 or 8 spike bitmaps per block
     int blocks_per_group;   // blocks sharing one group of samples (split of the destination words)
     int stage;              // stage the bitmaps in LDS
+    int lanes;              // lanes per destination word: 1 (k_route, the fields above apply) or
+                            // route_split_lanes() (k_route_split: one sample per block row)
 };
 
 // Launchers (return the first HIP error, hipSuccess otherwise).
@@ -255,6 +257,10 @@ hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total
 hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int ext,
                                        hipStream_t st);
 RouteCfg route_default_cfg(const DevNet &n);
+int route_split_lanes();
+// Lanes per word chosen for a configuration: the lane-split router when the
+// one-lane launch would have fewer blocks than the GPU has compute units.
+int route_auto_lanes(const DevNet &n, const RouteCfg &cfg);
 int route_dmax(int max_delay);
 int mfma_max_samples_per_wg();
 

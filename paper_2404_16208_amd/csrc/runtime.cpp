@@ -1266,6 +1266,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
         net->rcfg.stage = atoi(e) != 0;
     if ((size_t)n.C * n.NW * 4 * net->rcfg.samples_per_block > 128 * 1024)
         net->rcfg.stage = 0;
+    net->rcfg.lanes = route_auto_lanes(n, net->rcfg);
     net->last_stream = s;
     net->tick = 0;
     net->version = 1;
@@ -1761,9 +1762,17 @@ ranc_status ranc_autotune(ranc_net *net, const uint32_t *inputs, uint32_t flags,
                     rc.samples_per_block = sb;
                     rc.blocks_per_group = split;
                     rc.stage = stage;
+                    rc.lanes = 1;
                     cands.push_back({p.spw, rc});
                 }
             }
+        }
+        if (p.S <= 65535) {
+            // the lane-split router (one sample per block row; the fields
+            // above do not apply to it), once
+            RouteCfg rc = def;
+            rc.lanes = route_split_lanes();
+            cands.push_back({p.spw, rc});
         }
         if (cands.empty())
             cands.push_back({p.spw, def});
@@ -1837,6 +1846,7 @@ ranc_status ranc_autotune(ranc_net *net, const uint32_t *inputs, uint32_t flags,
     out->route_stage = tiled ? 0 : net->rcfg.stage;
     out->ms_per_tick = best / num_ticks;
     out->candidates = (int32_t)cands.size();
+    out->route_lanes_per_word = tiled ? 0 : net->rcfg.lanes;
     return RANC_OK;
 }
 
@@ -1867,6 +1877,13 @@ ranc_status ranc_set_launch_shape(ranc_net *net, const ranc_tune *shape)
         return fail(RANC_EINVAL, "staged spike bitmaps of %d samples exceed the router's LDS", sb);
     if ((p.S + sb - 1) / sb > 65535)
         return fail(RANC_EINVAL, "too many sample groups for the router grid");
+    const int lanes = shape->route_lanes_per_word;
+    if (lanes != 0 && lanes != 1 && lanes != route_split_lanes())
+        return fail(RANC_EINVAL, "route_lanes_per_word %d must be 0 (automatic), 1 or %d", lanes,
+                    route_split_lanes());
+    rc.lanes = lanes ? lanes : route_auto_lanes(net->dn, rc);
+    if (rc.lanes != 1 && p.S > 65535)
+        return fail(RANC_EINVAL, "the lane-split router takes at most 65535 samples");
     drop_graphs(net);
     net->rcfg = rc;
     return RANC_OK;
@@ -1883,6 +1900,7 @@ ranc_status ranc_get_launch_shape(const ranc_net *net, ranc_tune *out)
     out->route_stage = mf ? 0 : net->rcfg.stage;
     out->ms_per_tick = 0.0;
     out->candidates = 0;
+    out->route_lanes_per_word = mf ? 0 : net->rcfg.lanes;
     return RANC_OK;
 }
 

@@ -74,7 +74,7 @@ class ranc_counters(C.Structure):
 class ranc_tune(C.Structure):
     _fields_ = [("samples_per_wg", C.c_int32), ("route_samples_per_block", C.c_int32),
                 ("route_split", C.c_int32), ("route_stage", C.c_int32),
-                ("ms_per_tick", C.c_double), ("candidates", C.c_int32)]
+                ("ms_per_tick", C.c_double), ("candidates", C.c_int32), ("route_lanes_per_word", C.c_int32)]
 
 
 SPIKE_DTYPE = np.dtype([("tick", "<i8"), ("core", "<i4"), ("neuron", "<i4")])

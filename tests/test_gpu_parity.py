@@ -73,13 +73,62 @@ def test_random_shapes(shape, path):
     assert_parity(net, x, T, path, what=f"rand{shape[:7]}")
 
 
-def test_large_core_count_unstaged_route():
+@pytest.mark.parametrize("lanes", [1, 8], ids=["one_lane", "lane_split"])
+def test_large_core_count_unstaged_route(lanes):
     # 1280 cores x 512 neurons: the per-sample spike bitmap (80 KiB) exceeds the
-    # LDS staging size, so the router reads spikes from global memory.
+    # LDS staging size, so the one-lane router reads spikes from global memory
+    # (forced here: with 3 samples the automatic choice is the lane-split form)
+    from paper_2404_16208_amd.ranc import RancNet
     net = W.random_net(77, 1280, 64, 512, 2, weight_bits=9, max_delay=6, grid_w=40, density=0.3,
                        p_core=0.8, p_out=0.1, input_cores=list(range(0, 1280, 3)), config_id=701)
     x = W.bernoulli_inputs(12, net, 3, 5, 0.3, config_id=701)
-    assert_parity(net, x, 5, "plain", what="C1280N512")
+    g = RancNet(net, 3, 5, path="plain")
+    auto = g.launch_shape()
+    assert auto["route_lanes_per_word"] == 8 and auto["route_stage"] == 0
+    shape = g.launch_shape(dict(auto, route_lanes_per_word=lanes))
+    assert shape["route_lanes_per_word"] == lanes and shape["route_stage"] == 0
+    g.run(x, 5)
+    ref = oracle_results(net, x, 5, [0, 1, 2])
+    for s2 in (0, 1, 2):
+        assert_sample_equal(g, ref[s2], s2, 5, what=f"C1280N512/lanes{lanes}")
+
+
+@pytest.mark.parametrize("D", [3, 7, 12], ids=["dmax4", "dmax8", "dmax16"])
+@pytest.mark.parametrize("form", ["one_lane_staged", "one_lane_unstaged", "lane_split"])
+def test_router_forms(D, form):
+    """Every router form with every delay-register width (4, 8, 16), forced
+    through the launch shape and reported back by it: per-tick launches for
+    the first call, a graph replay for the second, the scheduler ring wrapping
+    more than once; every sample against the oracle."""
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.random_net(300 + D, 24, 128, 128, 4, max_delay=D, grid_w=6, density=0.25, p_core=0.85, p_out=0.1,
+                       thr_range=(32, 200), input_cores=list(range(0, 24, 3)), config_id=703)
+    S, T1, T2 = 37, D + 2, 2 * D + 3
+    x = W.bernoulli_inputs(20 + D, net, S, T1 + T2, 0.25, config_id=703)
+    g = RancNet(net, S, max(T1, T2), path="plain")
+    lanes = 8 if form == "lane_split" else 1
+    stage = 1 if form == "one_lane_staged" else 0
+    shape = g.launch_shape({"route_samples_per_block": 2, "route_split": 2, "route_stage": stage,
+                            "route_lanes_per_word": lanes})
+    assert shape["route_lanes_per_word"] == lanes and shape["route_stage"] == stage
+    g.run(np.ascontiguousarray(x[:, :T1]), T1)
+    g.run(np.ascontiguousarray(x[:, T1:]), T2, graph=True)
+    ref = oracle_results(net, x, T1 + T2, range(S))
+    for s2 in range(S):
+        assert_sample_equal(g, ref[s2], s2, T1 + T2, what=f"router/{form}/D{D}")
+
+
+def test_router_automatic_form():
+    """The automatic choice: the lane-split router while the one-lane launch
+    would have fewer blocks than the GPU has compute units, else one lane."""
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.random_net(310, 24, 128, 128, 4, max_delay=4, grid_w=6, input_cores=[0], config_id=703)
+    small = RancNet(net, 8, 4, path="plain").launch_shape()
+    big = RancNet(net, 4096, 4, path="plain").launch_shape()
+    assert small["route_lanes_per_word"] == 8
+    assert big["route_lanes_per_word"] == 1
+    blocks = big["route_split"] * -(-4096 // big["route_samples_per_block"])
+    assert blocks >= 256
 
 
 def test_no_input_no_output_cores():
