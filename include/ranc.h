@@ -81,7 +81,9 @@ enum {
  * library owns, never on the caller's) and replayed with one graph launch on
  * `stream` afterwards. The scheduler slot and raster row of each tick are
  * read from a tick counter kept in the workspace, so a replay is exact from
- * any starting tick. Results are identical to the per-launch form. */
+ * any starting tick. Results are identical to the per-launch form. A handle
+ * keeps at most 16 captured loops; capturing another drops the least recently
+ * replayed one (after synchronizing the handle's stream). */
 #define RANC_RUN_GRAPH 2u
 /* With several networks per call: run the MFMA-path networks of each tick in
  * one persistent launch (one workgroup per compute unit pulls units from a
@@ -309,6 +311,9 @@ typedef struct ranc_profile {
     int64_t route_launches;
     double graph_ms;             /* summed duration of tick-loop graph launches */
     int64_t graph_launches;
+    int64_t graphs_held;         /* captured tick loops the handle holds now (at most 16: the
+                                    least recently replayed one is dropped to capture another) */
+    int64_t graphs_dropped;      /* captured tick loops dropped since load */
 } ranc_profile;
 
 /* Enable (1) or disable (0) timing; enabling clears the totals. Host-side only. */

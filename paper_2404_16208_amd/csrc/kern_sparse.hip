@@ -272,7 +272,7 @@ void k_integrate_event(DevNet n, TickArgs ta)
     lds_barrier();
 
     // ---- 2. update, one neuron of the wave at a time for all 64 samples
-    unsigned em = 0, ro = 0, ou = 0;
+    uint32_t fm = 0;       // bit k: this lane's sample fired on neuron j0 + k
     uint64_t myword = 0;   // lane k < NPW: the history word of neuron j0 + k
     int32_t *vout = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
 #pragma unroll
@@ -281,17 +281,25 @@ void k_integrate_event(DevNet n, TickArgs ta)
         const int32_t in = acc[acc_index(lane, jl)];
         const int32_t lk = __builtin_amdgcn_readlane(p_leak, k), th = __builtin_amdgcn_readlane(p_thr, k);
         const int32_t rs = __builtin_amdgcn_readlane(p_rst, k);
-        const int32_t fl = EXT ? __builtin_amdgcn_readlane(p_fl, k) : n.vmin;
-        const bool lin = (lin_w >> k) & 1u;
         int32_t vn;
-        const bool fire = lif_update(vreg[k], in, lk, th, rs, n.vmin, n.vmax, fl, lin, vn) && svalid;
+        bool fire;
+        if constexpr (EXT) {
+            const int32_t fl = __builtin_amdgcn_readlane(p_fl, k);
+            fire = lif_update(vreg[k], in, lk, th, rs, n.vmin, n.vmax, fl, (lin_w >> k) & 1u, vn);
+        } else {
+            // 32-bit potentials, absolute reset, no floor: the saturating add
+            // is the whole clamp (the same arithmetic as lif_update)
+            const int32_t u = __builtin_elementwise_add_sat(vreg[k], in + lk);
+            fire = u >= th;
+            vn = fire ? rs : u;
+        }
+        fire = fire && svalid;
         __builtin_nontemporal_store(vn, vout + (size_t)k * n.S64);
         const uint64_t word = __ballot(fire);
         myword = lane == k ? word : myword;
-        em += fire;
-        ro += fire && ((cm_w >> k) & 1u);
-        ou += fire && ((om_w >> k) & 1u);
+        fm |= (uint32_t)fire << k;
     }
+    const unsigned em = (unsigned)__popc(fm), ro = (unsigned)__popc(fm & cm_w), ou = (unsigned)__popc(fm & om_w);
     if (lane < NPW) {
         const size_t g = (size_t)c * n.N + j0 + lane;
         n.hist[((size_t)q_now * CN + g) * HG + tile] = myword;

@@ -579,13 +579,18 @@ struct Profiler {
     int64_t launches[3] = {0, 0, 0};
 };
 
-// A captured tick loop: num_ticks ticks reading inputs at `base`.
+// A captured tick loop: num_ticks ticks reading inputs at `base`. A handle
+// keeps at most MAX_CAPTURED_LOOPS of them and drops the least recently
+// replayed one to capture a new one (callers that cycle through many input
+// buffers would otherwise hold one graph per address forever).
 struct CapturedLoop {
     int num_ticks;
     const uint32_t *base;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    uint64_t used;   // replay counter of the handle at the last replay
 };
+constexpr size_t MAX_CAPTURED_LOOPS = 16;
 
 // A batch of networks run together, as last set up by ranc_run_ticks with
 // this handle first; its tables are in this handle's workspace.
@@ -618,6 +623,8 @@ struct ranc_net {
     uint64_t uid = 0;   // unique per loaded handle
     Batch batch;
     std::vector<CapturedLoop> loops;
+    uint64_t replays = 0;              // captured-loop replays (recency of the cached loops)
+    uint64_t loops_dropped = 0;        // captured loops dropped to respect MAX_CAPTURED_LOOPS
     hipStream_t cap_stream = nullptr;  // private stream used only for capture
     RouteCfg rcfg;
     Profiler prof;
@@ -778,9 +785,28 @@ static ranc_status run_captured(ranc_net *net, const uint32_t *base, int num_tic
             hipGraphDestroy(graph);
             return hip_fail(e, "instantiating the tick loop");
         }
-        net->loops.push_back({num_ticks, base, graph, exec});
+        if (net->loops.size() >= MAX_CAPTURED_LOOPS) {
+            // drop the least recently used loop; its last replay may still be
+            // queued, so wait for the handle's stream first
+            e = hipStreamSynchronize(net->last_stream);
+            if (e == hipSuccess && net->last_stream != s)
+                e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                hipGraphExecDestroy(exec);
+                hipGraphDestroy(graph);
+                return hip_fail(e, "synchronizing before dropping a captured tick loop");
+            }
+            auto old = std::min_element(net->loops.begin(), net->loops.end(),
+                                        [](const CapturedLoop &x, const CapturedLoop &y) { return x.used < y.used; });
+            hipGraphExecDestroy(old->exec);
+            hipGraphDestroy(old->graph);
+            net->loops.erase(old);
+            ++net->loops_dropped;
+        }
+        net->loops.push_back({num_ticks, base, graph, exec, 0});
         loop = &net->loops.back();
     }
+    loop->used = ++net->replays;
     int slot = -1;
     hipError_t e = prof_begin(net, 2, s, &slot);
     if (e == hipSuccess)
@@ -1679,6 +1705,8 @@ ranc_status ranc_profile_read(ranc_net *net, ranc_profile *out)
     out->route_launches = net->prof.launches[1];
     out->graph_ms = net->prof.ms[2];
     out->graph_launches = net->prof.launches[2];
+    out->graphs_held = (int64_t)net->loops.size();
+    out->graphs_dropped = (int64_t)net->loops_dropped;
     return RANC_OK;
 }
 

@@ -64,7 +64,8 @@ class ranc_spike(C.Structure):
 class ranc_profile(C.Structure):
     _fields_ = [("integrate_ms", C.c_double), ("route_ms", C.c_double),
                 ("integrate_launches", C.c_int64), ("route_launches", C.c_int64),
-                ("graph_ms", C.c_double), ("graph_launches", C.c_int64)]
+                ("graph_ms", C.c_double), ("graph_launches", C.c_int64),
+                ("graphs_held", C.c_int64), ("graphs_dropped", C.c_int64)]
 
 
 class ranc_counters(C.Structure):
@@ -309,7 +310,7 @@ class RancNet:
     device: ranc_load_network_static)."""
 
     def __init__(self, net, num_samples: int, max_ticks_per_call: int, path="auto", device="cuda",
-                 static_workspace: bool = False):
+                 static_workspace: bool = False, workspace_fill: int | None = None):
         import torch
 
         self.net = net
@@ -325,6 +326,8 @@ class RancNet:
         else:
             nbytes = ranc_workspace_bytes(self.desc, num_samples, max_ticks_per_call, p)
             self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            if workspace_fill is not None:   # e.g. a poison byte, to show nothing reads unwritten memory
+                self.workspace.fill_(workspace_fill)
             self.stream = torch.cuda.current_stream(self.workspace.device)
             self.handle = ranc_load_network(self.desc, num_samples, max_ticks_per_call, p,
                                             self.workspace.data_ptr(), self.workspace.numel(),

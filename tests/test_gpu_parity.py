@@ -595,3 +595,59 @@ def test_sparse_mesh_paths_agree():
         assert_sample_equal(gs, r, s, T, what="sparse16x16/sparse")
     tot = gs.total_counters()
     assert tot["delivered"] > 0 and tot["events"] > 0
+
+
+def test_captured_loop_cache_is_bounded():
+    """20 input buffers at 20 addresses, each run as a graph replay: the handle
+    keeps at most 16 captured loops (the least recently replayed ones are
+    dropped), a dropped loop is captured again on its next use, and results
+    stay exact throughout."""
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.random_net(320, 8, 128, 128, 4, max_delay=3, grid_w=4, input_cores=[0, 2, 5], config_id=711)
+    S, TC, calls = 70, 2, 24
+    x = W.bernoulli_inputs(21, net, S, TC * calls, 0.2, config_id=711)
+    bufs = [torch.empty((S, TC) + x.shape[2:], dtype=torch.int32, device="cuda") for _ in range(20)]
+    g = RancNet(net, S, TC, path="mfma")
+    g.profile(True)
+    for i in range(calls):
+        b = bufs[i % 20]   # buffers 0..3 come back after 16 others were captured
+        b.copy_(torch.from_numpy(np.ascontiguousarray(x[:, i * TC:(i + 1) * TC]).view(np.int32)))
+        g.run(b, TC, graph=True)
+    prof = g.profile_read()
+    assert prof["graphs_held"] == 16 and prof["graphs_dropped"] == 8, prof
+    T = TC * calls
+    ref = oracle_results(net, x, T, [0, 35, 69])
+    for s2, r in ref.items():
+        assert_sample_equal(g, r, s2, T, what="graph cache")
+    g.close()
+
+
+@pytest.mark.parametrize("path", ["plain", "mfma", "sparse"])
+def test_workspace_poisoned_before_load(path):
+    """A workspace filled with 0xA5 bytes before load gives the same results as
+    the oracle: the library reads no workspace byte it has not written (state,
+    scheduler, history, counters, raster, link counts), across two calls, one
+    of them a graph replay."""
+    import torch
+    from paper_2404_16208_amd.ranc import RancNet, decode_raster
+    net = W.random_net(321, 12, 128, 256, 4, max_delay=5, grid_w=4, density=0.25, p_core=0.7, p_out=0.25,
+                       thr_range=(32, 200), input_cores=[0, 3, 7, 11], config_id=712)
+    S, T1, T2 = 70, 5, 6
+    x = W.bernoulli_inputs(22, net, S, T1 + T2, 0.2, config_id=712)
+    g = RancNet(net, S, 6, path=path, workspace_fill=0xA5)
+    g.count_links(True)
+    g.run(np.ascontiguousarray(x[:, :T1]), T1)
+    g.run(torch.from_numpy(np.ascontiguousarray(x[:, T1:]).view(np.int32)).cuda(), T2, graph=True)
+    raster = torch.empty(g.raster_bytes(T2, "neuron"), dtype=torch.uint8, device="cuda")
+    g.copy_raster(T1, T1 + T2, raster, "neuron")
+    torch.cuda.synchronize()
+    T = T1 + T2
+    ref = oracle_results(net, x, T, [0, 33, 69])
+    words = raster.cpu().numpy().view(np.uint64).reshape(T2, -1, 2)
+    for s2, r in ref.items():
+        assert_sample_equal(g, r, s2, T, what=f"poisoned/{path}")
+        assert np.array_equal(g.links(s2), r["links"]), f"poisoned/{path}: links of sample {s2}"
+        ev = r["events"]
+        assert np.array_equal(decode_raster(words, g.output_neurons(), T1, s2, "neuron"), ev[ev[:, 0] >= T1])
+    g.close()
