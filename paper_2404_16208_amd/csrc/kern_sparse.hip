@@ -26,7 +26,7 @@
 // neuron within the slice in 7, signed 9-bit weight in 9). For every spiking
 // axon of a sample the row's weights are added to the sample's input
 // currents, so the work is the number of synaptic events, not A x N per
-// sample. One workgroup of 4 wavefronts per (core, slice of <= 128 neurons,
+// sample. One workgroup of 8 wavefronts per (core, slice of <= 128 neurons,
 // 64-sample tile); a lane is a sample:
 //   0. loads that do not depend on each other are issued first and together:
 //      the slice's row starts and rows (for LDS), the lane's delivered and
@@ -50,7 +50,7 @@ namespace ranc {
 
 static constexpr int EV_TS = 64;          // samples per workgroup (one history word)
 static constexpr int EV_NS = 128;         // neurons per slice, at most
-static constexpr int EV_WAVES = 4;        // wavefronts per integration workgroup
+static constexpr int EV_WAVES = 8;        // wavefronts per integration workgroup
 static constexpr int EV_CSR_LDS = 3072;   // row entries staged in LDS (6 KiB)
 static constexpr int DV_WAVES = 4;        // wavefronts per delivery workgroup
 
@@ -152,7 +152,7 @@ __device__ __forceinline__ void scatter_word(uint32_t bits, int word, int s, con
 }
 
 template <int A_, int NS_, bool EXT>
-__global__ __launch_bounds__(64 * EV_WAVES) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(64 * EV_WAVES) __attribute__((amdgpu_waves_per_eu(6)))
 void k_integrate_event(DevNet n, TickArgs ta)
 {
     constexpr int W_ = A_ / 32;                             // axon words
@@ -202,7 +202,7 @@ void k_integrate_event(DevNet n, TickArgs ta)
         rv[r] = staged && i < (int)(e_pad / 8) ? src[i] : uint4{0u, 0u, 0u, 0u};
     }
     // delivered (scheduler row of the tick) and external input words of this
-    // lane's sample for the wave's scatter words w = wave, wave + 4, ...
+    // lane's sample for the wave's scatter words w = wave, wave + EV_WAVES, ...
     uint32_t xd[WPW], xe[WPW];
     const int ci = n.in_index[c];
     const uint32_t *dlv = n.ring + ((size_t)c * n.S64 + s) * W_;
@@ -253,7 +253,7 @@ void k_integrate_event(DevNet n, TickArgs ta)
     }
     lds_barrier();
 
-    // ---- 1. scatter: lane = sample; wave w takes axon words w, w + 4, ...
+    // ---- 1. scatter: lane = sample; wave w takes axon words w, w + EV_WAVES, ...
     unsigned events = 0, delivered = 0;
 #pragma unroll
     for (int k = 0; k < WPW; ++k) {
