@@ -648,7 +648,14 @@ __device__ __forceinline__ void batch_unit(const BatchEntry &e, const TickArgs &
     static_assert(!(TWO && A_ == 512) ||
                   8 * sizeof(typename L::VTile) + sizeof(typename L::Xch) <= 8 * sizeof(MfmaLds<512, 256>::VTile),
                   "exchange does not fit the staging area");
-    integrate_mfma_unit<A_, N_, TWO, true, false>(e.n, ta, e.spw, bid, reinterpret_cast<typename L::ATile *>(a_raw),
+    // Units store each tile's history words at once (no LDS history buffer).
+    // A buffer carved for the widest shape would not serve the others: the
+    // buffer of a shape with 256 axons or fewer (HB = 8) is twice the widest
+    // shape's (HB = 4), so those shapes would index past its end.
+    constexpr bool kHistBuf = false;
+    static_assert(!kHistBuf || sizeof(typename L::HBuf) <= sizeof(MfmaLds<512, 256>::HBuf),
+                  "this shape's history buffer is larger than the widest shape's");
+    integrate_mfma_unit<A_, N_, TWO, true, kHistBuf>(e.n, ta, e.spw, bid, reinterpret_cast<typename L::ATile *>(a_raw),
                                                   reinterpret_cast<typename L::VTile *>(v_raw),
                                                   reinterpret_cast<typename L::XTile *>(x_raw), nullptr,
                                                   reinterpret_cast<typename L::Xch *>(
