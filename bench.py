@@ -69,6 +69,20 @@ def integrate_algorithmic_bytes(net, S: int, path: str) -> dict:
     return dict(per_unit=per_unit, units=S * C, total=state + params, state=state, params=params, planes=planes)
 
 
+def resident_algorithmic_bytes(net, S: int, T: int) -> dict:
+    """Bytes one state-resident launch (T ticks, all samples) must move at
+    minimum: the potentials read and written once per call (8 N per (sample,
+    core)); per tick the axon spike bits read and the spike bits written
+    (A/8 + N/8 per (sample, core)), the external input bits and the raster
+    words; the network's compact parameters once (as for the per-tick
+    launch)."""
+    C, A, N = net.num_cores, net.num_axons, net.num_neurons
+    tick = integrate_algorithmic_bytes(net, S, "mfma")
+    per_tick_state = tick["state"] - S * C * 8 * N
+    total = S * C * 8 * N + T * per_tick_state + tick["params"]
+    return dict(total=total, potentials=S * C * 8 * N, per_tick=per_tick_state, params=tick["params"])
+
+
 def mfma_ops_per_launch(net, S: int) -> int:
     """int8 multiply-adds the MFMA path executes per launch, counted as 2 ops
     each: every 64-sample tile of every core multiplies [64 x A] by [A x N]
@@ -97,12 +111,12 @@ def read_traffic(src_hash: str, path: str = TRAFFIC_FILE, key: str = "hbm_bytes_
         return None
 
 
-def time_steps(g, xd, T, warmup, steps, torch, graph=False):
+def time_steps(g, xd, T, warmup, steps, torch, graph=False, resident=False):
     """Time `steps` calls of T ticks; the library's HIP events on the launch
-    stream time every kernel launch (or every graph launch) inside the same
-    timed region."""
+    stream time every kernel launch (or every graph or state-resident launch)
+    inside the same timed region."""
     for _ in range(warmup):
-        g.run(xd, T, graph=graph)
+        g.run(xd, T, graph=graph, resident=resident)
     torch.cuda.synchronize()
     before = g.total_counters()
     st = torch.cuda.current_stream()
@@ -111,7 +125,7 @@ def time_steps(g, xd, T, warmup, steps, torch, graph=False):
     torch.cuda.synchronize()
     e0.record(st)
     for _ in range(steps):
-        g.run(xd, T, graph=graph)
+        g.run(xd, T, graph=graph, resident=resident)
     e1.record(st)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
@@ -453,6 +467,7 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time per-launch calls instead of graph replays")
+    ap.add_argument("--skip-resident", action="store_true", help="skip the state-resident tick loop leg")
     ap.add_argument("--workload", default="mnist512",
                     choices=["mnist512", "sparse-mesh", "sweep", "table1", "stream"],
                     help="mnist512: the headline line (default); sparse-mesh: the event-driven vs dense "
@@ -585,6 +600,31 @@ def main():
     g.close()
     del g
     torch.cuda.empty_cache()
+
+    if not args.skip_resident:
+        # the same steps as state-resident launches (one per call)
+        print("[bench] mfma path, state-resident tick loop", file=sys.stderr, flush=True)
+        gr = RancNet(net, S, T, path="mfma")
+        rms, rdelta, rprof = time_steps(gr, xd, T, args.warmup, args.steps, torch, resident=True)
+        r_launch_ms = rprof["resident_ms"] / max(1, rprof["resident_launches"])
+        rb = resident_algorithmic_bytes(net, S, T)
+        r_ops = T * mfma_ops_per_launch(net, S)
+        out["resident"] = {
+            "value": rdelta["events"] / (rms / 1e3), "unit": "synaptic events/s", "ms_per_step": rms / args.steps,
+            "steps": args.steps, "launch_avg_ms": r_launch_ms, "launches_timed": rprof["resident_launches"],
+            "same_events_as_graph": rdelta["events"] == delta["events"],
+            "roofline": {"bound": "hbm", "achieved": rb["total"] / (r_launch_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": rb["total"] / (r_launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": rb["total"], "kernel": "k_mfma_resident<256,two planes>"},
+            "mfma": {"bound": "mfma", "executed_int8_ops_per_launch": r_ops,
+                     "achieved": r_ops / (r_launch_ms / 1e3) / 1e12, "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOPS",
+                     "util": r_ops / (r_launch_ms / 1e3) / 1e12 / INT8_MFMA_PEAK_TOPS},
+            "note": "all ticks of a call in one cooperative launch; potentials of each 64-sample group kept "
+                    "in LDS across the call's ticks; one grid barrier per tick"}
+        out["resident_speedup_vs_graph"] = out["ms_per_step"] / out["resident"]["ms_per_step"]
+        gr.close()
+        del gr
+        torch.cuda.empty_cache()
 
     # End to end, as a user sees one step from a cold handle: load (parameter
     # upload), one step with the inputs in host memory (staged over PCIe), and

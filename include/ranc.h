@@ -45,7 +45,9 @@ typedef enum ranc_status {
     RANC_EDEVICE = -4,      /* a HIP call or a kernel failed */
     RANC_ESTATE = -5,       /* call not valid in the handle's state (e.g. ticks no longer retained) */
     RANC_ETRUNC = -6,       /* output buffer too small; the required size is reported */
-    RANC_EUNSUPPORTED = -7  /* shape or option the library does not implement */
+    RANC_EUNSUPPORTED = -7, /* shape or option the library does not implement */
+    RANC_ETIMEOUT = -8      /* a bounded wait inside a persistent launch gave up (the state is
+                               undefined until ranc_reset_state) */
 } ranc_status;
 
 /* Destination kinds of a neuron's spikes. */
@@ -90,6 +92,23 @@ enum {
  * work queue, largest first; LDS sized for the largest shape) instead of one
  * launch per shape class. Results are identical. */
 #define RANC_BATCH_PERSISTENT 4u
+/* State-resident run (one network per call; MFMA path, cores of 256 neurons
+ * and at most 256 axons, no link counting): all ticks of the call in one
+ * persistent launch. Each workgroup keeps up to two cores' weight planes in
+ * registers and, for one 64-sample group after another, the group's
+ * potentials of its cores in LDS across all ticks of the call, so the
+ * potentials cross HBM once per call instead of once per tick; the grid
+ * synchronizes after every tick (spikes of tick t reach their destinations
+ * at t + d, d >= 1, through the spike history in HBM). The grid is launched
+ * cooperatively (every workgroup resident at once); every wait at a grid
+ * barrier is bounded (2 s, or RANC_RESIDENT_WAIT_US microseconds from the
+ * environment), and a wait that gives up ends the launch and the call
+ * returns RANC_ETIMEOUT. The call synchronizes `stream` to read that
+ * outcome. RANC_RUN_GRAPH is ignored with this flag (one launch per call
+ * already). Results are identical to the per-tick forms; calls may mix
+ * them on one handle. Networks it cannot run are refused with
+ * RANC_EUNSUPPORTED (nothing is queued). */
+#define RANC_RUN_RESIDENT 8u
 
 /*
  * Network description (host memory; the library copies it during
@@ -202,8 +221,10 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples,
  * RANC_INPUTS_ON_DEVICE, else in host memory (copied to the workspace's
  * staging area first). Consecutive calls continue the same simulation:
  * spikes whose delivery tick lies beyond the call stay scheduled.
- * flags: RANC_INPUTS_ON_DEVICE, RANC_RUN_GRAPH, RANC_BATCH_PERSISTENT (see
- * above); other bits are rejected with RANC_EINVAL. With RANC_RUN_GRAPH and device inputs, the
+ * flags: RANC_INPUTS_ON_DEVICE, RANC_RUN_GRAPH, RANC_BATCH_PERSISTENT,
+ * RANC_RUN_RESIDENT (see above); other bits are rejected with RANC_EINVAL. After a
+ * call that returned RANC_ETIMEOUT, runs of that handle return RANC_ESTATE until
+ * ranc_reset_state. With RANC_RUN_GRAPH and device inputs, the
  * input buffer must stay at the same address to reuse a captured loop.
  *
  * With num_nets > 1 the networks (any shapes, paths and sample counts; each
@@ -314,6 +335,8 @@ typedef struct ranc_profile {
     int64_t graphs_held;         /* captured tick loops the handle holds now (at most 16: the
                                     least recently replayed one is dropped to capture another) */
     int64_t graphs_dropped;      /* captured tick loops dropped since load */
+    double resident_ms;          /* summed duration of state-resident launches (RANC_RUN_RESIDENT) */
+    int64_t resident_launches;
 } ranc_profile;
 
 /* Enable (1) or disable (0) timing; enabling clears the totals. Host-side only. */

@@ -123,6 +123,26 @@ struct TickArgs {
     long long ext_sstride;  // words between consecutive samples of the input block
 };
 
+// Arguments of the state-resident MFMA tick loop (kern_resident.hip): the
+// call's external input (sample s, tick k, input core i, word w at
+// ext_base[s * ext_sstride + k * tick_words + i * W + w], or nullptr) and
+// its number of ticks.
+struct ResidentArgs {
+    const uint32_t *ext_base;
+    long long ext_sstride;
+    long long tick_words;
+    int num_ticks;
+};
+
+// Grid synchronization words of the state-resident loop: arrival counter and
+// give-up flag (zeroed before each launch), and the longest wait, in ticks of
+// the device's constant-rate wall clock.
+struct ResSync {
+    unsigned *ctr;
+    unsigned *abort;
+    unsigned long long wait_ticks;
+};
+
 // Scheduler slot and raster row of the tick at position k of the call.
 __device__ inline int tick_slot(const DevNet &n, int k) { return (n.tick[0] + k) % n.Q; }
 __device__ inline int tick_row(const DevNet &n, int k) { return (n.tick[1] + k) % n.RT; }
@@ -231,6 +251,13 @@ int sparse_slice_width(int N);   // neurons per sparse-path workgroup
 int sparse_row_align();          // entries each slice's rows are aligned to
 hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes,
                                  int samples_per_wg, hipStream_t st);
+// State-resident MFMA tick loop (N = 256 in one slice, A <= 256, at most
+// resident_max_cores_per_wg() cores per workgroup): zeroes the sync words,
+// then launches `grid` workgroups cooperatively.
+hipError_t launch_mfma_resident(const DevNet &n, const ResidentArgs &ra, const ResSync &sy, int grid, int two_planes,
+                                hipStream_t st);
+int resident_blocks_per_cu(int A, int two_planes, int ext);   // 0: the shape is not built
+int resident_max_cores_per_wg();
 hipError_t launch_route(const DevNet &n, int k, const RouteCfg &cfg, hipStream_t st);
 hipError_t launch_reset_state(const DevNet &n, const LinkArgs &l, hipStream_t st);
 hipError_t launch_advance_tick(const DevNet &n, int num_ticks, hipStream_t st);

@@ -47,7 +47,8 @@ enum Region {
     R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
     R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT, R_LINKREC, R_OUTCOL, R_OUTPOS,
     R_PARAMS_END,  // everything before this is uploaded once at load
-    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_LINKD, R_NREG
+    R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_LINKD,
+    R_RSYNC, R_NREG
 };
 
 struct Plan {
@@ -321,6 +322,7 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_OUTCOL] = tiled ? 0 : std::max<size_t>((size_t)p.Wout, 1) * 8;
     p.size[R_OUTPOS] = tiled ? 0 : std::max<size_t>((size_t)p.Nout, 1) * 4;
     p.size[R_LINKD] = (size_t)4 * C * p.S64 * 8;
+    p.size[R_RSYNC] = mf ? 8 : 0;   // state-resident loop: arrival counter, give-up flag
     size_t off = 0;
     for (int r = 0; r < R_NREG; ++r) {
         if (r == R_PARAMS_END)
@@ -574,9 +576,9 @@ struct EventPair {
 struct Profiler {
     bool on = false;
     std::vector<EventPair> pool;          // created on demand, reused
-    std::vector<std::pair<int, int>> used; // (pool index, kind 0=integrate 1=route 2=graph)
-    double ms[3] = {0, 0, 0};
-    int64_t launches[3] = {0, 0, 0};
+    std::vector<std::pair<int, int>> used; // (pool index, kind 0=integrate 1=route 2=graph 3=resident)
+    double ms[4] = {0, 0, 0, 0};           // kind 3: state-resident launches
+    int64_t launches[4] = {0, 0, 0, 0};
 };
 
 // A captured tick loop: num_ticks ticks reading inputs at `base`. A handle
@@ -647,6 +649,7 @@ struct ranc_net {
     uint64_t links_version = 0;
     std::vector<long long> links_host; // mirror of the link difference arrays
     int static_dev = -1;               // device whose library-held workspace this handle holds, or -1
+    bool state_lost = false;           // a state-resident launch gave up: state undefined until reset
 };
 
 static hipError_t prof_begin(ranc_net *net, int kind, hipStream_t s, int *slot)
@@ -815,6 +818,100 @@ static ranc_status run_captured(ranc_net *net, const uint32_t *base, int num_tic
         e = prof_end(net, slot, s);
     if (e != hipSuccess)
         return hip_fail(e, "launching the tick loop");
+    return RANC_OK;
+}
+
+static int device_cu_count();
+
+// Longest wait at a grid barrier of the state-resident loop, in microseconds
+// (a normal wait takes a few). RANC_RESIDENT_WAIT_US overrides it.
+static unsigned long long resident_wait_us()
+{
+    const char *e = getenv("RANC_RESIDENT_WAIT_US");
+    if (e && *e) {
+        char *end = nullptr;
+        const unsigned long long v = strtoull(e, &end, 10);
+        if (end && *end == '\0')
+            return v;
+    }
+    return 2000000ull;
+}
+
+// Why the state-resident loop cannot run this handle (nullptr: it can), and
+// its grid.
+static const char *resident_blocker(const ranc_net *net, int *grid)
+{
+    const Plan &p = net->p;
+    if (p.path != RANC_PATH_MFMA)
+        return "the state-resident loop runs MFMA-path handles only";
+    if (p.N != 256 || p.slices != 1)
+        return "the state-resident loop needs cores of 256 neurons";
+    if (p.A > 256)
+        return "the state-resident loop needs cores of at most 256 axons";
+    if (net->links_on)
+        return "mesh link counting needs the per-tick loop";
+    const int per_cu = resident_blocks_per_cu(p.A, p.two, net->dn.model_ext);
+    const int cus = device_cu_count();
+    if (per_cu < 1 || cus < 1)
+        return "the state-resident kernel cannot be resident on this device";
+    const long long max_wg = (long long)per_cu * cus;
+    const long long cpw = ((long long)p.C + max_wg - 1) / max_wg;
+    if (cpw > resident_max_cores_per_wg())
+        return "too many cores to keep resident on this device";
+    *grid = (int)((p.C + cpw - 1) / cpw);
+    return nullptr;
+}
+
+// All ticks of the call in one cooperative launch (kern_resident.hip), then
+// the count fold and tick advance. The launch's give-up flag is read back
+// before returning (the call synchronizes `s`).
+static ranc_status run_resident(ranc_net *net, const uint32_t *base, int num_ticks, hipStream_t s)
+{
+    const Plan &p = net->p;
+    int grid = 0;
+    if (const char *why = resident_blocker(net, &grid))
+        return fail(RANC_EUNSUPPORTED, "%s", why);
+    int dev = 0, rate_khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess || rate_khz < 1)
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidValue, "reading the device wall-clock rate");
+    ResidentArgs ra;
+    ra.ext_base = base;
+    ra.tick_words = (long long)p.Cin * p.W;
+    ra.ext_sstride = (long long)num_ticks * ra.tick_words;
+    ra.num_ticks = num_ticks;
+    unsigned *sync = (unsigned *)(net->ws + p.off[R_RSYNC]);
+    ResSync sy;
+    sy.ctr = sync;
+    sy.abort = sync + 1;
+    sy.wait_ticks = resident_wait_us() * (unsigned long long)rate_khz / 1000ull;
+    int slot = -1;
+    e = prof_begin(net, 3, s, &slot);
+    if (e == hipSuccess)
+        e = launch_mfma_resident(net->dn, ra, sy, grid, p.two, s);
+    if (e == hipSuccess)
+        e = prof_end(net, slot, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "launching the state-resident tick loop");
+    e = launch_fold_counts(net->dn, num_ticks, s);
+    if (e == hipSuccess)
+        e = launch_advance_tick(net->dn, num_ticks, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "advancing the tick");
+    unsigned gave_up = 0;
+    e = hipMemcpyAsync(&gave_up, sy.abort, sizeof(gave_up), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "reading the state-resident loop's give-up flag");
+    if (gave_up) {
+        net->state_lost = true;
+        return fail(RANC_ETIMEOUT, "a grid barrier of the state-resident loop waited longer than %llu us; "
+                                   "the state is undefined until ranc_reset_state",
+                    resident_wait_us());
+    }
     return RANC_OK;
 }
 
@@ -1349,8 +1446,18 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
         if (num_ticks < 1 || num_ticks > nets[i]->p.RT)
             return fail(RANC_EINVAL, "num_ticks %d outside [1, max_ticks_per_call=%d]", num_ticks, nets[i]->p.RT);
     }
-    if (flags & ~(RANC_INPUTS_ON_DEVICE | RANC_RUN_GRAPH | RANC_BATCH_PERSISTENT))
+    if (flags & ~(RANC_INPUTS_ON_DEVICE | RANC_RUN_GRAPH | RANC_BATCH_PERSISTENT | RANC_RUN_RESIDENT))
         return fail(RANC_EINVAL, "unknown flags 0x%x", flags);
+    for (int i = 0; i < num_nets; ++i)
+        if (nets[i]->state_lost)
+            return fail(RANC_ESTATE, "nets[%d]: a state-resident run gave up; reset the state first", i);
+    if (flags & RANC_RUN_RESIDENT) {
+        if (num_nets != 1)
+            return fail(RANC_EUNSUPPORTED, "RANC_RUN_RESIDENT runs one network per call");
+        int grid = 0;
+        if (const char *why = resident_blocker(nets[0], &grid))
+            return fail(RANC_EUNSUPPORTED, "%s", why);
+    }
     for (int i = 0; i < num_nets; ++i)
         for (int j = 0; j < i; ++j)
             if (nets[i] == nets[j])
@@ -1380,8 +1487,14 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
         if (st != RANC_OK)
             return st;
     } else {
-        ranc_status st = (flags & RANC_RUN_GRAPH) ? run_captured(nets[0], bases[0], num_ticks, s)
-                                                 : queue_ticks(nets[0], bases[0], num_ticks, s, true);
+        ranc_status st = (flags & RANC_RUN_RESIDENT) ? run_resident(nets[0], bases[0], num_ticks, s)
+                         : (flags & RANC_RUN_GRAPH)  ? run_captured(nets[0], bases[0], num_ticks, s)
+                                                     : queue_ticks(nets[0], bases[0], num_ticks, s, true);
+        if (st == RANC_ETIMEOUT) {   // the ticks ran partially: the call counts as run
+            nets[0]->tick += num_ticks;
+            nets[0]->last_stream = s;
+            ++nets[0]->version;
+        }
         if (st != RANC_OK)
             return st;
     }
@@ -1680,7 +1793,7 @@ ranc_status ranc_profile_enable(ranc_net *net, int32_t enable)
         if (st != RANC_OK)
             return st;
         net->prof.used.clear();
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             net->prof.ms[k] = 0;
             net->prof.launches[k] = 0;
         }
@@ -1707,6 +1820,8 @@ ranc_status ranc_profile_read(ranc_net *net, ranc_profile *out)
     out->graph_launches = net->prof.launches[2];
     out->graphs_held = (int64_t)net->loops.size();
     out->graphs_dropped = (int64_t)net->loops_dropped;
+    out->resident_ms = net->prof.ms[3];
+    out->resident_launches = net->prof.launches[3];
     return RANC_OK;
 }
 
@@ -1721,6 +1836,7 @@ ranc_status ranc_reset_state(ranc_net *net, void *stream)
     net->tick = 0;
     net->last_stream = s;
     ++net->version;
+    net->state_lost = false;
     return RANC_OK;
 }
 

@@ -19,14 +19,16 @@ LIB_PATH = os.path.join(_HERE, "libranc.so")
 RANC_ABI_VERSION = 2
 RANC_OK, RANC_EINVAL, RANC_ERANGE, RANC_ENOMEM, RANC_EDEVICE, RANC_ESTATE, RANC_ETRUNC, RANC_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
+RANC_ETIMEOUT = -8
 STATUS_NAMES = {0: "RANC_OK", -1: "RANC_EINVAL", -2: "RANC_ERANGE", -3: "RANC_ENOMEM", -4: "RANC_EDEVICE",
-                -5: "RANC_ESTATE", -6: "RANC_ETRUNC", -7: "RANC_EUNSUPPORTED"}
+                -5: "RANC_ESTATE", -6: "RANC_ETRUNC", -7: "RANC_EUNSUPPORTED", -8: "RANC_ETIMEOUT"}
 RANC_PATH_AUTO, RANC_PATH_PLAIN, RANC_PATH_MFMA, RANC_PATH_SPARSE = 0, 1, 2, 3
 PATHS = {"auto": RANC_PATH_AUTO, "plain": RANC_PATH_PLAIN, "mfma": RANC_PATH_MFMA, "sparse": RANC_PATH_SPARSE}
 RANC_RESET_ABSOLUTE, RANC_RESET_LINEAR = 0, 1
 RANC_INPUTS_ON_DEVICE = 1
 RANC_RUN_GRAPH = 2
 RANC_BATCH_PERSISTENT = 4
+RANC_RUN_RESIDENT = 8
 
 EXPORTED = ("ranc_last_error", "ranc_workspace_bytes", "ranc_load_network", "ranc_run_ticks",
             "ranc_read_spikes", "ranc_read_potentials", "ranc_read_counters", "ranc_current_tick",
@@ -65,7 +67,8 @@ class ranc_profile(C.Structure):
     _fields_ = [("integrate_ms", C.c_double), ("route_ms", C.c_double),
                 ("integrate_launches", C.c_int64), ("route_launches", C.c_int64),
                 ("graph_ms", C.c_double), ("graph_launches", C.c_int64),
-                ("graphs_held", C.c_int64), ("graphs_dropped", C.c_int64)]
+                ("graphs_held", C.c_int64), ("graphs_dropped", C.c_int64),
+                ("resident_ms", C.c_double), ("resident_launches", C.c_int64)]
 
 
 class ranc_counters(C.Structure):
@@ -349,11 +352,14 @@ class RancNet:
     def tick(self) -> int:
         return ranc_current_tick(self.handle)
 
-    def run(self, inputs, num_ticks: int, graph: bool = False):
+    def run(self, inputs, num_ticks: int, graph: bool = False, resident: bool = False):
         """Advance by num_ticks. ``inputs``: None, a numpy uint32 array or a CUDA tensor
         (int32/uint32 bits) of shape [S, num_ticks, C_in, A/32]. ``graph``: run the
-        ticks as one captured HIP graph (captured on first use, then replayed)."""
-        flags, ptr, keep = (RANC_RUN_GRAPH if graph else 0), None, None
+        ticks as one captured HIP graph (captured on first use, then replayed).
+        ``resident``: run them in one state-resident persistent launch
+        (RANC_RUN_RESIDENT; synchronizes the stream)."""
+        flags = (RANC_RUN_GRAPH if graph else 0) | (RANC_RUN_RESIDENT if resident else 0)
+        ptr, keep = None, None
         if inputs is not None:
             if isinstance(inputs, np.ndarray):
                 keep = np.ascontiguousarray(inputs, dtype=np.uint32)

@@ -10,6 +10,7 @@ every neuron and the five counters, for every sample listed.
   c2  512-core MNIST-shaped net, all 100 samples x 32 ticks, plain and MFMA
       paths, plus the class read-out (argmax of class spike counts)
   c3  the same net, all 1024 samples x 32 ticks in one batched MFMA launch
+      per tick, and in one state-resident launch per call
   c4  all 64 design-space variants in one batch, 64 samples x 16 ticks (two
       8-tick calls), per-shape-class launches and the persistent launch,
       samples 0 and 63 of every variant
@@ -36,7 +37,7 @@ def _gpu():
     from paper_2404_16208_amd import ranc  # noqa: F401  (fails loudly if the library is missing)
 
 
-def _run_collect(g, chunks, samples, graph=True):
+def _run_collect(g, chunks, samples, graph=True, resident=False):
     """Advance the handle call by call; chunks yields (device input or None,
     ticks). Output spikes of the listed samples are read after every call, so
     every tick is compared, not only the ticks the raster still holds."""
@@ -44,7 +45,7 @@ def _run_collect(g, chunks, samples, graph=True):
     got = {s: [] for s in samples}
     t = g.tick
     for xd, k in chunks:
-        g.run(xd, k, graph=graph)
+        g.run(xd, k, graph=graph, resident=resident)
         torch.cuda.synchronize()
         for s in samples:
             got[s].append(g.spikes(s, t, t + k))
@@ -107,13 +108,15 @@ def test_c2_mnist512_all_100_samples(mnist100, path):
 
 
 @pytest.mark.timeout(900)
-def test_c3_mnist512_all_1024_samples():
-    """The benchmark's configuration: 1024 samples in one MFMA launch per
-    tick, the 32-tick loop as one graph replay, inputs in device memory; every
-    sample against the oracle (in batches of 64 samples, so that only one
-    batch's spike lists are held at a time). A second replay (ticks 32..63,
-    the same input buffer, as the benchmark's second step) is checked on 64
-    samples against 64-tick oracle runs."""
+@pytest.mark.parametrize("mode", ["graph", "resident"])
+def test_c3_mnist512_all_1024_samples(mode):
+    """The benchmark's configuration: 1024 samples on the MFMA path, the
+    32-tick loop as one graph replay of per-tick launches, or as one
+    state-resident launch, inputs in device memory; every sample against the
+    oracle (in batches of 64 samples, so that only one batch's spike lists
+    are held at a time). A second call (ticks 32..63, the same input buffer,
+    as the benchmark's second step) is checked on 64 samples against 64-tick
+    oracle runs."""
     import torch
     from paper_2404_16208_amd.ranc import RancNet
     net = W.mnist_net(0)
@@ -121,22 +124,22 @@ def test_c3_mnist512_all_1024_samples():
     x = W.mnist_inputs(0, 1024, 32)
     xd = torch.from_numpy(x.view(np.int32)).cuda()
     g = RancNet(net, 1024, 32, path="mfma")
-    log("[c3] GPU: one graph replay of 32 ticks")
-    g.run(xd, 32, graph=True)
+    log(f"[c3] GPU: one {mode} call of 32 ticks")
+    g.run(xd, 32, graph=mode == "graph", resident=mode == "resident")
     torch.cuda.synchronize()
     for b0 in range(0, 1024, 64):
         batch = range(b0, b0 + 64)
         ref = {r["sample"]: r for r in O.simulate(net, x, 32, samples=batch)}
-        _compare(g, ref, {s: g.spikes(s, 0, 32) for s in batch}, "c3/mfma")
+        _compare(g, ref, {s: g.spikes(s, 0, 32) for s in batch}, f"c3/{mode}")
         log(f"[c3] samples {b0}..{b0 + 63} equal the oracle")
     picks = list(range(0, 1024, 16))
-    spikes2 = _run_collect(g, [(xd, 32)], picks)
+    spikes2 = _run_collect(g, [(xd, 32)], picks, graph=mode == "graph", resident=mode == "resident")
     x2 = np.concatenate([x[picks], x[picks]], axis=1)
     ref2 = {}
     for r in O.simulate(net, x2, 64):
         ev = r["events"]
         ref2[picks[r["sample"]]] = dict(r, events=ev[ev[:, 0] >= 32])
-    _compare(g, ref2, spikes2, "c3/mfma replay 2")
+    _compare(g, ref2, spikes2, f"c3/{mode} call 2")
     log("[c3] second replay: 64 samples equal 64-tick oracle runs")
     g.close()
 
