@@ -462,7 +462,7 @@ def test_call_errors_leave_state_untouched():
     g.run(np.ascontiguousarray(x[:, :8]), 8)
     stream = torch.cuda.current_stream().cuda_stream
     for flags, ticks, handles, status in ((0, 9, [g.handle], R.RANC_EINVAL), (0, 0, [g.handle], R.RANC_EINVAL),
-                                          (8, 4, [g.handle], R.RANC_EINVAL),
+                                          (16, 4, [g.handle], R.RANC_EINVAL),
                                           (0, 4, [g.handle, g.handle], R.RANC_EINVAL)):
         with pytest.raises(R.RancError) as ei:
             R.ranc_run_ticks(handles, None, flags, ticks, stream)
