@@ -33,14 +33,17 @@ HBM_PEAK_GBS = 8000.0
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 MFMA
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_integrate_mfma_mnist512_s1024.txt")
 TRAFFIC_FILE_MESH = os.path.join(ROOT, "profiles", "traffic_integrate_mesh16384_s64.txt")
-KERNEL_SOURCES = ["paper_2404_16208_amd/csrc/kern_mfma.hip", "paper_2404_16208_amd/csrc/kern_sparse.hip",
-                  "paper_2404_16208_amd/csrc/kern_common.h", "paper_2404_16208_amd/csrc/kern_bits.h",
-                  "paper_2404_16208_amd/csrc/ranc_internal.h"]
+# Sources whose text decides each measured kernel's device code: a traffic
+# summary under profiles/ is used only while these hash to the value it
+# records.
+_CSRC = "paper_2404_16208_amd/csrc/"
+KERNEL_SOURCES_MFMA = [_CSRC + f for f in ("kern_mfma.hip", "kern_common.h", "kern_bits.h", "ranc_internal.h")]
+KERNEL_SOURCES_MESH = KERNEL_SOURCES_MFMA + [_CSRC + "kern_sparse.hip"]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=KERNEL_SOURCES_MFMA) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -230,7 +233,8 @@ def bench_sparse_mesh(args, torch, np):
         ticks = args.steps * T
         per_tick = prof["graph_ms"] / max(1, prof["graph_launches"] * T)
         byts = sparse_mesh_algorithmic_bytes(net, S, delta["delivered"] / ticks, ext_bits)[path]
-        traffic = read_traffic(kernel_source_hash(), TRAFFIC_FILE_MESH, f"{path}_hbm_bytes_per_launch")
+        traffic = read_traffic(kernel_source_hash(KERNEL_SOURCES_MESH), TRAFFIC_FILE_MESH,
+                               f"{path}_hbm_bytes_per_launch")
         out[path] = {"value": delta["events"] / (ms / 1e3), "ms_per_tick": ms / ticks,
                      "core_ticks_per_s": S * C * ticks / (ms / 1e3),
                      "integrate_avg_ms": per_tick,

@@ -30,18 +30,22 @@
 // 64-sample tile); a lane is a sample:
 //   0. loads that do not depend on each other are issued first and together:
 //      the slice's row starts and rows (for LDS), the lane's delivered and
-//      external input words, then the potentials of the wave's neurons (V is
-//      neuron-major, [C][N][S64], so a wave's load of one neuron is 256
-//      contiguous bytes), which stay in flight through the scatter;
+//      external input words;
 //   1. scatter: each lane walks the spiking axons of its sample in its wave's
 //      axon words and, flat over (axon, entry), adds every entry's weight to
 //      its sample's current of that neuron in LDS (LDS atomic add: waves
 //      share neurons);
-//   2. update: per neuron of the wave, leak, threshold and reset for all 64
-//      samples at once (lif_update); the wave's ballot of the spikes is the
+//   2. update: the potentials of the wave's neurons are loaded (V is
+//      neuron-major, [C][N][S64], so a wave's load of one neuron is 256
+//      contiguous bytes), then per neuron leak, threshold and reset for all
+//      64 samples at once (lif_update); the wave's ballot of the spikes is the
 //      neuron's 64-sample history word; potentials are stored back.
-// Barriers order LDS only (lds_barrier), so no wave waits for the potential
-// loads of the others.
+// Loading the potentials only for the update keeps them out of the registers
+// during the scatter: the kernel then fits 64 VGPRs, so four workgroups (32
+// wavefronts, as many as the LDS holds) share a CU, and their potential
+// loads and scatters overlap (6% faster on the 16384-core mesh than loading
+// them in step 0 with three workgroups per CU). Barriers order LDS only
+// (lds_barrier), so no wave waits for the potential loads of the others.
 #include "kern_bits.h"
 #include "kern_common.h"
 #include "ranc_internal.h"
@@ -152,7 +156,7 @@ __device__ __forceinline__ void scatter_word(uint32_t bits, int word, int s, con
 }
 
 template <int A_, int NS_, bool EXT>
-__global__ __launch_bounds__(64 * EV_WAVES) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ __launch_bounds__(64 * EV_WAVES) __attribute__((amdgpu_waves_per_eu(8)))
 void k_integrate_event(DevNet n, TickArgs ta)
 {
     constexpr int W_ = A_ / 32;                             // axon words
@@ -215,11 +219,6 @@ void k_integrate_event(DevNet n, TickArgs ta)
         xd[k] = (svalid && wi < W_) ? dlv[wi] : 0u;
         xe[k] = (ext && wi < W_) ? ext[wi] : 0u;
     }
-    int32_t vreg[NPW];
-    const int32_t *vin = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
-#pragma unroll
-    for (int k = 0; k < NPW; ++k)
-        vreg[k] = __builtin_nontemporal_load(vin + (size_t)k * n.S64);
     // parameters of the wave's neurons, lane k holding neuron j0 + k (one
     // load each, broadcast per neuron in the update): the kernel stores
     // through other pointers, so per-neuron loads inside the update would be
@@ -272,6 +271,11 @@ void k_integrate_event(DevNet n, TickArgs ta)
     lds_barrier();
 
     // ---- 2. update, one neuron of the wave at a time for all 64 samples
+    int32_t vreg[NPW];
+    const int32_t *vin = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k)
+        vreg[k] = __builtin_nontemporal_load(vin + (size_t)k * n.S64);
     uint32_t fm = 0;       // bit k: this lane's sample fired on neuron j0 + k
     uint64_t myword = 0;   // lane k < NPW: the history word of neuron j0 + k
     int32_t *vout = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
