@@ -492,6 +492,7 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time per-launch calls instead of graph replays")
     ap.add_argument("--skip-resident", action="store_true", help="skip the state-resident tick loop leg")
+    ap.add_argument("--skip-links", action="store_true", help="skip the leg with mesh link counting on")
     ap.add_argument("--workload", default="mnist512",
                     choices=["mnist512", "sparse-mesh", "sweep", "table1", "stream"],
                     help="mnist512: the headline line (default); sparse-mesh: the event-driven vs dense "
@@ -648,6 +649,19 @@ def main():
         out["resident_speedup_vs_graph"] = out["ms_per_step"] / out["resident"]["ms_per_step"]
         gr.close()
         del gr
+        torch.cuda.empty_cache()
+
+    if not args.skip_links:
+        # the same steps with packets per mesh link counted on every tick
+        print("[bench] mfma path with mesh link counts", file=sys.stderr, flush=True)
+        gl = RancNet(net, S, T, path="mfma")
+        gl.count_links(True)
+        lms, _, lprof = time_steps(gl, xd, T, args.warmup, max(2, args.steps // 4), torch, graph=graph)
+        out["link_counts"] = {"ms_per_step": lms / max(2, args.steps // 4),
+                              "overhead_vs_headline": (lms / max(2, args.steps // 4)) / out["ms_per_step"] - 1.0,
+                              "note": "packets per mesh link (XY route) counted per sample on every tick"}
+        gl.close()
+        del gl
         torch.cuda.empty_cache()
 
     # End to end, as a user sees one step from a cold handle: load (parameter

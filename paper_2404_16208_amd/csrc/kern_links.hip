@@ -18,24 +18,30 @@
 // of a core's neurons and are added once per core and sample. Entries are
 // 64-bit and signed (two's complement in unsigned atomics).
 //
-// Mapping: one wavefront per (core, 64-sample word), lane = sample. The
-// neurons' spike words of the tick and their precomputed path ends are read
-// 64 neurons at a time, one per lane, and walked neuron by neuron with the
-// word of the current neuron broadcast from its lane; entries are atomic adds
-// into [direction][core][S64] (consecutive samples at consecutive addresses).
+// Sample-tiled paths (MFMA, event-driven), where the tick's spikes are
+// history words (64 samples of one neuron per word): the entries are gathered
+// by the difference-array row they land on. At load, every (direction, core)
+// row gets the list of its entries (source neuron, +1 or -1). One wavefront
+// per (row, 64-sample word) reads the history words of 64 listed neurons at a
+// time (lane = entry), transposes the 64 x 64 bit block so that a lane holds
+// one sample's bits of those entries, and adds popcount(+1 entries) -
+// popcount(-1 entries): the row's 64 counters of that word are the
+// wavefront's alone, so they are updated without atomics. The wavefronts of
+// one row (its 64-sample words) run in one workgroup and read the same
+// history lines (a neuron's words are consecutive).
+//
+// Plain path (spike words per (sample, core)): one wavefront per (core,
+// 64-sample word), lane = sample. The neurons' spike words of the tick and
+// their precomputed path ends are read 64 neurons at a time, one per lane,
+// and walked neuron by neuron with the word of the current neuron broadcast
+// from its lane; entries are atomic adds into [direction][core][S64]
+// (consecutive samples at consecutive addresses).
 #include "kern_bits.h"
 #include "ranc_internal.h"
 
 namespace ranc {
 
 static constexpr int LINK_WAVES = 4;   // wavefronts per workgroup
-
-__device__ inline unsigned long long bcast64(uint64_t v, int q)
-{
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, q);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), q);
-    return (unsigned long long)hi << 32 | lo;
-}
 
 __global__ __launch_bounds__(64 * LINK_WAVES) void k_link_counts(DevNet n, LinkArgs l, int k)
 {
@@ -45,23 +51,16 @@ __global__ __launch_bounds__(64 * LINK_WAVES) void k_link_counts(DevNet n, LinkA
         return;   // whole wavefronts
     const int lane = threadIdx.x & 63;
     const int c = wv / HG, i = wv - c * HG;
-    const bool hist = n.vlayout != VLAYOUT_CSN;
-    // sample of this lane: bit `lane` of a history word (MFMA path: the MFMA
-    // result row order within each 32-sample half), else lane = sample
-    const int s = n.vlayout == VLAYOUT_BRICK ? 64 * i + 32 * (lane >> 5) + sigma32(lane & 31) : 64 * i + lane;
+    const int s = 64 * i + lane;   // this lane's sample
     const bool live = s < n.S;
     const size_t CS = (size_t)n.C * n.S64;
     unsigned long long *D = reinterpret_cast<unsigned long long *>(l.d);
-    const int slot = tick_slot(n, k);
     unsigned src_xp = 0, src_xm = 0, src_yp = 0, src_ym = 0;   // runs that start at this core
     for (int jb = 0; jb < n.N; jb += 64) {
         const size_t g = (size_t)c * n.N + jb + lane;
         const int2 rec = l.rec[g];
-        uint64_t w = 0;
         uint32_t sw0 = 0, sw1 = 0;
-        if (hist) {
-            w = n.hist[((size_t)slot * n.C * n.N + g) * HG + i];
-        } else if (live) {
+        if (live) {
             const uint32_t *sp = n.spk + ((size_t)s * n.C + c) * n.NW + jb / 32;
             sw0 = sp[0];
             sw1 = sp[1];
@@ -71,17 +70,9 @@ __global__ __launch_bounds__(64 * LINK_WAVES) void k_link_counts(DevNet n, LinkA
             const int yc = __builtin_amdgcn_readlane(rec.y, q);
             if ((xc & yc) < 0)
                 continue;   // no hop (not routed to a core, or to its own core)
-            bool fire;
-            if (hist) {
-                const unsigned long long wq = bcast64(w, q);
-                if (!wq)
-                    continue;
-                fire = (wq >> lane) & 1ull;
-            } else {
-                fire = (((q < 32 ? sw0 : sw1) >> (q & 31)) & 1u) != 0u;
-                if (!__ballot(fire))
-                    continue;
-            }
+            const bool fire = (((q < 32 ? sw0 : sw1) >> (q & 31)) & 1u) != 0u;
+            if (!__ballot(fire))
+                continue;
             if (xc >= 0) {
                 if (xc & 1)
                     src_xm += fire;
@@ -116,10 +107,64 @@ __global__ __launch_bounds__(64 * LINK_WAVES) void k_link_counts(DevNet n, LinkA
         atomicAdd(&D[3 * CS + at], (unsigned long long)src_ym);
 }
 
+static constexpr int LINK_GATHER_WAVES = 16;   // wavefronts per workgroup of the gather form
+
+__global__ __launch_bounds__(64 * LINK_GATHER_WAVES) void k_link_counts_gather(DevNet n, LinkArgs l, int k)
+{
+    const int HG = n.S64 / 64;
+    const long long wv = (long long)blockIdx.x * LINK_GATHER_WAVES + (threadIdx.x >> 6);
+    if (wv >= 4LL * n.C * HG)
+        return;   // whole wavefronts
+    const int lane = threadIdx.x & 63;
+    const int row = (int)(wv / HG);   // direction * C + core
+    const int i = (int)(wv - (long long)row * HG);
+    const size_t CN = (size_t)n.C * n.N;
+    const int slot = tick_slot(n, k);
+    const uint32_t b = l.rows[row], e = l.rows[row + 1];
+    int acc_lo = 0, acc_hi = 0;   // lanes x < 32: history bits x and 32 + x of word i
+    for (uint32_t c0 = b; c0 < e; c0 += 64) {
+        uint64_t w = 0;
+        bool neg = false;
+        if (c0 + lane < e) {
+            const uint32_t en = l.ents[c0 + lane];
+            neg = (en & 1u) != 0u;
+            w = n.hist[((size_t)slot * CN + (en >> 1)) * HG + i];
+        }
+        // lane (h, x): bit j = history bit x (tl) or 32 + x (th) of entry 32 h + j
+        const uint32_t m = (uint32_t)(__ballot(neg) >> (32 * (lane >> 5)));
+        const uint32_t tl = transpose32((uint32_t)w, lane), th = transpose32((uint32_t)(w >> 32), lane);
+        int cl = __popc(tl & ~m) - __popc(tl & m);
+        int ch = __popc(th & ~m) - __popc(th & m);
+        acc_lo += cl + __shfl_xor(cl, 32, 64);
+        acc_hi += ch + __shfl_xor(ch, 32, 64);
+    }
+    if (lane < 32) {
+        // sample of history bit p: the MFMA result row order within each
+        // 32-sample half on the MFMA path, else bit p = sample p
+        const bool mf = n.vlayout == VLAYOUT_BRICK;
+        const int s_lo = 64 * i + (mf ? sigma32(lane) : lane);
+        const int s_hi = 64 * i + 32 + (mf ? sigma32(lane) : lane);
+        unsigned long long *D = reinterpret_cast<unsigned long long *>(l.d) + (size_t)row * n.S64;
+        if (acc_lo)
+            D[s_lo] += (unsigned long long)(long long)acc_lo;
+        if (acc_hi)
+            D[s_hi] += (unsigned long long)(long long)acc_hi;
+    }
+}
+
 hipError_t launch_link_counts(const DevNet &n, const LinkArgs &l, int k, hipStream_t st)
 {
     if (n.N % 64 || !l.d || !l.rec)
         return hipErrorInvalidValue;
+    if (n.vlayout != VLAYOUT_CSN) {
+        if (!l.rows || !l.ents)
+            return hipErrorInvalidValue;
+        const long long waves = 4LL * n.C * (n.S64 / 64);
+        const dim3 grid((unsigned)((waves + LINK_GATHER_WAVES - 1) / LINK_GATHER_WAVES)),
+            block(64 * LINK_GATHER_WAVES);
+        hipLaunchKernelGGL(k_link_counts_gather, grid, block, 0, st, n, l, k);
+        return hipGetLastError();
+    }
     const long long waves = (long long)n.C * (n.S64 / 64);
     const dim3 grid((unsigned)((waves + LINK_WAVES - 1) / LINK_WAVES)), block(64 * LINK_WAVES);
     hipLaunchKernelGGL(k_link_counts, grid, block, 0, st, n, l, k);

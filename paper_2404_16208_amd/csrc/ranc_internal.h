@@ -111,8 +111,10 @@ struct DevNet {
 // Mesh link statistics (kern_links.hip); kept out of DevNet, which travels
 // in batched kernels' arguments.
 struct LinkArgs {
-    const int2 *rec;   // linkrec [C][N]
-    long long *d;      // linkd [4][C][S64]
+    const int2 *rec;         // linkrec [C][N]
+    long long *d;            // linkd [4][C][S64]
+    const uint32_t *rows;    // sample-tiled paths: row starts [4 C + 1] of the entries per (direction, core)
+    const uint32_t *ents;    // entries: source neuron << 1 | (1: the run ends here, 0: it starts here)
 };
 
 // Per-tick launch arguments: the tick's position k in the call (the tick is

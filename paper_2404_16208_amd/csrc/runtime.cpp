@@ -45,7 +45,7 @@ ranc_status hip_fail(hipError_t e, const char *what)
 enum Region {
     R_COLBITS, R_TYPEMASK, R_WTS, R_LEAK, R_THR, R_RST, R_VINIT, R_COREMASK, R_OUTMASK, R_OUTWORD,
     R_ININDEX, R_RTDCNT, R_RTGOFF, R_RTENT, R_DEGB, R_OUTIDX, R_PLANES, R_RTXPTR, R_RTXENT, R_HZERO,
-    R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT, R_LINKREC, R_OUTCOL, R_OUTPOS,
+    R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT, R_LINKREC, R_OUTCOL, R_OUTPOS, R_LINKPTR, R_LINKENT,
     R_PARAMS_END,  // everything before this is uploaded once at load
     R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_LINKD,
     R_RSYNC, R_NREG
@@ -319,6 +319,10 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_BATCH] = BATCH_TABLE_BYTES;
     p.size[R_EXT] = (size_t)RT * S * p.Cin * W * 4;
     p.size[R_LINKREC] = C * N * 8;
+    // sample-tiled paths: for every (direction, core) difference-array row,
+    // the run starts (+1) and ends (-1) that land there, by source neuron
+    p.size[R_LINKPTR] = tiled ? (size_t)(4 * C + 1) * 4 : 0;
+    p.size[R_LINKENT] = tiled ? std::max<size_t>((size_t)4 * E, 1) * 4 : 0;
     p.size[R_OUTCOL] = tiled ? 0 : std::max<size_t>((size_t)p.Wout, 1) * 8;
     p.size[R_OUTPOS] = tiled ? 0 : std::max<size_t>((size_t)p.Nout, 1) * 4;
     p.size[R_LINKD] = (size_t)4 * C * p.S64 * 8;
@@ -534,6 +538,35 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
             lr[2 * i] = xc;
             lr[2 * i + 1] = yc;
         }
+        if (p.size[R_LINKPTR]) {
+            // rows of the difference arrays ([direction][core], direction
+            // 0 +x, 1 -x, 2 +y, 3 -y) and the entries each packet adds to
+            // them: +1 where a run of links starts, -1 where it ends; entry =
+            // source neuron << 1 | (1 for -1), by source neuron within a row
+            uint32_t *tp = (uint32_t *)at(R_LINKPTR);
+            uint32_t *te = (uint32_t *)at(R_LINKENT);
+            std::fill(tp, tp + 4 * (size_t)C + 1, 0u);
+            auto visit = [&](auto &&emit) {
+                for (size_t i = 0; i < (size_t)C * N; ++i) {
+                    const int32_t xc = lr[2 * i], yc = lr[2 * i + 1];
+                    const int c = (int)(i / N);
+                    if (xc >= 0) {
+                        emit((xc & 1) * C + c, i, 0u);
+                        emit((xc & 1) * C + (xc >> 1), i, 1u);
+                    }
+                    if (yc >= 0) {
+                        const int dir = 2 + (yc & 1);
+                        emit(dir * C + (xc >= 0 ? xc >> 1 : c), i, 0u);
+                        emit(dir * C + (yc >> 1), i, 1u);
+                    }
+                }
+            };
+            visit([&](int row, size_t, uint32_t) { ++tp[row + 1]; });
+            for (size_t r = 0; r < 4 * (size_t)C; ++r)
+                tp[r + 1] += tp[r];
+            std::vector<uint32_t> fill(tp, tp + 4 * (size_t)C);
+            visit([&](int row, size_t g, uint32_t neg) { te[fill[row]++] = (uint32_t)g << 1 | neg; });
+        }
     }
     if (p.size[R_OUTIDX]) {
         int32_t *oi = (int32_t *)at(R_OUTIDX);
@@ -642,7 +675,7 @@ struct ranc_net {
     std::vector<int32_t> v_host;       // mirror of the potentials
     uint64_t cnt_version = 0;
     std::vector<unsigned long long> cnt_host; // mirror of the counters
-    LinkArgs lk{nullptr, nullptr};     // mesh link path ends and counts in the workspace
+    LinkArgs lk{nullptr, nullptr, nullptr, nullptr}; // mesh link path ends, rows and counts in the workspace
     const int2 *outcol = nullptr;      // plain path: raster columns (kern_raster.hip)
     const int32_t *opos = nullptr;     // plain path: raster position of each output neuron
     bool links_on = false;             // count packets per mesh link on every tick run
@@ -839,7 +872,7 @@ static unsigned long long resident_wait_us()
 
 // Why the state-resident loop cannot run this handle (nullptr: it can), and
 // its grid.
-static const char *resident_blocker(const ranc_net *net, int *grid)
+static const char *resident_blocker(const ranc_net *net, int num_ticks, int *grid)
 {
     const Plan &p = net->p;
     if (p.path != RANC_PATH_MFMA)
@@ -859,6 +892,10 @@ static const char *resident_blocker(const ranc_net *net, int *grid)
     if (cpw > resident_max_cores_per_wg())
         return "too many cores to keep resident on this device";
     *grid = (int)((p.C + cpw - 1) / cpw);
+    // the arrival counter counts every workgroup at every barrier (one per
+    // tick and 64-sample group) in 32 bits
+    if ((unsigned long long)(p.S64 / 64) * (unsigned long long)num_ticks * (unsigned long long)*grid >= (1ull << 32))
+        return "too many ticks x sample groups for one state-resident launch";
     return nullptr;
 }
 
@@ -869,7 +906,7 @@ static ranc_status run_resident(ranc_net *net, const uint32_t *base, int num_tic
 {
     const Plan &p = net->p;
     int grid = 0;
-    if (const char *why = resident_blocker(net, &grid))
+    if (const char *why = resident_blocker(net, num_ticks, &grid))
         return fail(RANC_EUNSUPPORTED, "%s", why);
     int dev = 0, rate_khz = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1354,6 +1391,8 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.cring = (unsigned long long *)reg(R_CRING);
     n.tick = (int *)reg(R_TICK);
     net->lk.rec = (const int2 *)reg(R_LINKREC);
+    net->lk.rows = p.size[R_LINKPTR] ? (const uint32_t *)reg(R_LINKPTR) : nullptr;
+    net->lk.ents = p.size[R_LINKPTR] ? (const uint32_t *)reg(R_LINKENT) : nullptr;
     net->outcol = p.size[R_OUTCOL] ? (const int2 *)reg(R_OUTCOL) : nullptr;
     net->opos = p.size[R_OUTPOS] ? (const int32_t *)reg(R_OUTPOS) : nullptr;
     net->lk.d = (long long *)reg(R_LINKD);
@@ -1455,7 +1494,7 @@ ranc_status ranc_run_ticks(ranc_net *const *nets, int32_t num_nets, const uint32
         if (num_nets != 1)
             return fail(RANC_EUNSUPPORTED, "RANC_RUN_RESIDENT runs one network per call");
         int grid = 0;
-        if (const char *why = resident_blocker(nets[0], &grid))
+        if (const char *why = resident_blocker(nets[0], num_ticks, &grid))
             return fail(RANC_EUNSUPPORTED, "%s", why);
     }
     for (int i = 0; i < num_nets; ++i)

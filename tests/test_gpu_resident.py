@@ -146,3 +146,20 @@ def test_resident_refuses_what_it_cannot_run():
         g.run(x, 4)                # the handle still runs per tick
         torch.cuda.synchronize()
         g.close()
+
+
+def test_resident_host_inputs_and_library_workspace():
+    """Host inputs (staged by the library) and a handle in the library-held
+    workspace run the state-resident loop too; every sample against the
+    oracle over two calls."""
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.random_net(618, 6, 256, 256, 4, weight_bits=9, max_delay=3, grid_w=3, density=0.25, p_core=0.85,
+                       p_out=0.1, thr_range=(40, 300), config_id=875)
+    x = W.bernoulli_inputs(13, net, 70, 10, 0.15, config_id=875)
+    g = RancNet(net, 70, 5, path="mfma", static_workspace=True)
+    for t0 in (0, 5):
+        g.run(np.ascontiguousarray(x[:, t0:t0 + 5]), 5, resident=True)
+    ref = oracle_results(net, x, 10, range(70))
+    for s in range(70):
+        assert_sample_equal(g, ref[s], s, 10, what="resident, host inputs, library workspace")
+    g.close()
