@@ -719,6 +719,36 @@ def main():
         del gp
         torch.cuda.empty_cache()
 
+    if not args.skip_plain:
+        # the 100-sample configuration of the same net: plain and MFMA paths
+        # (graph replay), and the class read-out of every sample (spikes per
+        # class from the by-sample raster, argmax with the lowest class on ties)
+        S2 = 100
+        print(f"[bench] {S2}-sample configuration, plain and MFMA paths", file=sys.stderr, flush=True)
+        x2 = np.ascontiguousarray(x[:S2])
+        xd2 = torch.from_numpy(x2.view(np.int32)).cuda()
+        c2 = {"samples": S2, "ticks_per_step": T}
+        for path in ("plain", "mfma"):
+            g2 = RancNet(net, S2, T, path=path)
+            ms2, d2, _ = time_steps(g2, xd2, T, 2, max(4, args.steps // 2), torch, graph=True)
+            n2 = max(4, args.steps // 2)
+            c2[path] = {"ms_per_step": ms2 / n2, "synaptic_events_per_s": d2["events"] / (ms2 / 1e3),
+                        "core_ticks_per_s": S2 * C * T * n2 / (ms2 / 1e3)}
+            if path == "plain":
+                g2.reset()
+                g2.run(xd2, T, graph=True)
+                rb = torch.empty(g2.raster_bytes(T, "sample"), dtype=torch.uint8, device="cuda")
+                g2.copy_raster(0, T, rb, "sample")
+                torch.cuda.synchronize()
+                words = rb.cpu().numpy().view(np.uint32).reshape(T, S2, -1)
+                votes = class_votes(words, class_masks(net, g2.output_neurons(), np), np)
+                c2["class_counts"] = np.bincount(np.argmax(votes, axis=1), minlength=10).tolist()
+            g2.close()
+            del g2
+        c2["mfma_speedup_vs_plain"] = c2["plain"]["ms_per_step"] / c2["mfma"]["ms_per_step"]
+        out["c2_100_samples"] = c2
+        torch.cuda.empty_cache()
+
     if not args.skip_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         gc = RancNet(net, S, T, path="mfma")

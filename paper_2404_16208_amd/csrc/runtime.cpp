@@ -857,7 +857,8 @@ static ranc_status run_captured(ranc_net *net, const uint32_t *base, int num_tic
 static int device_cu_count();
 
 // Longest wait at a grid barrier of the state-resident loop, in microseconds
-// (a normal wait takes a few). RANC_RESIDENT_WAIT_US overrides it.
+// (a normal wait takes a few). RANC_RESIDENT_WAIT_US overrides it (at most
+// one hour).
 static unsigned long long resident_wait_us()
 {
     const char *e = getenv("RANC_RESIDENT_WAIT_US");
@@ -865,7 +866,7 @@ static unsigned long long resident_wait_us()
         char *end = nullptr;
         const unsigned long long v = strtoull(e, &end, 10);
         if (end && *end == '\0')
-            return v;
+            return std::min(v, 3600000000ull);
     }
     return 2000000ull;
 }
