@@ -609,8 +609,15 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
     }
 }
 
+// Occupancy request (amdgpu_waves_per_eu(4): at most 128 VGPRs, so two
+// 8-wavefront workgroups per CU): the compiler meets it for the 128-neuron
+// slices with at most 128 axons (a few spilled VGPRs), whose LDS also fits
+// twice per CU, and keeps the larger shapes as they are (one workgroup per
+// CU). On the 64-variant sweep at 64 samples (one tile per workgroup, so no
+// pipelining across tiles) the overlap of two workgroups gains 1.6%.
 template <int A_, int N_, bool TWO, bool EXT>
-__global__ __launch_bounds__(512) void k_integrate_mfma(DevNet n, TickArgs ta, int spw)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_integrate_mfma(DevNet n, TickArgs ta,
+                                                                                               int spw)
 {
     typedef MfmaLds<A_, N_> L;
     __shared__ __attribute__((aligned(16))) typename L::ATile a_lds[2];
@@ -725,7 +732,8 @@ hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total
 // range holds u. The entries come as kernel arguments and the LDS is exactly
 // the shape's, as in the single-network kernel.
 template <int A_, int N_, bool TWO, bool EXT>
-__global__ __launch_bounds__(512) void k_integrate_mfma_group(MfmaGroupArgs g, int k)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_integrate_mfma_group(MfmaGroupArgs g,
+                                                                                                     int k)
 {
     typedef MfmaLds<A_, N_> L;
     __shared__ __attribute__((aligned(16))) typename L::ATile a_lds[2];
