@@ -661,6 +661,11 @@ struct ranc_net {
     uint64_t replays = 0;              // captured-loop replays (recency of the cached loops)
     uint64_t loops_dropped = 0;        // captured loops dropped to respect MAX_CAPTURED_LOOPS
     hipStream_t cap_stream = nullptr;  // private stream used only for capture
+    // batches led by this handle: streams on which the shape classes' tick
+    // chains run side by side, and the fork and join events
+    static constexpr int BATCH_BRANCHES = 4;
+    hipStream_t br_stream[BATCH_BRANCHES] = {};
+    hipEvent_t br_fork = nullptr, br_join[BATCH_BRANCHES] = {};
     RouteCfg rcfg;
     Profiler prof;
     DevNet dn;
@@ -1159,13 +1164,72 @@ static unsigned *batch_queue(ranc_net *lead)
     return (unsigned *)(batch_table(lead, 0) + 2 * BATCH_MAX);
 }
 
+// Branch form of a batch's ticks: the networks of different shape classes do
+// not depend on each other, so each class's launches for all ticks form one
+// chain, and the chains (and the chain of the plain-path networks) run on the
+// lead handle's branch streams side by side, forked from and joined back to
+// `s` with events (under stream capture they become parallel branches of the
+// graph). Used when nothing orders the classes within a tick: one phase, no
+// persistent launch, no link counting, no per-launch timing.
+static hipError_t queue_batch_branches(ranc_net *lead, const Batch &b, hipStream_t s)
+{
+    const BatchEntry *tpl = batch_table(lead, 1);
+    const Batch::Phase &ph = b.phases[0];
+    const int chains = ph.g_num + (ph.pl_num > 0 ? 1 : 0);
+    const int nb = std::min(chains, (int)ranc_net::BATCH_BRANCHES);
+    hipError_t e = hipSuccess;
+    for (int i = 0; e == hipSuccess && i < nb; ++i) {
+        if (!lead->br_stream[i])
+            e = hipStreamCreateWithFlags(&lead->br_stream[i], hipStreamNonBlocking);
+        if (e == hipSuccess && !lead->br_join[i])
+            e = hipEventCreateWithFlags(&lead->br_join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess && !lead->br_fork)
+        e = hipEventCreateWithFlags(&lead->br_fork, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventRecord(lead->br_fork, s);
+    for (int i = 0; e == hipSuccess && i < nb; ++i)
+        e = hipStreamWaitEvent(lead->br_stream[i], lead->br_fork, 0);
+    for (int c = 0; e == hipSuccess && c < chains; ++c) {
+        hipStream_t st = lead->br_stream[c % nb];
+        if (c < ph.g_num) {
+            const Batch::Group &g = b.groups[ph.g_first + c];
+            for (int k = 0; e == hipSuccess && k < b.num_ticks; ++k)
+                e = launch_integrate_mfma_group(g.args, g.units, k, g.code, g.ext, st);
+        } else {
+            const BatchEntry *tp = tpl + ph.pl_first;
+            for (int k = 0; e == hipSuccess && k < b.num_ticks; ++k) {
+                e = launch_integrate_plain_batch(tp, ph.pl_num, ph.pl_units, k, st);
+                if (e == hipSuccess)
+                    e = launch_route_batch(tp, ph.pl_num, ph.rt_units, k, b.rt_lds, st);
+            }
+        }
+    }
+    for (int i = 0; e == hipSuccess && i < nb; ++i) {
+        e = hipEventRecord(lead->br_join[i], lead->br_stream[i]);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, lead->br_join[i], 0);
+    }
+    return e;
+}
+
 static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t s, bool timed)
 {
     const BatchEntry *tmf = batch_table(lead, 0), *tpl = batch_table(lead, 1);
     unsigned *queue = batch_queue(lead);
     timed = timed && lead->prof.on;
+    bool any_links = false;
+    for (const auto &pl : b.phase_links)
+        any_links = any_links || !pl.empty();
+    const bool branches = !b.persistent && b.phases.size() == 1 && !any_links && !timed &&
+                          b.phases[0].g_num + (b.phases[0].pl_num > 0 ? 1 : 0) > 1;
+    if (branches) {
+        hipError_t e = queue_batch_branches(lead, b, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "launching batch integration (branches)");
+    }
     for (const Batch::Phase &ph : b.phases)
-    for (int k = 0; k < b.num_ticks; ++k) {
+    for (int k = 0; !branches && k < b.num_ticks; ++k) {
         int slot = -1;
         hipError_t e = hipSuccess;
         const bool mf = b.persistent ? !b.mf.empty() : ph.g_num > 0;
@@ -2096,6 +2160,14 @@ void ranc_free(ranc_net *net)
     drop_graphs(net);
     if (net->cap_stream)
         hipStreamDestroy(net->cap_stream);
+    for (int i = 0; i < ranc_net::BATCH_BRANCHES; ++i) {
+        if (net->br_stream[i])
+            hipStreamDestroy(net->br_stream[i]);
+        if (net->br_join[i])
+            hipEventDestroy(net->br_join[i]);
+    }
+    if (net->br_fork)
+        hipEventDestroy(net->br_fork);
     for (auto &e : net->prof.pool) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);

@@ -60,11 +60,13 @@ def _assert_same(R, handles, got, S, what):
 
 def test_static_workspace_matches_caller_workspace_twice(R):
     # first load: the 512-core MNIST-shaped net on the event-driven path, 10
-    # samples (63 MiB of the 64 MiB array), 16 ticks as 8 per-launch ticks and
-    # one 8-tick graph replay
+    # samples, at most 4 ticks per call (66.3 MB of the 67.1 MB array), 16
+    # ticks as two 4-tick per-launch calls and two 4-tick graph replays
     net1 = W.mnist_net(0)
     x1 = W.mnist_inputs(0, 10, 16)
-    h1, g1 = _run_both(R, net1, x1, 10, 8, "sparse", [(8, False), (8, True)])
+    need = R.ranc_workspace_bytes(R.Desc(net1), 10, 4, R.RANC_PATH_SPARSE)
+    assert R.RANC_STATIC_WORKSPACE_BYTES - (1 << 20) < need <= R.RANC_STATIC_WORKSPACE_BYTES, need
+    h1, g1 = _run_both(R, net1, x1, 10, 4, "sparse", [(4, False), (4, False), (4, True), (4, True)])
     try:
         assert sum(len(v) for v in g1["static"].values()) > 0
         _assert_same(R, h1, g1, 10, "mnist512/sparse")
