@@ -163,3 +163,25 @@ def test_resident_host_inputs_and_library_workspace():
     for s in range(70):
         assert_sample_equal(g, ref[s], s, 10, what="resident, host inputs, library workspace")
     g.close()
+
+
+def test_resident_ignores_graph_flag():
+    """RANC_RUN_RESIDENT with RANC_RUN_GRAPH runs the state-resident launch
+    (one launch per call already) and captures nothing."""
+    from paper_2404_16208_amd.ranc import RancNet
+    net = W.random_net(619, 4, 128, 256, 2, weight_bits=8, grid_w=2, density=0.25, thr_range=(40, 300),
+                       config_id=876)
+    x = W.bernoulli_inputs(14, net, 64, 8, 0.15, config_id=876)
+    g = RancNet(net, 64, 4, path="mfma")
+    g.profile(True)
+    import torch
+    xd = torch.from_numpy(np.ascontiguousarray(x).view(np.int32)).cuda()
+    for t0 in (0, 4):
+        g.run(xd[:, t0:t0 + 4].contiguous(), 4, graph=True, resident=True)
+    p = g.profile_read()
+    g.profile(False)
+    assert p["resident_launches"] == 2 and p["graph_launches"] == 0 and p["graphs_held"] == 0
+    ref = oracle_results(net, x, 8, range(64))
+    for s in range(64):
+        assert_sample_equal(g, ref[s], s, 8, what="resident with the graph flag")
+    g.close()
