@@ -37,7 +37,8 @@ TRAFFIC_FILE_MESH = os.path.join(ROOT, "profiles", "traffic_integrate_mesh16384_
 # summary under profiles/ is used only while these hash to the value it
 # records.
 _CSRC = "paper_2404_16208_amd/csrc/"
-KERNEL_SOURCES_MFMA = [_CSRC + f for f in ("kern_mfma.hip", "kern_common.h", "kern_bits.h", "ranc_internal.h")]
+KERNEL_SOURCES_MFMA = [_CSRC + f for f in ("kern_mfma.hip", "kern_mfma_unit.h", "kern_mfma_cb.hip", "kern_common.h",
+                                              "kern_bits.h", "ranc_internal.h")]
 KERNEL_SOURCES_MESH = KERNEL_SOURCES_MFMA + [_CSRC + "kern_sparse.hip"]
 
 
@@ -58,9 +59,10 @@ def integrate_algorithmic_bytes(net, S: int, path: str) -> dict:
     Per core, once per launch: the network's parameters in their compact form
     (crossbar bits A*N/8, per-type weights 4GN, axon types as type masks
     GA/8, leak, threshold and reset 12 N), whatever form the path keeps them
-    in. The MFMA path's int8 weight planes (A*N bytes per plane) are this
-    implementation's expansion of those parameters: they are reported as
-    overhead (``planes``), not counted as algorithmic bytes.
+    in. The MFMA path's kernel reads them as crossbar column words (A*N/8),
+    per-type plane bytes (8 per neuron and weight plane) and axon-type bytes
+    (A) per core, and builds its int8 B tiles from those in registers; that
+    form's size is reported as ``b_source``.
     """
     C, A, N, G = net.num_cores, net.num_axons, net.num_neurons, net.num_types
     Cin = len(net.input_cores)
@@ -68,8 +70,10 @@ def integrate_algorithmic_bytes(net, S: int, path: str) -> dict:
     per_unit = 8 * N + A // 8 + N // 8
     state = S * C * per_unit + S * Cin * (A // 8) + S * out_words * 4
     params = C * (A * N // 8 + 4 * G * N + G * A // 8 + 12 * N)
-    planes = C * A * N * (2 if net.weight_bits > 8 else 1) if path == "mfma" else 0
-    return dict(per_unit=per_unit, units=S * C, total=state + params, state=state, params=params, planes=planes)
+    pl = 2 if net.weight_bits > 8 else 1
+    b_source = C * (A * N // 8 + 8 * pl * N + A) if path == "mfma" else 0
+    return dict(per_unit=per_unit, units=S * C, total=state + params, state=state, params=params,
+                b_source=b_source)
 
 
 def resident_algorithmic_bytes(net, S: int, T: int) -> dict:
@@ -203,8 +207,8 @@ def bench_sparse_mesh(args, torch, np):
     """Large sparse mesh (16384 cores of 256x256 on a 128x128 mesh, 64
     samples): the event-driven path against dense MFMA integration, each as
     graph replays of a 10-tick chunk with the inputs resident in HBM. Both are
-    held to the same algorithmic bytes (the network's compact parameters; the
-    MFMA path's weight planes are its own expansion of them)."""
+    held to the same algorithmic bytes (the network's compact parameters,
+    which both paths read in a compact form of their own)."""
     from paper_2404_16208_amd import workloads as W
     from paper_2404_16208_amd.ranc import RancNet
 
@@ -617,7 +621,7 @@ def main():
                      "algorithmic_bytes_per_launch": ib["total"],
                      "bytes_per_unit": ib["per_unit"], "units_per_launch": ib["units"],
                      "params_bytes_per_launch": ib["params"],
-                     "weight_plane_bytes_per_launch": ib["planes"],
+                     "b_source_bytes_per_launch": ib["b_source"],
                      "kernel_source_sha256_16": src_hash},
         "mfma": {"bound": "mfma", "executed_int8_ops_per_launch": mfma_ops_per_launch(net, S),
                  "achieved": mfma_ops_per_launch(net, S) / (avg_int_ms / 1e3) / 1e12,

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libranc.so")
-SOURCES = ["runtime.cpp", "kern_plain.hip", "kern_route.hip", "kern_mfma.hip", "kern_sparse.hip", "kern_links.hip",
+SOURCES = ["runtime.cpp", "kern_plain.hip", "kern_route.hip", "kern_mfma.hip", "kern_mfma_cb.hip", "kern_sparse.hip", "kern_links.hip",
            "kern_raster.hip", "kern_resident.hip", "static_ws.hip"]
 ARCH = "gfx950"
 

@@ -283,8 +283,15 @@ hipError_t launch_route_batch(const BatchEntry *tab, int num, int total, int k, 
 hipError_t launch_advance_batch(const BatchEntry *tab, int num, int num_ticks, unsigned *queue, hipStream_t st);
 hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k, unsigned *queue,
                                        int workgroups, hipStream_t st);
-hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int ext,
+// compact: B tiles built from the compact crossbar (every network of the
+// group has one sample chunk per core), else read from the weight planes
+hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int ext, int compact,
                                        hipStream_t st);
+// the compact-B forms (kern_mfma_cb.hip); arguments validated by the callers above
+hipError_t launch_integrate_mfma_cb(const DevNet &n, const TickArgs &a, int two_planes, int samples_per_wg,
+                                    hipStream_t st);
+hipError_t launch_integrate_mfma_group_cb(const MfmaGroupArgs &g, int total, int k, int code, int ext,
+                                          hipStream_t st);
 RouteCfg route_default_cfg(const DevNet &n);
 int route_split_lanes();
 // Lanes per word chosen for a configuration: the lane-split router when the

@@ -48,7 +48,11 @@ enum Region {
     R_FLOOR, R_LINMASK, R_ECSRPTR, R_ECSRENT, R_LINKREC, R_OUTCOL, R_OUTPOS, R_LINKPTR, R_LINKENT,
     R_PARAMS_END,  // everything before this is uploaded once at load
     R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_LINKD,
-    R_RSYNC, R_NREG
+    R_RSYNC,
+    // MFMA path: the compact B source, uploaded at load as well; kept past
+    // the state regions so that their placement does not depend on it (the
+    // 512-core net's tick is 0.9% slower with these 6 MB in front of them)
+    R_BSRC, R_NREG
 };
 
 struct Plan {
@@ -288,6 +292,10 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     const bool sp = p.path == RANC_PATH_SPARSE;
     const bool tiled = mf || sp;   // sample-tiled paths: spike history, neuron-major raster
     p.size[R_COLBITS] = tiled ? 0 : C * W * N * 4;
+    // MFMA path: crossbar column words, then the per-type plane bytes of
+    // every neuron, then the axon types (the compact source its kernels build
+    // B tiles from; see pack_bsrc)
+    p.size[R_BSRC] = mf ? C * W * N * 4 + C * (p.two ? 2 : 1) * 2 * N * 4 + C * A : 0;
     p.size[R_TYPEMASK] = C * G * W * 4;
     p.size[R_WTS] = C * G * N * 4;
     p.size[R_LEAK] = p.size[R_THR] = p.size[R_RST] = p.size[R_VINIT] = p.size[R_FLOOR] = C * N * 4;
@@ -305,6 +313,9 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     p.size[R_HZERO] = tiled ? HG * 8 : 0;
     p.size[R_DEGB] = mf ? C * p.slices * 2 * A : 0;
     p.size[R_OUTIDX] = tiled ? C * N * 4 : 0;
+    // int8 weight planes: the B source when a core's samples take several
+    // workgroups, of the persistent batch kernel and of the state-resident
+    // kernel (otherwise B is built from R_BSRC)
     p.size[R_PLANES] = mf ? C * A * N * (p.two ? 2 : 1) : 0;
     p.size[R_V] = C * (tiled ? (size_t)p.S64 : (size_t)S) * N * 4;
     // plain path: the scheduler ring; sparse path: the scheduler row of the
@@ -336,6 +347,34 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     }
     p.total = off;
     return RANC_OK;
+}
+
+// Host-side packing of the MFMA path's compact B source (R_BSRC): column
+// words [C][W][N] (bit a % 32 of word a / 32 of neuron j: axon a connects to
+// j); then [C][planes][2][N] words, byte g % 4 of word g / 4 = the plane
+// value of weight(j, g) (two planes: w >> 7, then w & 127; one: w); then the
+// axon types [C][A], one byte each.
+void pack_bsrc(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &buf)
+{
+    buf.assign(p.size[R_BSRC], 0);
+    const int C = p.C, A = p.A, N = p.N, G = p.G, W = p.W, NW = p.NW, PL = p.two ? 2 : 1;
+    uint32_t *col = reinterpret_cast<uint32_t *>(buf.data());
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < A; ++a)
+            for (int j = 0; j < N; ++j)
+                if ((d->crossbar[((size_t)c * A + a) * NW + j / 32] >> (j % 32)) & 1u)
+                    col[((size_t)c * W + a / 32) * N + j] |= 1u << (a % 32);
+    uint32_t *ws = col + (size_t)C * W * N;
+    for (int c = 0; c < C; ++c)
+        for (int j = 0; j < N; ++j)
+            for (int g = 0; g < G; ++g) {
+                const int w = d->weight[((size_t)c * N + j) * G + g];
+                for (int pl = 0; pl < PL; ++pl) {
+                    const uint32_t v = (uint32_t)(PL == 2 ? (pl == 0 ? w >> 7 : w & 127) : w) & 255u;
+                    ws[(((size_t)c * PL + pl) * 2 + g / 4) * N + j] |= v << (8 * (g % 4));
+                }
+            }
+    memcpy(reinterpret_cast<uint8_t *>(ws + (size_t)C * PL * 2 * N), d->axon_type, (size_t)C * A);
 }
 
 // Host-side packing of the parameter region (bytes [0, params_bytes)).
@@ -636,7 +675,7 @@ struct Batch {
     int num_ticks = 0;
     std::vector<BatchEntry> mf, pl;
     // MFMA shape classes (one launch each per tick), unless persistent
-    struct Group { int first, num, units, code, ext; MfmaGroupArgs args; };
+    struct Group { int first, num, units, code, ext, compact; MfmaGroupArgs args; };
     std::vector<Group> groups;
     // Phases: networks whose combined per-tick state fits the GPU's last-level
     // cache; all ticks of a phase run before the next phase starts. Groups
@@ -887,6 +926,8 @@ static const char *resident_blocker(const ranc_net *net, int num_ticks, int *gri
         return "the state-resident loop needs cores of 256 neurons";
     if (p.A > 256)
         return "the state-resident loop needs cores of at most 256 axons";
+    if (!net->dn.planes)
+        return "the state-resident loop needs the weight planes";
     if (net->links_on)
         return "mesh link counting needs the per-tick loop";
     const int per_cu = resident_blocks_per_cu(p.A, p.two, net->dn.model_ext);
@@ -997,8 +1038,8 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         std::vector<std::pair<size_t, int>> foot;
         for (int i = 0; i < num; ++i) {
             const Plan &p = nets[i]->p;
-            foot.push_back({p.params_bytes + p.size[R_V] + p.size[R_HIST] + p.size[R_RING] + p.size[R_SPK] +
-                                p.size[R_CNT],
+            foot.push_back({p.params_bytes + p.size[R_BSRC] + p.size[R_V] + p.size[R_HIST] + p.size[R_RING] +
+                                p.size[R_SPK] + p.size[R_CNT],
                             i});
         }
         std::stable_sort(foot.begin(), foot.end(), [](const std::pair<size_t, int> &x,
@@ -1062,6 +1103,8 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         return (double)e.spw * (e.n.N / e.n.slices) * (e.n.A + 64) * ((e.code & 1) ? 2 : 1);
     };
     auto ext = [](const BatchEntry &e) { return e.n.model_ext; };
+    // one sample chunk per core: the group builds its B tiles from R_BSRC
+    auto compact = [](const BatchEntry &e) { return e.n.S <= e.spw ? 1 : 0; };
     long long mu = 0, pu = 0, ru = 0;
     if (persistent) {
         // one unit numbering, largest units first
@@ -1080,13 +1123,15 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
                 return x.code < y.code;
             if (ext(x) != ext(y))
                 return ext(x) < ext(y);
+            if (compact(x) != compact(y))
+                return compact(x) < compact(y);
             return work(x) > work(y);
         });
         for (size_t i = 0; i < b.mf.size(); ++i) {
             BatchEntry &e = b.mf[i];
             if (b.groups.empty() || b.mf[b.groups.back().first].phase != e.phase ||
                 b.groups.back().code != e.code || b.groups.back().ext != ext(e) ||
-                b.groups.back().num == MFMA_GROUP_MAX) {
+                b.groups.back().compact != compact(e) || b.groups.back().num == MFMA_GROUP_MAX) {
                 b.groups.push_back(Batch::Group());
                 Batch::Group &g = b.groups.back();
                 memset(&g.args, 0, sizeof g.args);
@@ -1094,6 +1139,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
                 g.num = g.units = 0;
                 g.code = e.code;
                 g.ext = ext(e);
+                g.compact = compact(e);
             }
             Batch::Group &g = b.groups.back();
             if ((long long)g.units + e.units > INT32_MAX)
@@ -1195,7 +1241,7 @@ static hipError_t queue_batch_branches(ranc_net *lead, const Batch &b, hipStream
         if (c < ph.g_num) {
             const Batch::Group &g = b.groups[ph.g_first + c];
             for (int k = 0; e == hipSuccess && k < b.num_ticks; ++k)
-                e = launch_integrate_mfma_group(g.args, g.units, k, g.code, g.ext, st);
+                e = launch_integrate_mfma_group(g.args, g.units, k, g.code, g.ext, g.compact, st);
         } else {
             const BatchEntry *tp = tpl + ph.pl_first;
             for (int k = 0; e == hipSuccess && k < b.num_ticks; ++k) {
@@ -1239,7 +1285,7 @@ static ranc_status queue_batch_ticks(ranc_net *lead, const Batch &b, hipStream_t
                 e = launch_integrate_mfma_batch(tmf, (int)b.mf.size(), b.mf_units, k, queue, b.mf_workgroups, s);
             for (int g = ph.g_first; e == hipSuccess && !b.persistent && g < ph.g_first + ph.g_num; ++g)
                 e = launch_integrate_mfma_group(b.groups[g].args, b.groups[g].units, k, b.groups[g].code,
-                                                b.groups[g].ext, s);
+                                                b.groups[g].ext, b.groups[g].compact, s);
             if (e == hipSuccess && timed)
                 e = prof_end(lead, slot, s);
             if (e != hipSuccess)
@@ -1425,7 +1471,10 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.model_ext = neuron_model_ext(desc) ? 1 : 0;
     n.floor = (const int32_t *)reg(R_FLOOR);
     n.linmask = (const uint32_t *)reg(R_LINMASK);
-    n.colbits = (const uint32_t *)reg(R_COLBITS);
+    // the plain path's column words, or the MFMA path's compact B source
+    // (which starts with the same words)
+    n.colbits = p.size[R_BSRC] ? (const uint32_t *)reg(R_BSRC)
+                : p.size[R_COLBITS] ? (const uint32_t *)reg(R_COLBITS) : nullptr;
     n.typemask = (const uint32_t *)reg(R_TYPEMASK);
     n.wts = (const int32_t *)reg(R_WTS);
     n.leak = (const int32_t *)reg(R_LEAK);
@@ -1441,7 +1490,7 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
     n.rt_ent = (const uint32_t *)reg(R_RTENT);
     n.degb = (const uint32_t *)reg(R_DEGB);
     n.outidx = (const int32_t *)reg(R_OUTIDX);
-    n.planes = (const uint4 *)reg(R_PLANES);
+    n.planes = p.size[R_PLANES] ? (const uint4 *)reg(R_PLANES) : nullptr;
     n.V = (int32_t *)reg(R_V);
     n.ring = (uint32_t *)reg(R_RING);
     n.spk = (uint32_t *)reg(R_SPK);
@@ -1470,6 +1519,11 @@ ranc_status ranc_load_network(const ranc_net_desc *desc, int32_t num_samples, in
         }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(net->ws, host.data(), p.params_bytes, hipMemcpyHostToDevice, s);
+    std::vector<uint8_t> bsrc;
+    if (e == hipSuccess && p.size[R_BSRC]) {
+        pack_bsrc(desc, p, bsrc);
+        e = hipMemcpyAsync(reg(R_BSRC), bsrc.data(), bsrc.size(), hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess)
         e = launch_reset_state(n, net->lk, s);
     if (e == hipSuccess)

@@ -73,6 +73,27 @@ def test_random_shapes(shape, path):
     assert_parity(net, x, T, path, what=f"rand{shape[:7]}")
 
 
+@pytest.mark.parametrize("shape", [s for s in SHAPES if s[8] > 64],
+                         ids=lambda s: "C{}A{}N{}G{}b{}P{}D{}".format(*s[:7]))
+def test_random_shapes_weight_planes(shape, monkeypatch):
+    """The MFMA kernel with more than one 64-sample chunk per core reads its
+    B tiles from the int8 weight planes (with one chunk it builds them from
+    the compact crossbar, as in test_random_shapes): the same networks with
+    64 samples per workgroup."""
+    monkeypatch.setenv("RANC_MFMA_SPW", "64")
+    C, A, N, G, b, P, D, gw, S, T = shape
+    wmax = (1 << (b - 1)) - 1
+    lim = (1 << (P - 1)) - 1
+    net = W.random_net(1000 + C * A + N + G + b + P + D, C, A, N, G, weight_bits=b, potential_bits=P,
+                       max_delay=D, grid_w=gw, density=0.25, p_core=0.7, p_out=0.25,
+                       leak_range=(-4, 4), thr_range=(max(1, wmax // 2), min(lim, 4 * wmax)),
+                       reset_range=(-3, 2), vinit_range=(-5, 5),
+                       input_cores=list(range(0, C, 2)), config_id=700,
+                       weight_range=(-wmax - 1, wmax))
+    x = W.bernoulli_inputs(11, net, S, T, 0.3, config_id=700)
+    assert_parity(net, x, T, "mfma", what=f"planes{shape[:7]}")
+
+
 @pytest.mark.parametrize("lanes", [1, 8], ids=["one_lane", "lane_split"])
 def test_large_core_count_unstaged_route(lanes):
     # 1280 cores x 512 neurons: the per-sample spike bitmap (80 KiB) exceeds the
