@@ -168,6 +168,20 @@ hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k,
                    : launch_group_code<false>(g, total, k, code, ext, st);
 }
 
+// B source of a launch by default. The compact crossbar when one workgroup covers all
+// samples of a core (it alone reads the core's B tiles in the tick) and the
+// planes it replaces are large (A x planes >= 256 bytes per neuron, cores of
+// >= 256 neurons) and the launch has a workgroup per CU or more; otherwise
+// the int8 planes. With one 64-sample tile per workgroup the expansion's
+// VALU work is latency nothing hides: measured per network of the 64-variant
+// sweep, 512-neuron cores with 512 axons run 8-24% faster, while 64- and
+// 128-neuron cores and networks of fewer workgroups than CUs run 2-20%
+// slower with the compact source.
+bool mfma_compact_b(const DevNet &n, int two_planes, int samples_per_wg)
+{
+    return n.S <= samples_per_wg && n.N >= 256 && n.A * (two_planes ? 2 : 1) >= 256 && n.C * n.slices >= 256;
+}
+
 bool mfma_shape_supported(int A, int N, int two_planes)
 {
     const bool ok_a = A == 64 || A == 128 || A == 256 || A == 512;
@@ -189,19 +203,16 @@ int mfma_slices(int A, int N, int two_planes)
     return N > w ? N / w : 1;
 }
 
-hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes, int samples_per_wg,
+hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes, int samples_per_wg, int compact,
                                  hipStream_t st)
 {
     if (!mfma_shape_supported(n.A, n.N, two_planes) || n.slices != mfma_slices(n.A, n.N, two_planes) ||
         n.cnt_rows != n.slices ||
         samples_per_wg <= 0 || samples_per_wg % MFMA_TS ||
         samples_per_wg > MFMA_SPW_MAX || n.vlayout != VLAYOUT_BRICK || n.S64 % MFMA_TS || n.S > n.S64 ||
-        !n.colbits || !n.planes)
+        (compact ? !n.colbits : !n.planes))
         return hipErrorInvalidValue;
-    // B source: built from the compact crossbar when one workgroup covers all
-    // samples of a core (it alone reads the core's B tiles in the tick), else
-    // the int8 planes, which the core's other workgroups then read from L2
-    if (n.S <= samples_per_wg)
+    if (compact)
         return launch_integrate_mfma_cb(n, a, two_planes, samples_per_wg, st);
     return launch_mfma_shape<false>(n, a, two_planes, samples_per_wg, st);
 }

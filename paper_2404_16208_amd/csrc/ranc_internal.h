@@ -198,6 +198,7 @@ struct BatchEntry {
     int unit_begin, units;      // integration units
     int route_begin, route_units, route_code, route_split;   // plain path: router units and shape
     int phase;                  // cache-sized phase of the batch (host bookkeeping)
+    int compact;                // MFMA path: B tiles built from the compact crossbar (host bookkeeping)
 };
 
 // Networks of one MFMA shape class in one launch, passed by value as kernel
@@ -251,8 +252,9 @@ bool sparse_shape_supported(int A, int N, int G);
 int sparse_max_samples_per_wg();
 int sparse_slice_width(int N);   // neurons per sparse-path workgroup
 int sparse_row_align();          // entries each slice's rows are aligned to
-hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes,
-                                 int samples_per_wg, hipStream_t st);
+// compact: B tiles built from the compact crossbar (R_BSRC), else read from the planes
+hipError_t launch_integrate_mfma(const DevNet &n, const TickArgs &a, int two_planes, int samples_per_wg, int compact,
+                                 hipStream_t st);
 // State-resident MFMA tick loop (N = 256 in one slice, A <= 256, at most
 // resident_max_cores_per_wg() cores per workgroup): zeroes the sync words,
 // then launches `grid` workgroups cooperatively.
@@ -283,8 +285,11 @@ hipError_t launch_route_batch(const BatchEntry *tab, int num, int total, int k, 
 hipError_t launch_advance_batch(const BatchEntry *tab, int num, int num_ticks, unsigned *queue, hipStream_t st);
 hipError_t launch_integrate_mfma_batch(const BatchEntry *tab, int num, int total, int k, unsigned *queue,
                                        int workgroups, hipStream_t st);
-// compact: B tiles built from the compact crossbar (every network of the
-// group has one sample chunk per core), else read from the weight planes
+// Whether a launch of this network should build its B tiles from the compact
+// crossbar (R_BSRC) rather than read the int8 weight planes (kern_mfma.hip)
+bool mfma_compact_b(const DevNet &n, int two_planes, int samples_per_wg);
+// compact: B tiles built from the compact crossbar (chosen for every network
+// of the group), else read from the weight planes
 hipError_t launch_integrate_mfma_group(const MfmaGroupArgs &g, int total, int k, int code, int ext, int compact,
                                        hipStream_t st);
 // the compact-B forms (kern_mfma_cb.hip); arguments validated by the callers above

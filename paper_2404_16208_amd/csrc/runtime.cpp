@@ -57,6 +57,7 @@ enum Region {
 
 struct Plan {
     int C, A, N, G, W, NW, D, Q, S, S64, RT, Wout, Nout, Cin, path, two, spw;
+    int bsrc;            // MFMA path B source: -1 by mfma_compact_b, 0 the planes, 1 the compact crossbar
     int grid_w, grid_h;  // mesh size
     int slices;          // MFMA and sparse: neuron slices per core (one workgroup each)
     int cnt_rows;        // counter rows per core
@@ -239,6 +240,9 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
                 p.spw = v;
         }
     }
+    p.bsrc = -1;
+    if (const char *e = getenv("RANC_MFMA_BSRC"))
+        p.bsrc = strcmp(e, "planes") == 0 ? 0 : strcmp(e, "compact") == 0 ? 1 : -1;
     long long E = 0, wout = 0, nout = 0;
     for (size_t i = 0; i < (size_t)p.C * p.N; ++i) {
         E += d->dest_kind[i] == RANC_DEST_CORE;
@@ -729,6 +733,15 @@ struct ranc_net {
     bool state_lost = false;           // a state-resident launch gave up: state undefined until reset
 };
 
+// MFMA path: whether this network's launches build their B tiles from the
+// compact crossbar (RANC_MFMA_BSRC=planes|compact at load overrides the
+// default choice, mfma_compact_b)
+static int mfma_compact(const ranc_net *net)
+{
+    const Plan &p = net->p;
+    return p.bsrc >= 0 ? p.bsrc : mfma_compact_b(net->dn, p.two, p.spw) ? 1 : 0;
+}
+
 static hipError_t prof_begin(ranc_net *net, int kind, hipStream_t s, int *slot)
 {
     *slot = -1;
@@ -797,7 +810,7 @@ static ranc_status queue_ticks(ranc_net *net, const uint32_t *base, int num_tick
         int slot = -1;
         hipError_t e = timed ? prof_begin(net, 0, s, &slot) : hipSuccess;
         if (e == hipSuccess)
-            e = p.path == RANC_PATH_MFMA     ? launch_integrate_mfma(net->dn, ta, p.two, p.spw, s)
+            e = p.path == RANC_PATH_MFMA     ? launch_integrate_mfma(net->dn, ta, p.two, p.spw, mfma_compact(net), s)
                 : p.path == RANC_PATH_SPARSE ? launch_integrate_sparse(net->dn, ta, p.spw, s)
                                              : launch_integrate_plain(net->dn, ta, s);
         if (e == hipSuccess && timed)
@@ -1074,6 +1087,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         e.tick_words = (long long)p.Cin * p.W;
         e.ext_sstride = (long long)num_ticks * e.tick_words;
         e.spw = p.spw;
+        e.compact = p.path == RANC_PATH_MFMA ? mfma_compact(net) : 0;
         e.phase = phase_of[i];
         if (p.path == RANC_PATH_SPARSE)
             return fail(RANC_EUNSUPPORTED, "nets[%d]: the sparse path runs one network per call", i);
@@ -1103,8 +1117,7 @@ static ranc_status build_batch(ranc_net *const *nets, int num, const uint32_t *c
         return (double)e.spw * (e.n.N / e.n.slices) * (e.n.A + 64) * ((e.code & 1) ? 2 : 1);
     };
     auto ext = [](const BatchEntry &e) { return e.n.model_ext; };
-    // one sample chunk per core: the group builds its B tiles from R_BSRC
-    auto compact = [](const BatchEntry &e) { return e.n.S <= e.spw ? 1 : 0; };
+    auto compact = [](const BatchEntry &e) { return e.compact; };
     long long mu = 0, pu = 0, ru = 0;
     if (persistent) {
         // one unit numbering, largest units first

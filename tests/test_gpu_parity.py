@@ -73,25 +73,44 @@ def test_random_shapes(shape, path):
     assert_parity(net, x, T, path, what=f"rand{shape[:7]}")
 
 
-@pytest.mark.parametrize("shape", [s for s in SHAPES if s[8] > 64],
-                         ids=lambda s: "C{}A{}N{}G{}b{}P{}D{}".format(*s[:7]))
-def test_random_shapes_weight_planes(shape, monkeypatch):
-    """The MFMA kernel with more than one 64-sample chunk per core reads its
-    B tiles from the int8 weight planes (with one chunk it builds them from
-    the compact crossbar, as in test_random_shapes): the same networks with
-    64 samples per workgroup."""
-    monkeypatch.setenv("RANC_MFMA_SPW", "64")
+def _random_shape_net(shape):
     C, A, N, G, b, P, D, gw, S, T = shape
     wmax = (1 << (b - 1)) - 1
     lim = (1 << (P - 1)) - 1
-    net = W.random_net(1000 + C * A + N + G + b + P + D, C, A, N, G, weight_bits=b, potential_bits=P,
-                       max_delay=D, grid_w=gw, density=0.25, p_core=0.7, p_out=0.25,
-                       leak_range=(-4, 4), thr_range=(max(1, wmax // 2), min(lim, 4 * wmax)),
-                       reset_range=(-3, 2), vinit_range=(-5, 5),
-                       input_cores=list(range(0, C, 2)), config_id=700,
-                       weight_range=(-wmax - 1, wmax))
+    return W.random_net(1000 + C * A + N + G + b + P + D, C, A, N, G, weight_bits=b, potential_bits=P,
+                        max_delay=D, grid_w=gw, density=0.25, p_core=0.7, p_out=0.25,
+                        leak_range=(-4, 4), thr_range=(max(1, wmax // 2), min(lim, 4 * wmax)),
+                        reset_range=(-3, 2), vinit_range=(-5, 5),
+                        input_cores=list(range(0, C, 2)), config_id=700,
+                        weight_range=(-wmax - 1, wmax))
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "C{}A{}N{}G{}b{}P{}D{}".format(*s[:7]))
+def test_random_shapes_compact_b(shape, monkeypatch):
+    """The MFMA kernel with its B tiles built from the compact crossbar
+    (column words, per-type plane bytes, axon types) instead of read from the
+    int8 weight planes, forced for networks this small (by default it is
+    chosen for large networks of wide cores only)."""
+    monkeypatch.setenv("RANC_MFMA_BSRC", "compact")
+    net = _random_shape_net(shape)
+    S, T = shape[8], shape[9]
     x = W.bernoulli_inputs(11, net, S, T, 0.3, config_id=700)
-    assert_parity(net, x, T, "mfma", what=f"planes{shape[:7]}")
+    assert_parity(net, x, T, "mfma", what=f"compact{shape[:7]}")
+
+
+@pytest.mark.parametrize("bsrc", ["planes", "compact"])
+@pytest.mark.parametrize("shape", [s for s in SHAPES if s[8] > 64],
+                         ids=lambda s: "C{}A{}N{}G{}b{}P{}D{}".format(*s[:7]))
+def test_random_shapes_weight_planes(shape, bsrc, monkeypatch):
+    """Both B sources with more than one 64-sample chunk per core (64 samples
+    per workgroup): several workgroups of a core read (or build) the same B
+    tiles."""
+    monkeypatch.setenv("RANC_MFMA_SPW", "64")
+    monkeypatch.setenv("RANC_MFMA_BSRC", bsrc)
+    net = _random_shape_net(shape)
+    S, T = shape[8], shape[9]
+    x = W.bernoulli_inputs(11, net, S, T, 0.3, config_id=700)
+    assert_parity(net, x, T, "mfma", what=f"{bsrc}{shape[:7]}")
 
 
 @pytest.mark.parametrize("lanes", [1, 8], ids=["one_lane", "lane_split"])
@@ -340,17 +359,20 @@ def _small_sweep_variants(limit_neuron_axons=1 << 22):
     return out
 
 
-@pytest.mark.parametrize("graph,persistent,phase_mb", [(False, False, None), (True, False, None),
-                                                      (False, True, None), (True, True, None),
-                                                      (False, False, "1"), (True, False, "1")])
-def test_batch_of_uneven_variants(graph, persistent, phase_mb, monkeypatch):
+@pytest.mark.parametrize("graph,persistent,phase_mb,bsrc", [(False, False, None, None), (True, False, None, None),
+                                                           (False, True, None, None), (True, True, None, None),
+                                                           (False, False, "1", None), (True, False, "1", None),
+                                                           (False, False, None, "compact"),
+                                                           (True, False, None, "compact")])
+def test_batch_of_uneven_variants(graph, persistent, phase_mb, bsrc, monkeypatch):
     """Design-space sweep variants of different core counts, core sizes, axon
     types and weight precisions (both paths) advanced together (per tick one
     launch per MFMA shape class, or one persistent launch, and one per plain
     step; with a 1 MB phase budget every network runs all its ticks in a phase
     of its own), in two calls; plus a 6-core net on each path with its own
     sample count. Every network equals the oracle on sampled instances and
-    equals the same network run alone on every instance."""
+    equals the same network run alone on every instance. bsrc "compact": the
+    MFMA-path launches build their B tiles from the compact crossbar."""
     import torch
     from paper_2404_16208_amd.ranc import RancNet, run_batch
     vs = _small_sweep_variants()
@@ -365,7 +387,9 @@ def test_batch_of_uneven_variants(graph, persistent, phase_mb, monkeypatch):
     xs = [W.bernoulli_inputs(17, n, s, T, 0.1, config_id=709) for n, s in zip(nets, S)]
     if phase_mb is not None:
         monkeypatch.setenv("RANC_BATCH_PHASE_MB", phase_mb)
-    log(f"[batch] {len(nets)} networks, graph={graph}, persistent={persistent}, phase_mb={phase_mb}")
+    if bsrc is not None:
+        monkeypatch.setenv("RANC_MFMA_BSRC", bsrc)
+    log(f"[batch] {len(nets)} networks, graph={graph}, persistent={persistent}, phase_mb={phase_mb}, bsrc={bsrc}")
     gs = [RancNet(n, s, TC) for n, s in zip(nets, S)]
     paths = [g.path for g in gs]
     assert "mfma" in paths and "plain" in paths
