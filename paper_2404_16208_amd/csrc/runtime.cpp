@@ -50,8 +50,7 @@ enum Region {
     R_V = R_PARAMS_END, R_RING, R_SPK, R_HIST, R_RASTER, R_CNT, R_CRING, R_TICK, R_BATCH, R_EXT, R_LINKD,
     R_RSYNC,
     // MFMA path: the compact B source, uploaded at load as well; kept past
-    // the state regions so that their placement does not depend on it (the
-    // 512-core net's tick is 0.9% slower with these 6 MB in front of them)
+    // the state regions so that their placement does not depend on it
     R_BSRC, R_NREG
 };
 
@@ -353,6 +352,22 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
     return RANC_OK;
 }
 
+// Crossbar columns [C][A/32][N] (bit a % 32 of word a / 32 of neuron j: axon
+// a connects to j), into zeroed words, visiting the set crossbar bits only.
+static void pack_columns(const ranc_net_desc *d, const Plan &p, uint32_t *col)
+{
+    const int C = p.C, A = p.A, N = p.N, W = p.W, NW = p.NW;
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < A; ++a) {
+            const uint32_t *row = d->crossbar + ((size_t)c * A + a) * NW;
+            uint32_t *cw = col + ((size_t)c * W + a / 32) * N;
+            const uint32_t bit = 1u << (a % 32);
+            for (int w = 0; w < NW; ++w)
+                for (uint32_t b = row[w]; b; b &= b - 1u)
+                    cw[32 * w + __builtin_ctz(b)] |= bit;
+        }
+}
+
 // Host-side packing of the MFMA path's compact B source (R_BSRC): column
 // words [C][W][N] (bit a % 32 of word a / 32 of neuron j: axon a connects to
 // j); then [C][planes][2][N] words, byte g % 4 of word g / 4 = the plane
@@ -361,13 +376,9 @@ ranc_status make_plan(const ranc_net_desc *d, int32_t S, int32_t RT, int32_t pat
 void pack_bsrc(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &buf)
 {
     buf.assign(p.size[R_BSRC], 0);
-    const int C = p.C, A = p.A, N = p.N, G = p.G, W = p.W, NW = p.NW, PL = p.two ? 2 : 1;
+    const int C = p.C, A = p.A, N = p.N, G = p.G, W = p.W, PL = p.two ? 2 : 1;
     uint32_t *col = reinterpret_cast<uint32_t *>(buf.data());
-    for (int c = 0; c < C; ++c)
-        for (int a = 0; a < A; ++a)
-            for (int j = 0; j < N; ++j)
-                if ((d->crossbar[((size_t)c * A + a) * NW + j / 32] >> (j % 32)) & 1u)
-                    col[((size_t)c * W + a / 32) * N + j] |= 1u << (a % 32);
+    pack_columns(d, p, col);
     uint32_t *ws = col + (size_t)C * W * N;
     for (int c = 0; c < C; ++c)
         for (int j = 0; j < N; ++j)
@@ -390,14 +401,8 @@ void pack_params(const ranc_net_desc *d, const Plan &p, std::vector<uint8_t> &bu
     auto conn = [&](int c, int a, int j) -> int {
         return (d->crossbar[((size_t)c * A + a) * NW + j / 32] >> (j % 32)) & 1u;
     };
-    if (p.size[R_COLBITS]) {
-        uint32_t *col = (uint32_t *)at(R_COLBITS);
-        for (int c = 0; c < C; ++c)
-            for (int a = 0; a < A; ++a)
-                for (int j = 0; j < N; ++j)
-                    if (conn(c, a, j))
-                        col[((size_t)c * W + a / 32) * N + j] |= 1u << (a % 32);
-    }
+    if (p.size[R_COLBITS])
+        pack_columns(d, p, (uint32_t *)at(R_COLBITS));
     uint32_t *tm = (uint32_t *)at(R_TYPEMASK);
     for (int c = 0; c < C; ++c)
         for (int a = 0; a < A; ++a)
