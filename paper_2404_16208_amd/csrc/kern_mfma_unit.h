@@ -172,9 +172,14 @@ __device__ __forceinline__ void integrate_mfma_unit(const DevNet &n, const TickA
             const uint32_t tq[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                // 0xFF in byte i where axon 32k + 16h + 4q + i connects
-                const uint32_t m = ((((bits >> (4 * q)) & 15u) * 0x00204081u) & 0x01010101u) * 255u;
-                const uint32_t sel = (tq[q] & m) | (0x0C0C0C0Cu & ~m);
+                // bit i of the nibble (axon 32k + 16h + 4q + i connects) to
+                // bit 2 of byte i (one 24-bit multiply: the four shifted
+                // copies do not overlap), then byte i of the index = i, or
+                // 4 + i where the axon connects
+                const uint32_t spread = ((bits >> (4 * q)) & 15u) * 0x00810204u;
+                const uint32_t idx = (spread & 0x04040404u) | 0x03020100u;
+                // byte i: the axon's type (byte i of tq), or 0x0C where it does not connect
+                const uint32_t sel = __builtin_amdgcn_perm(tq[q], 0x0C0C0C0Cu, idx);
 #pragma unroll
                 for (int p = 0; p < PL; ++p)
                     breg[k][p][q] = (int)__builtin_amdgcn_perm(wh[p], wl[p], sel);
