@@ -98,6 +98,21 @@ def test_random_shapes_compact_b(shape, monkeypatch):
     assert_parity(net, x, T, "mfma", what=f"compact{shape[:7]}")
 
 
+@pytest.mark.parametrize("shape,S", [(s, 3) for s in SHAPES] + [(SHAPES[i], S) for i in (0, 5, 12, 15)
+                                                                  for S in (1, 8)],
+                         ids=lambda v: "S{}".format(v) if isinstance(v, int) else
+                         "C{}A{}N{}G{}b{}P{}D{}".format(*v[:7]))
+def test_sparse_small_batch(shape, S):
+    """The event-driven path with at most 8 samples, whose integration takes
+    the samples in turn with the wavefront's lanes over a row's entries
+    (rows staged in LDS or read from memory, every neuron-model option):
+    every sample against the oracle."""
+    net = _random_shape_net(shape)
+    T = shape[9]
+    x = W.bernoulli_inputs(11, net, S, T, 0.3, config_id=700)
+    assert_parity(net, x, T, "sparse", what=f"sparse S{S}{shape[:7]}")
+
+
 @pytest.mark.parametrize("bsrc", ["planes", "compact"])
 @pytest.mark.parametrize("shape", [s for s in SHAPES if s[8] > 64],
                          ids=lambda s: "C{}A{}N{}G{}b{}P{}D{}".format(*s[:7]))
