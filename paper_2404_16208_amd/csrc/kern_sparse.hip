@@ -36,7 +36,7 @@
 //      its sample's current of that neuron in LDS (LDS atomic add: waves
 //      share neurons); with at most EV_SMALL_S samples the wavefront instead
 //      takes the samples in turn and its lanes take a row's entries, 64 at a
-//      time (one instance of MNIST-12c: 11.3 instead of 47.0 us per tick);
+//      time (one instance of MNIST-12c: 11.8 instead of 47.0 us per tick);
 //   2. update: the potentials of the wave's neurons are loaded (V is
 //      neuron-major, [C][N][S64], so a wave's load of one neuron is 256
 //      contiguous bytes), then per neuron leak, threshold and reset for all
@@ -310,9 +310,11 @@ void k_integrate_event(DevNet n, TickArgs ta)
     // ---- 2. update, one neuron of the wave at a time for all 64 samples
     int32_t vreg[NPW];
     const int32_t *vin = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
+    // (small batches: only the valid samples' potentials move; the padding
+    // lanes of the tile are never read)
 #pragma unroll
     for (int k = 0; k < NPW; ++k)
-        vreg[k] = __builtin_nontemporal_load(vin + (size_t)k * n.S64);
+        vreg[k] = (!SMALL || svalid) ? __builtin_nontemporal_load(vin + (size_t)k * n.S64) : 0;
     uint32_t fm = 0;       // bit k: this lane's sample fired on neuron j0 + k
     uint64_t myword = 0;   // lane k < NPW: the history word of neuron j0 + k
     int32_t *vout = n.V + ((size_t)c * n.N + j0) * n.S64 + s;
@@ -335,7 +337,8 @@ void k_integrate_event(DevNet n, TickArgs ta)
             vn = fire ? rs : u;
         }
         fire = fire && svalid;
-        __builtin_nontemporal_store(vn, vout + (size_t)k * n.S64);
+        if (!SMALL || svalid)
+            __builtin_nontemporal_store(vn, vout + (size_t)k * n.S64);
         const uint64_t word = __ballot(fire);
         myword = lane == k ? word : myword;
         fm |= (uint32_t)fire << k;
